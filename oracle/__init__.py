@@ -1,0 +1,182 @@
+"""ctypes front end of the plain FP64 CPU oracle (tdse_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may use this package; the product library never does.
+Each function propagates pulses one at a time, single-threaded, in the loop
+order of the C source. Arrays follow the library's layout: complex vectors
+interleaved (re, im), field samples [B, nsteps, S].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tdse_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+
+
+def build(force: bool = True) -> str:
+    """Compile tdse_oracle.c with gcc into liboracle.so (no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER(ctypes.c_double)
+        i32, i64, d = ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        lib.oracle_dmul.argtypes = [i32, i32, P, P, P]
+        lib.oracle_dmul.restype = None
+        lib.oracle_hmul.argtypes = [i32, i32, P, P, d, P, P]
+        lib.oracle_hmul.restype = None
+        lib.oracle_rk4.argtypes = [i32, i32, P, P, d, i64, P, P]
+        lib.oracle_rk4.restype = i32
+        lib.oracle_taylor.argtypes = [i32, i32, P, P, i32, d, i64, P, P]
+        lib.oracle_taylor.restype = i32
+        lib.oracle_rk4_tangent.argtypes = [i32, i32, P, P, d, i64, P, P, P, P]
+        lib.oracle_rk4_tangent.restype = i32
+        lib.oracle_rk4_adjoint.argtypes = [i32, i32, P, P, d, i64, P, P, P, P]
+        lib.oracle_rk4_adjoint.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dims_n(energies, dipole, n=None):
+    en = _f64(energies)
+    dip = _f64(dipole)
+    lmax = dip.shape[0]
+    n = dip.shape[1] if n is None else n
+    if en.size != (lmax + 1) * n:
+        raise ValueError("energies size does not match (lmax+1)*n")
+    return en, dip, lmax, n
+
+
+def dmul(energies, dipole, u, n=None):
+    """z = D u for one interleaved complex vector u."""
+    en, dip, lmax, n = _dims_n(energies, dipole, n)
+    u = _f64(u)
+    z = np.empty_like(u)
+    _load().oracle_dmul(lmax, n, _p(dip), _p(u), _p(z))
+    return z
+
+
+def hmul(energies, dipole, field, u, n=None):
+    """y = H(field) u = E o u + field * D u."""
+    en, dip, lmax, n = _dims_n(energies, dipole, n)
+    u = _f64(u)
+    y = np.empty_like(u)
+    _load().oracle_hmul(lmax, n, _p(en), _p(dip), float(field), _p(u), _p(y))
+    return y
+
+
+def rk4(energies, dipole, dt, field, c0, n=None):
+    """RK4 over field[B, nsteps, 3] from c0[B, 2n]; returns c(T) [B, 2n]."""
+    en, dip, lmax, n = _dims_n(energies, dipole, n)
+    field = _f64(field)
+    c = np.array(c0, dtype=np.float64, copy=True, order="C")
+    if field.ndim == 2:
+        field = field[None]
+    if c.ndim == 1:
+        c = c[None]
+    assert field.shape[-1] == 3 and field.shape[0] == c.shape[0]
+    lib = _load()
+    for b in range(c.shape[0]):
+        fb = _f64(field[b])
+        cb = np.ascontiguousarray(c[b])
+        rc = lib.oracle_rk4(lmax, n, _p(en), _p(dip), float(dt), fb.shape[0], _p(fb), _p(cb))
+        if rc != 0:
+            raise MemoryError("oracle_rk4 allocation failed")
+        c[b] = cb
+    return c
+
+
+def taylor(energies, dipole, order, dt, field, c0, n=None):
+    """Taylor-order propagation over field[B, nsteps, 1] (or [B, nsteps])."""
+    en, dip, lmax, n = _dims_n(energies, dipole, n)
+    field = _f64(field)
+    c = np.array(c0, dtype=np.float64, copy=True, order="C")
+    if c.ndim == 1:
+        c = c[None]
+    if field.ndim == 1:
+        field = field[None]
+    if field.ndim == 3:
+        field = field[..., 0]
+    lib = _load()
+    for b in range(c.shape[0]):
+        fb = _f64(field[b])
+        cb = np.ascontiguousarray(c[b])
+        rc = lib.oracle_taylor(lmax, n, _p(en), _p(dip), int(order), float(dt), fb.shape[0],
+                               _p(fb), _p(cb))
+        if rc != 0:
+            raise MemoryError("oracle_taylor allocation failed")
+        c[b] = cb
+    return c
+
+
+def rk4_tangent(energies, dipole, dt, field, dfield, c0, dc0=None, n=None):
+    """Returns (c(T), dc(T)) for one pulse: field, dfield [nsteps, 3]."""
+    en, dip, lmax, n = _dims_n(energies, dipole, n)
+    field, dfield = _f64(field), _f64(dfield)
+    c = np.array(c0, dtype=np.float64, copy=True).reshape(-1)
+    dc = np.zeros_like(c) if dc0 is None else np.array(dc0, dtype=np.float64, copy=True).reshape(-1)
+    rc = _load().oracle_rk4_tangent(lmax, n, _p(en), _p(dip), float(dt), field.shape[0],
+                                    _p(field), _p(dfield), _p(c), _p(dc))
+    if rc != 0:
+        raise MemoryError("oracle_rk4_tangent allocation failed")
+    return c, dc
+
+
+def rk4_adjoint(energies, dipole, dt, field, c0, lam_t, n=None):
+    """Discrete RK4 adjoint for one pulse. Returns (lambda_0, grad[nsteps, 3])."""
+    en, dip, lmax, n = _dims_n(energies, dipole, n)
+    field = _f64(field)
+    c0 = _f64(np.asarray(c0).reshape(-1))
+    lam = np.array(lam_t, dtype=np.float64, copy=True).reshape(-1)
+    grad = np.zeros_like(field)
+    rc = _load().oracle_rk4_adjoint(lmax, n, _p(en), _p(dip), float(dt), field.shape[0],
+                                    _p(field), _p(c0), _p(lam), _p(grad))
+    if rc != 0:
+        raise MemoryError("oracle_rk4_adjoint allocation failed")
+    return lam, grad
+
+
+def positive_mask(energies):
+    """Indicator of continuum (E > 0) states, the ionization-yield support."""
+    return np.asarray(energies) > 0.0
+
+
+def ionization_yield(energies, c):
+    """Y = sum over E_j > 0 of |c_j|^2, per pulse."""
+    c = np.atleast_2d(c)
+    m = positive_mask(energies)
+    re, im = c[:, 0::2], c[:, 1::2]
+    return ((re * re + im * im) * m[None, :]).sum(axis=1)
+
+
+def yield_seed(energies, c):
+    """lambda_T = dY/dRe c + i dY/dIm c = 2 [E > 0] c."""
+    m = np.repeat(positive_mask(energies), 2).astype(np.float64)
+    return 2.0 * np.atleast_2d(c) * m[None, :]
