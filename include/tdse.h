@@ -1,0 +1,173 @@
+/*
+ * tdse.h -- C ABI of the MI355X (gfx950) TDSE propagation library.
+ *
+ * The library time-propagates dc/dt = -i [diag(E) + F(t) D] c over the
+ * field-free |n,l> basis of O Broin & Nikolopoulos, "An OpenCL implementation
+ * for the solution of TDSE on GPU and CPU architectures" (arXiv:1201.6062):
+ *   - Sec. 3, Eqs. tdse_ode / tdse_ode_c: the projected TDSE i dC/dt = H(t) C;
+ *   - Sec. 3, dipole selection rules and Fig. Matrix: H is block tridiagonal
+ *     in l, diagonal blocks are the energies E_l, off-diagonal blocks are
+ *     dense n x n dipole blocks coupling l and l+1;
+ *   - Sec. 4, Eq. ode and the block product that follows it: the derivative
+ *     is -i (E_l C_l + F (D_l C_{l+1} + D_{l-1}^T C_{l-1})) per block l;
+ *   - Sec. 5: only the superdiagonal blocks D_l = D_{l,l+1} are stored, the
+ *     subdiagonal block is its transpose (H is real symmetric);
+ *   - Appendix B: truncated Taylor series (Eq. taylor) and explicit
+ *     Runge-Kutta (Eqs. RKFinal, RKDeriv; classic RK4 tableau).
+ *
+ * Layout conventions (all arguments):
+ *   lmax        highest partial wave; blocks l = 0..lmax, lmax >= 0.
+ *   n           states per partial wave, n >= 1. nstates = (lmax+1)*n.
+ *   energies    [(lmax+1)*n] doubles, block l at [l*n, (l+1)*n).
+ *   dipole      [lmax][n][n] doubles, row-major; D_l[a][b] couples state a
+ *               of block l (row) to state b of block l+1 (column).
+ *   state c     [batch][2*nstates] doubles: complex coefficients interleaved
+ *               (re, im), state j = l*n + a.
+ *   field       [batch][nsteps][S] doubles, S = 3 for RK4 (the field at
+ *               t_k, t_k + dt/2, t_k + dt; stages 2 and 3 share the midpoint
+ *               sample), S = 1 for Taylor (H frozen over the step at the
+ *               given sample, appendix B).
+ *   stream      a hipStream_t passed as void*; NULL means the null stream.
+ *
+ * Memory: arguments named "device" must point to device memory (hipMalloc,
+ * torch CUDA/HIP tensors); arguments named "host or device" may be either.
+ * All device arguments must be 8-byte aligned.
+ *
+ * Errors: every argument is checked on the host before anything is
+ * enqueued. On error nothing is enqueued, outputs are untouched, the status
+ * is returned and tdse_last_error() describes the problem. HIP failures map
+ * to TDSE_E_HIP.
+ *
+ * Asynchrony and ownership: tdse_propagate, tdse_adjoint, tdse_hmul and
+ * tdse_group_propagate only enqueue work on the given stream and return;
+ * caller buffers must stay valid until the stream reaches that point. The
+ * library never frees caller memory. A plan or group owns its device copies
+ * of the Hamiltonian, its scratch and its captured graphs. One plan may be
+ * used by one stream at a time; distinct plans are independent.
+ */
+#ifndef TDSE_H
+#define TDSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TDSE_ABI_VERSION 1
+
+typedef struct tdse_plan_s *tdse_plan;
+typedef struct tdse_group_s *tdse_group;
+
+typedef enum {
+    TDSE_OK = 0,
+    TDSE_E_INVAL = 1,        /* invalid argument; nothing enqueued */
+    TDSE_E_NOMEM = 2,        /* device allocation failed */
+    TDSE_E_HIP = 3,          /* a HIP runtime call failed */
+    TDSE_E_UNSUPPORTED = 4,  /* valid request this build does not support */
+    TDSE_E_UNSTABLE = 5      /* step size outside the method's stability bound */
+} tdse_status;
+
+typedef enum {
+    TDSE_RK4 = 0,            /* classic 4th-order Runge-Kutta, 4 products per step */
+    TDSE_TAYLOR = 1          /* truncated Taylor series of order p, p products per step */
+} tdse_method;
+
+/* Version of this ABI (TDSE_ABI_VERSION of the built library). */
+int tdse_abi_version(void);
+
+/* Text of the last error on the calling thread; valid until the next call on
+ * this thread. Never NULL (empty string when the last call succeeded). */
+const char *tdse_last_error(void);
+
+/*
+ * Create a plan for one Hamiltonian (Sec. 5: energies and superdiagonal
+ * dipole blocks), and for propagating `batch` independent states (pulses)
+ * at once. energies and dipole: host or device memory, copied into plan-owned,
+ * re-laid-out device buffers; the call synchronises `stream`, so the caller
+ * may free its inputs on return. batch >= 1; batch == 1 selects the
+ * single-vector streaming kernels, batch > 1 the FP64 matrix-core kernels.
+ * Errors: TDSE_E_INVAL (null out/energies, dipole null with lmax > 0,
+ * lmax < 0, n < 1, batch < 1, sizes overflowing 2^40 states), TDSE_E_NOMEM,
+ * TDSE_E_HIP.
+ */
+tdse_status tdse_create(tdse_plan *out, const double *energies, const double *dipole,
+                        int32_t lmax, int32_t n, int32_t batch, void *stream);
+
+/* Release a plan and everything it owns. Synchronises the device. NULL is a no-op. */
+tdse_status tdse_destroy(tdse_plan plan);
+
+/* Query the plan's shape. Any output pointer may be NULL. */
+tdse_status tdse_plan_shape(tdse_plan plan, int32_t *lmax, int32_t *n, int32_t *batch);
+
+/*
+ * y = H(F) u = E o u + F (D u) for every column b of the batch with its own
+ * field value F = fields[b] (Sec. 4, the block product after Eq. ode).
+ * fields [batch] (device), u and y [batch][2*nstates] (device, must not
+ * alias). One product per column; the building block of every step.
+ */
+tdse_status tdse_hmul(tdse_plan plan, const double *fields, const double *u, double *y,
+                      void *stream);
+
+/*
+ * Propagate c0 over nsteps steps of size dt with RK4 (taylor_order ignored)
+ * or the Taylor series of order taylor_order (1 <= order <= 32), writing c(T)
+ * to cT. field: [batch][nsteps][S] device; c0, cT: [batch][2*nstates]
+ * device; cT may alias c0. nsteps == 0 copies c0 to cT.
+ * ckpt: NULL, or device [batch][nsteps/ckpt_every + 1][2*nstates] receiving
+ * c(k*ckpt_every*dt) for k = 0..nsteps/ckpt_every (ckpt_every >= 1).
+ * The result is the discrete RK4 / Taylor map applied to the given samples.
+ * Errors: TDSE_E_INVAL (null/misaligned/host pointers, dt <= 0 or not finite,
+ * nsteps < 0, order out of range, ckpt_every < 1 with ckpt != NULL).
+ */
+tdse_status tdse_propagate(tdse_plan plan, tdse_method method, int32_t taylor_order, double dt,
+                           int64_t nsteps, const double *field, const double *c0, double *cT,
+                           double *ckpt, int32_t ckpt_every, void *stream);
+
+/*
+ * Discrete adjoint of tdse_propagate (RK4 only; TDSE_E_UNSUPPORTED for
+ * Taylor). For a real loss L(c(T)) with lambdaT = dL/dRe c(T) + i dL/dIm c(T)
+ * ([batch][2*nstates] device), writes grad_field[batch][nsteps][3] =
+ * dL/dfield (device, overwritten) and, if lambda0 != NULL, lambda0 =
+ * dL/dRe c0 + i dL/dIm c0 ([batch][2*nstates] device).
+ * ckpt: the checkpoints written by tdse_propagate with the same field, c0,
+ * dt and ckpt_every (device), or NULL: then the library recomputes them into
+ * plan-owned memory first. Forward states between checkpoints are recomputed
+ * segment by segment, so memory stays at one segment of stage inputs.
+ */
+tdse_status tdse_adjoint(tdse_plan plan, tdse_method method, int32_t taylor_order, double dt,
+                         int64_t nsteps, const double *field, const double *c0,
+                         const double *ckpt, int32_t ckpt_every, const double *lambdaT,
+                         double *grad_field, double *lambda0, void *stream);
+
+/*
+ * Uneven multi-instance propagation: `count` plans (each batch == 1, any
+ * lmax and n) advanced together in one persistent launch per chunk of steps.
+ * tdse_group_create: plans[count] (host array), the group keeps references
+ * (the plans must outlive the group).
+ * tdse_group_propagate: RK4 only; nsteps[count] (host), fields, c0, cT:
+ * host arrays of `count` device pointers laid out as in tdse_propagate.
+ * Instance i runs its own nsteps[i] steps; the launch ends when every
+ * instance is done.
+ */
+tdse_status tdse_group_create(tdse_group *out, int32_t count, const tdse_plan *plans,
+                              void *stream);
+tdse_status tdse_group_propagate(tdse_group group, tdse_method method, int32_t taylor_order,
+                                 double dt, const int64_t *nsteps, const double *const *fields,
+                                 const double *const *c0, double *const *cT, void *stream);
+tdse_status tdse_group_destroy(tdse_group group);
+
+/*
+ * Autotuner: time the candidate tile shapes for a (lmax, n, batch) problem on
+ * the current device with synthetic data and record the fastest in the JSON
+ * cache at cache_path (created or updated; NULL uses $TDSE_TUNE_CACHE, else
+ * no file is written). Later tdse_create calls read the cache named by
+ * $TDSE_TUNE_CACHE. Synchronous; allocates and frees its own buffers.
+ */
+tdse_status tdse_tune(int32_t lmax, int32_t n, int32_t batch, const char *cache_path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDSE_H */

@@ -1,0 +1,153 @@
+"""Python front end of the TDSE library: plans, propagation, adjoint, autograd.
+
+Thin marshalling over the C ABI (include/tdse.h): tensors are float64 torch
+tensors on the GPU, passed by data pointer with torch's current HIP stream.
+Every step of the computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _capi
+from ._capi import TDSE_RK4, TDSE_TAYLOR, TdseError, check
+
+METHODS = {"rk4": TDSE_RK4, "taylor": TDSE_TAYLOR}
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_f64(x, device):
+    if isinstance(x, torch.Tensor):
+        t = x.to(device=device, dtype=torch.float64)
+    else:
+        t = torch.as_tensor(np.asarray(x, dtype=np.float64), device=device)
+    return t.contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def slots_of(method: str) -> int:
+    return 3 if method == "rk4" else 1
+
+
+class Plan:
+    """One Hamiltonian (energies [(L+1)N], upper dipole blocks [L, N, N]) and a batch width."""
+
+    def __init__(self, energies, dipole, batch: int = 1, device="cuda"):
+        self._lib = _capi.load()
+        self.device = torch.device(device)
+        en = _dev_f64(energies, self.device).reshape(-1)
+        dip = _dev_f64(dipole, self.device)
+        if dip.dim() != 3 or dip.shape[1] != dip.shape[2]:
+            raise ValueError("dipole must have shape [lmax, n, n]")
+        self.lmax = int(dip.shape[0])
+        self.n = int(dip.shape[1]) if self.lmax > 0 else int(en.numel())
+        self.batch = int(batch)
+        self.energies = en
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(self._lib.tdse_create(ctypes.byref(h), _ptr(en), _ptr(dip) if self.lmax else None,
+                                        self.lmax, self.n, self.batch, _stream(self.device)))
+        self._h = h
+
+    @property
+    def nstates(self) -> int:
+        return (self.lmax + 1) * self.n
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.tdse_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _state(self, c):
+        t = _dev_f64(c, self.device)
+        return t.reshape(self.batch, 2 * self.nstates)
+
+    def hmul(self, fields, u):
+        """y = H(F_b) u_b for each batch column b."""
+        f = _dev_f64(fields, self.device).reshape(self.batch)
+        u = self._state(u)
+        y = torch.empty_like(u)
+        check(self._lib.tdse_hmul(self._h, _ptr(f), _ptr(u), _ptr(y), _stream(self.device)))
+        return y
+
+    def propagate(self, field, c0, dt: float, method: str = "rk4", order: int = 8,
+                  ckpt_every: int = 0, out=None):
+        """c(T) for field [B, nsteps, S]; returns cT (and checkpoints if ckpt_every > 0)."""
+        m = METHODS[method]
+        f = _dev_f64(field, self.device)
+        nsteps = f.numel() // (self.batch * slots_of(method))
+        f = f.reshape(self.batch, nsteps, slots_of(method)).contiguous()
+        c0 = self._state(c0)
+        cT = out if out is not None else torch.empty_like(c0)
+        ck = None
+        if ckpt_every > 0:
+            ck = torch.empty(self.batch, nsteps // ckpt_every + 1, 2 * self.nstates,
+                             dtype=torch.float64, device=self.device)
+        check(self._lib.tdse_propagate(self._h, m, int(order), float(dt), nsteps, _ptr(f), _ptr(c0),
+                                       _ptr(cT), _ptr(ck), int(max(ckpt_every, 1)) if ck is not None else 0,
+                                       _stream(self.device)))
+        return (cT, ck) if ckpt_every > 0 else cT
+
+    def adjoint(self, field, c0, dt: float, lambda_t, ckpt=None, ckpt_every: int = 64,
+                method: str = "rk4", order: int = 8, want_lambda0: bool = True):
+        """(grad_field [B, nsteps, 3], lambda0 [B, 2n]) for lambda_T = dL/dRe c + i dL/dIm c."""
+        m = METHODS[method]
+        f = _dev_f64(field, self.device)
+        nsteps = f.numel() // (self.batch * slots_of(method))
+        f = f.reshape(self.batch, nsteps, slots_of(method)).contiguous()
+        c0 = self._state(c0)
+        lam = self._state(lambda_t)
+        g = torch.empty_like(f)
+        l0 = torch.empty_like(c0) if want_lambda0 else None
+        check(self._lib.tdse_adjoint(self._h, m, int(order), float(dt), nsteps, _ptr(f), _ptr(c0),
+                                     _ptr(ckpt), int(ckpt_every), _ptr(lam), _ptr(g), _ptr(l0),
+                                     _stream(self.device)))
+        return g, l0
+
+
+def ionization_yield(cT: torch.Tensor, energies) -> torch.Tensor:
+    """Y_b = sum over states with E > 0 of |c_b,j|^2 (torch ops; autograd-friendly)."""
+    en = torch.as_tensor(energies, dtype=torch.float64, device=cT.device).reshape(-1)
+    mask = (en > 0).to(torch.float64)
+    c = cT.reshape(cT.shape[0], -1, 2)
+    return ((c * c).sum(-1) * mask).sum(-1)
+
+
+class Propagate(torch.autograd.Function):
+    """c(T) = RK4 map of (field, c0); backward runs the library's discrete adjoint."""
+
+    @staticmethod
+    def forward(ctx, field, c0, plan: Plan, dt: float, ckpt_every: int = 64):
+        cT, ck = plan.propagate(field, c0, dt, "rk4", ckpt_every=ckpt_every)
+        ctx.plan, ctx.dt, ctx.ckpt_every = plan, dt, ckpt_every
+        ctx.save_for_backward(field, c0, ck)
+        return cT
+
+    @staticmethod
+    def backward(ctx, grad_cT):
+        field, c0, ck = ctx.saved_tensors
+        plan = ctx.plan
+        g, l0 = plan.adjoint(field, c0, ctx.dt, grad_cT.contiguous(), ckpt=ck,
+                             ckpt_every=ctx.ckpt_every)
+        return g.reshape(field.shape), l0.reshape(c0.shape), None, None, None
+
+
+__all__ = ["Plan", "Propagate", "ionization_yield", "TdseError", "METHODS"]

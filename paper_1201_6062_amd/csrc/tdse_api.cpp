@@ -1,0 +1,360 @@
+// C ABI of the TDSE library: argument checking, plan lifetime, scheduling of
+// the per-product launches, and graph capture of step chunks.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+
+#include "tdse_internal.h"
+#include "tdse_validate.h"
+
+namespace tdse {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+tdse_status fail(tdse_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+tdse_status hip_fail(hipError_t e, const char *what) {
+    g_last_error = std::string("HIP error ") + hipGetErrorString(e) + " in " + what;
+    return TDSE_E_HIP;
+}
+
+// Device memory check used by every entry point before anything is enqueued.
+static bool is_device_ptr(const void *p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+static tdse_status check_dev(const void *p, const char *name) {
+    if (!p) return fail(TDSE_E_INVAL, std::string(name) + " is NULL");
+    if (reinterpret_cast<uintptr_t>(p) % 8) return fail(TDSE_E_INVAL, std::string(name) + " is not 8-byte aligned");
+    if (!is_device_ptr(p)) return fail(TDSE_E_INVAL, std::string(name) + " is not device memory");
+    return TDSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch schedule of one step: the completion each launch performs on the
+// previous launch's product (see vec_kernels.hip).
+static void step_launches(tdse_method m, int order, std::vector<Completion> &out) {
+    out.clear();
+    if (m == TDSE_RK4) {
+        // launch 1 completes stage 4 of the previous step, launches 2..4 complete stages 1..3
+        out.push_back({CK_RK4_END, 2, -1, 0, 1.0 / 6.0, 0.0});
+        out.push_back({CK_RK4_MID, 0, 0, 1, 1.0 / 6.0, 0.5});
+        out.push_back({CK_RK4_MID, 1, 0, 0, 2.0 / 6.0, 0.5});
+        out.push_back({CK_RK4_MID, 1, 0, 0, 2.0 / 6.0, 1.0});
+    } else {
+        // launch 1 completes term p of the previous step, launch m completes term m-1
+        out.push_back({CK_TAY_END, 0, -1, 0, 0.0, 1.0 / order});
+        for (int t = 1; t < order; ++t) out.push_back({CK_TAY_MID, 0, 0, 0, 0.0, 1.0 / t});
+    }
+}
+
+static Completion final_completion(tdse_method m, int order) {
+    std::vector<Completion> v;
+    step_launches(m, order, v);
+    return v[0];
+}
+
+static hipError_t enqueue_steps(tdse_plan p, tdse_method m, int order, int64_t nsteps_chunk,
+                                int32_t &parity, hipStream_t s) {
+    std::vector<Completion> sl;
+    step_launches(m, order, sl);
+    for (int64_t k = 0; k < nsteps_chunk; ++k) {
+        for (const Completion &c : sl) {
+            VecLaunch L{};
+            L.comp = c;
+            L.off = (int32_t)k;
+            L.parity = parity;
+            hipError_t e = p->lmax > 0 ? vec_launch_tiles(p->vb, L, s) : vec_launch_combine(p->vb, L, s);
+            if (e != hipSuccess) return e;
+            parity ^= 1;
+        }
+    }
+    return hipSuccess;
+}
+
+static const int64_t CHUNK_STEPS = 64;  // even, so every chunk has an even launch count
+
+static tdse_status get_chunk_graph(tdse_plan p, tdse_method m, int order, hipGraphExec_t *out) {
+    char key[64];
+    snprintf(key, sizeof key, "vec:%d:%d:%lld", (int)m, order, (long long)CHUNK_STEPS);
+    auto it = p->graphs.find(key);
+    if (it != p->graphs.end()) {
+        *out = it->second;
+        return TDSE_OK;
+    }
+    hipStream_t cs;
+    TDSE_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int32_t par = 0;
+    if (e == hipSuccess) e = enqueue_steps(p, m, order, CHUNK_STEPS, par, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess) e = e2;
+    hipGraphExec_t ge = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(e, "graph capture of a step chunk");
+    }
+    p->graphs[key] = ge;
+    p->graph_defs.push_back(g);
+    *out = ge;
+    return TDSE_OK;
+}
+
+static bool graphs_enabled() {
+    const char *v = getenv("TDSE_NO_GRAPH");
+    return !(v && v[0] == '1');
+}
+
+static tdse_status vec_propagate(tdse_plan p, tdse_method m, int order, double dt, int64_t nsteps,
+                                 const double *field, const double *c0, double *cT, double *ckpt,
+                                 int32_t K, hipStream_t s) {
+    CallDesc d{};
+    d.base_step = 0;
+    d.nsteps = nsteps;
+    d.field = field;
+    d.ckpt = ckpt;
+    d.ckpt_every = ckpt ? K : 1;
+    d.dt = dt;
+    d.slots = m == TDSE_RK4 ? 3 : 1;
+    TDSE_HIP(set_desc(p->vb.desc, d, s));
+    int32_t parity = 0;
+    TDSE_HIP(vec_launch_start(p->vb, parity, c0, m, s));
+    int64_t done = 0;
+    if (graphs_enabled() && nsteps >= CHUNK_STEPS) {
+        hipGraphExec_t ge;
+        tdse_status st = get_chunk_graph(p, m, order, &ge);
+        if (st != TDSE_OK) return st;
+        for (; done + CHUNK_STEPS <= nsteps; done += CHUNK_STEPS) {
+            TDSE_HIP(set_desc_base(p->vb.desc, done, s));
+            TDSE_HIP(hipGraphLaunch(ge, s));
+        }
+    }
+    TDSE_HIP(set_desc_base(p->vb.desc, done, s));
+    TDSE_HIP(enqueue_steps(p, m, order, nsteps - done, parity, s));
+    VecLaunch L{};
+    L.comp = final_completion(m, order);
+    L.off = (int32_t)(nsteps - done);
+    L.parity = parity;
+    L.finish = 1;
+    L.out = cT;
+    TDSE_HIP(vec_launch_combine(p->vb, L, s));
+    return TDSE_OK;
+}
+
+// Lay the plan's scratch out in one allocation.
+static tdse_status vec_alloc(tdse_plan p) {
+    const size_t ns = (size_t)(p->lmax + 1) * p->n;
+    const size_t npart = (size_t)p->lmax * p->T * p->T * VEC_TILE_MAX;
+    const size_t st_bytes = ns * sizeof(double2);
+    const size_t part_bytes = npart * sizeof(double2);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t total = 6 * al(st_bytes) + 4 * al(part_bytes) + al(sizeof(CallDesc));
+    char *base = nullptr;
+    if (hipMalloc(&base, total) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(TDSE_E_NOMEM, "hipMalloc of plan scratch failed");
+    }
+    p->scratch = reinterpret_cast<double *>(base);
+    p->scratch_bytes = total;
+    size_t off = 0;
+    for (int par = 0; par < 2; ++par)
+        for (int v = 0; v < 3; ++v) {
+            p->vb.st[par][v] = reinterpret_cast<double2 *>(base + off);
+            off += al(st_bytes);
+        }
+    for (int par = 0; par < 2; ++par) {
+        p->vb.rowp[par] = reinterpret_cast<double2 *>(base + off);
+        off += al(part_bytes);
+        p->vb.colp[par] = reinterpret_cast<double2 *>(base + off);
+        off += al(part_bytes);
+    }
+    p->vb.desc = reinterpret_cast<CallDesc *>(base + off);
+    p->vb.en = p->en;
+    p->vb.dip = p->dip;
+    p->vb.lmax = p->lmax;
+    p->vb.n = p->n;
+    p->vb.ld = p->ld;
+    p->vb.T = p->T;
+    return TDSE_OK;
+}
+
+}  // namespace tdse
+
+using namespace tdse;
+
+extern "C" {
+
+int tdse_abi_version(void) { return TDSE_ABI_VERSION; }
+
+const char *tdse_last_error(void) { return g_last_error.c_str(); }
+
+tdse_status tdse_create(tdse_plan *out, const double *energies, const double *dipole,
+                        int32_t lmax, int32_t n, int32_t batch, void *stream) {
+    clear_error();
+    std::string why;
+    tdse_status st = validate_create(out, energies, dipole, lmax, n, batch, &why);
+    if (st != TDSE_OK) return fail(st, why);
+    if (batch != 1) return fail(TDSE_E_UNSUPPORTED, "batch > 1 is not built yet");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    tdse_plan p = new (std::nothrow) tdse_plan_s();
+    if (!p) return fail(TDSE_E_NOMEM, "host allocation failed");
+    p->lmax = lmax;
+    p->n = n;
+    p->batch = batch;
+    TDSE_HIP(hipGetDevice(&p->device));
+    p->ld = n + (n & 1);
+    p->T = (n + VEC_TILE_MAX - 1) / VEC_TILE_MAX;
+    const size_t ns = (size_t)(lmax + 1) * n;
+    hipError_t e = hipMalloc(&p->en, ns * sizeof(double));
+    if (e == hipSuccess && lmax > 0) e = hipMalloc(&p->dip, (size_t)lmax * n * p->ld * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        tdse_destroy(p);
+        return fail(TDSE_E_NOMEM, "hipMalloc of the Hamiltonian failed");
+    }
+    e = hipMemcpyAsync(p->en, energies, ns * sizeof(double), hipMemcpyDefault, s);
+    if (e == hipSuccess && lmax > 0)
+        e = hipMemcpy2DAsync(p->dip, p->ld * sizeof(double), dipole, n * sizeof(double),
+                             n * sizeof(double), (size_t)lmax * n, hipMemcpyDefault, s);
+    if (e == hipSuccess && lmax > 0 && p->ld != n)
+        e = hipMemset2DAsync(p->dip + n, p->ld * sizeof(double), 0, (p->ld - n) * sizeof(double),
+                             (size_t)lmax * n, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        tdse_destroy(p);
+        return hip_fail(e, "copy of the Hamiltonian into the plan");
+    }
+    st = vec_alloc(p);
+    if (st != TDSE_OK) {
+        std::string msg = g_last_error;
+        tdse_destroy(p);
+        return fail(st, msg);
+    }
+    *out = p;
+    return TDSE_OK;
+}
+
+tdse_status tdse_destroy(tdse_plan p) {
+    clear_error();
+    if (!p) return TDSE_OK;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t g : p->graph_defs) (void)hipGraphDestroy(g);
+    if (p->scratch) (void)hipFree(p->scratch);
+    if (p->dip) (void)hipFree(p->dip);
+    if (p->en) (void)hipFree(p->en);
+    delete p;
+    return TDSE_OK;
+}
+
+tdse_status tdse_plan_shape(tdse_plan p, int32_t *lmax, int32_t *n, int32_t *batch) {
+    clear_error();
+    if (!p) return fail(TDSE_E_INVAL, "plan is NULL");
+    if (lmax) *lmax = p->lmax;
+    if (n) *n = p->n;
+    if (batch) *batch = p->batch;
+    return TDSE_OK;
+}
+
+tdse_status tdse_hmul(tdse_plan p, const double *fields, const double *u, double *y, void *stream) {
+    clear_error();
+    if (!p) return fail(TDSE_E_INVAL, "plan is NULL");
+    tdse_status st;
+    if ((st = check_dev(fields, "fields")) || (st = check_dev(u, "u")) || (st = check_dev(y, "y")))
+        return st;
+    if (u == y) return fail(TDSE_E_INVAL, "u and y must not alias");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    CallDesc d{};
+    d.nsteps = 1;
+    d.field = fields;
+    d.ckpt_every = 1;
+    d.dt = 1.0;
+    d.slots = 1;
+    TDSE_HIP(set_desc(p->vb.desc, d, s));
+    TDSE_HIP(vec_launch_start(p->vb, 0, u, TDSE_RK4, s));
+    VecLaunch L{};
+    L.comp = {CK_RK4_END, 0, -1, 0, 1.0 / 6.0, 0.0};
+    L.parity = 0;
+    if (p->lmax > 0) TDSE_HIP(vec_launch_tiles(p->vb, L, s));
+    else TDSE_HIP(vec_launch_combine(p->vb, L, s));
+    VecLaunch H{};
+    H.comp = {CK_HMUL, 0, 0, 0, 0.0, 0.0};
+    H.parity = 1;
+    H.out = y;
+    TDSE_HIP(vec_launch_combine(p->vb, H, s));
+    return TDSE_OK;
+}
+
+tdse_status tdse_propagate(tdse_plan p, tdse_method method, int32_t order, double dt,
+                           int64_t nsteps, const double *field, const double *c0, double *cT,
+                           double *ckpt, int32_t ckpt_every, void *stream) {
+    clear_error();
+    std::string why;
+    tdse_status st = validate_propagate(p != nullptr, (int)method, order, dt, nsteps, ckpt != nullptr,
+                                        ckpt_every, &why);
+    if (st != TDSE_OK) return fail(st, why);
+    if (nsteps > 0 && (st = check_dev(field, "field"))) return st;
+    if ((st = check_dev(c0, "c0")) || (st = check_dev(cT, "cT"))) return st;
+    if (ckpt && (st = check_dev(ckpt, "ckpt"))) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return vec_propagate(p, method, method == TDSE_RK4 ? 4 : order, dt, nsteps, field, c0, cT, ckpt,
+                         ckpt_every, s);
+}
+
+tdse_status tdse_adjoint(tdse_plan p, tdse_method method, int32_t order, double dt, int64_t nsteps,
+                         const double *field, const double *c0, const double *ckpt,
+                         int32_t ckpt_every, const double *lambdaT, double *grad_field,
+                         double *lambda0, void *stream) {
+    clear_error();
+    (void)order; (void)dt; (void)nsteps; (void)field; (void)c0; (void)ckpt; (void)ckpt_every;
+    (void)lambdaT; (void)grad_field; (void)lambda0; (void)stream;
+    if (!p) return fail(TDSE_E_INVAL, "plan is NULL");
+    if (method != TDSE_RK4) return fail(TDSE_E_UNSUPPORTED, "the adjoint is implemented for RK4 only");
+    return fail(TDSE_E_UNSUPPORTED, "adjoint not built yet");
+}
+
+tdse_status tdse_group_create(tdse_group *out, int32_t count, const tdse_plan *plans, void *stream) {
+    clear_error();
+    (void)out; (void)count; (void)plans; (void)stream;
+    return fail(TDSE_E_UNSUPPORTED, "groups not built yet");
+}
+
+tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order, double dt,
+                                 const int64_t *nsteps, const double *const *fields,
+                                 const double *const *c0, double *const *cT, void *stream) {
+    clear_error();
+    (void)g; (void)method; (void)order; (void)dt; (void)nsteps; (void)fields; (void)c0; (void)cT;
+    (void)stream;
+    return fail(TDSE_E_UNSUPPORTED, "groups not built yet");
+}
+
+tdse_status tdse_group_destroy(tdse_group g) {
+    clear_error();
+    (void)g;
+    return TDSE_OK;
+}
+
+tdse_status tdse_tune(int32_t lmax, int32_t n, int32_t batch, const char *cache_path) {
+    clear_error();
+    (void)lmax; (void)n; (void)batch; (void)cache_path;
+    return fail(TDSE_E_UNSUPPORTED, "tuner not built yet");
+}
+
+}  // extern "C"

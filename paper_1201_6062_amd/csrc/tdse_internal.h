@@ -1,0 +1,111 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tdse.h"
+#include "tdse_split.h"
+
+namespace tdse {
+
+// ---------------------------------------------------------------------------
+// Error reporting (thread-local text, see tdse_last_error).
+void set_error(const std::string &msg);
+void clear_error();
+tdse_status fail(tdse_status st, const std::string &msg);
+tdse_status hip_fail(hipError_t e, const char *what);
+
+#define TDSE_HIP(call)                                        \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return ::tdse::hip_fail(e_, #call); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Completion of one product (the RK4 stage or Taylor term whose dipole
+// product the previous launch computed) and formation of the next input.
+enum CompletionKind : int32_t {
+    CK_RK4_MID = 0,   // completed RK4 stage s in 1..3
+    CK_RK4_END = 1,   // completed RK4 stage 4 (finishes a step)
+    CK_TAY_MID = 2,   // completed Taylor term m < p
+    CK_TAY_END = 3,   // completed Taylor term p (finishes a step)
+    CK_HMUL = -1,     // no completion: write y = E o u + F z (single product)
+};
+
+struct Completion {
+    int32_t kind;
+    int32_t slot;        // field sample slot of the completed product
+    int32_t step_delta;  // step of the completed product = base + off + step_delta
+    int32_t first;       // RK4 stage 1: acc = w k (reset); else acc += w k
+    double w_acc;        // RK4: b_s; Taylor: unused
+    double a_next;       // RK4: alpha_{s+1} (times dt in-kernel); Taylor: dt/m factor
+};
+
+// Per-call values that a captured graph reads from device memory, so one
+// graph serves every call of the same shape.
+struct CallDesc {
+    int64_t base_step;   // first step of the current chunk
+    int64_t nsteps;
+    const double *field; // [B][nsteps][S]
+    double *ckpt;        // may be null
+    int64_t ckpt_every;
+    double dt;
+    int32_t slots;       // S
+    int32_t pad_;
+};
+
+// ---------------------------------------------------------------------------
+// Single-vector (batch == 1) streaming path.
+constexpr int VEC_TILE_MAX = 128;   // max rows/cols of one dipole tile
+constexpr int VEC_THREADS = 512;    // 8 waves per tile workgroup
+
+struct VecBuffers {
+    const double *en;      // [(lmax+1)*n]
+    const double *dip;     // [lmax][n][ld]
+    double2 *st[2][3];     // [parity][c, acc, u] each [(lmax+1)*n]
+    double2 *rowp[2];      // [parity][lmax][T][T][VEC_TILE_MAX]
+    double2 *colp[2];      // [parity][lmax][T(out seg j)][T(contrib i)][VEC_TILE_MAX]
+    CallDesc *desc;
+    int32_t lmax, n, ld, T;
+};
+
+struct VecLaunch {
+    Completion comp;
+    int32_t off;     // step offset within chunk of the launch
+    int32_t parity;  // launch parity: read st/partials[parity], write [parity^1]
+    int32_t finish;  // 1: write c' to the caller's cT (finish launch)
+    int32_t pad_;
+    double *out;     // caller cT for the finish launch
+};
+
+hipError_t vec_launch_tiles(const VecBuffers &b, const VecLaunch &l, hipStream_t s);
+hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream_t s);
+hipError_t vec_launch_start(const VecBuffers &b, int32_t parity, const double *c0, int32_t method,
+                            hipStream_t s);
+hipError_t set_desc_base(CallDesc *d, int64_t base, hipStream_t s);
+hipError_t set_desc(CallDesc *d, const CallDesc &v, hipStream_t s);
+
+}  // namespace tdse
+
+// ---------------------------------------------------------------------------
+struct tdse_plan_s {
+    int32_t lmax = 0, n = 0, batch = 1;
+    int device = 0;
+    // device copies of the Hamiltonian
+    double *en = nullptr;
+    double *dip = nullptr;
+    int32_t ld = 0;
+    // single-vector path
+    int32_t T = 1;
+    double *scratch = nullptr;   // one allocation holding states, partials, descriptor
+    size_t scratch_bytes = 0;
+    tdse::VecBuffers vb{};
+    // captured chunk graphs keyed by (method, order, chunk steps, parity)
+    std::map<std::string, hipGraphExec_t> graphs;
+    std::vector<hipGraph_t> graph_defs;
+};
