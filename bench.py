@@ -1,0 +1,204 @@
+"""Throughput of the TDSE propagation hot path on one MI355X.
+
+A step of this benchmark is one whole propagation of the Lmax=15, N=500
+single-instance workload (8000 complex128 states, 20-cycle pulse, RK4 with
+dt=0.005: 50266 time steps, 201064 dipole products). The metric is
+state-steps/s = states x time steps / wall time, with inputs resident in HBM.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line. `roofline` describes the dominant kernel (the fused
+tile kernel, one launch per dipole product); `cpu_baseline` times the CPU
+oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 matrix / vector
+
+
+def algorithmic_bytes_per_product(lmax: int, n: int) -> int:
+    """Dipole read once (8 L N^2) + energies (8 n) + one complex vector in and out (32 n)."""
+    ns = (lmax + 1) * n
+    return 8 * lmax * n * n + 40 * ns
+
+
+def time_propagation(plan, w, method, order, steps, warmup, torch):
+    import torch as _t
+    f = _t.as_tensor(w.field, device="cuda")
+    c0 = _t.as_tensor(w.c0, device="cuda")
+    out = _t.empty_like(c0)
+    for _ in range(warmup):
+        plan.propagate(f, c0, w.dt, method, order=order, out=out)
+    _t.cuda.synchronize()
+    stream = _t.cuda.current_stream()
+    e0, e1 = _t.cuda.Event(enable_timing=True), _t.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.propagate(f, c0, w.dt, method, order=order, out=out)
+    e1.record(stream)
+    _t.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_s = e0.elapsed_time(e1) / 1e3
+    return ev_s, wall, out.cpu().numpy()
+
+
+def cpu_baseline(w, target_s: float = 20.0):
+    """The oracle, single-threaded, on the first steps of the same workload."""
+    import oracle
+    oracle.build(force=False)
+    h = w.ham
+
+    def run(k):
+        if w.method == "rk4":
+            oracle.rk4(h.energies, h.dipole, w.dt, w.field[:, :k], w.c0)
+        else:
+            oracle.taylor(h.energies, h.dipole, w.order, w.dt, w.field[:, :k], w.c0)
+    # size the sample from one timed step
+    t = time.perf_counter()
+    run(1)
+    per = time.perf_counter() - t
+    nst = max(1, min(w.nsteps, int(target_s / max(per, 1e-6))))
+    t = time.perf_counter()
+    run(nst)
+    el = time.perf_counter() - t
+    return {"value": h.nstates * nst / el, "unit": "state-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {nst} of {w.nsteps} {w.method} steps of the Lmax=15 N=500 workload, "
+                      f"one thread, {el:.1f} s"}
+
+
+def hbm_diagnostic(torch, steps=64):
+    """Lmax=63, N=1000 (504 MB of dipole, far beyond L2 and MALL): HBM-streaming rate."""
+    from paper_1201_6062_amd import workloads as wl
+    from paper_1201_6062_amd.api import Plan
+    lmax, n, dt = 63, 1000, 0.005
+    en = wl.energies(lmax, n)
+    rng = np.random.default_rng(5)
+    dip = rng.standard_normal((lmax, n, n)) * 0.01
+    plan = Plan(en, dip)
+    f = wl.rk4_samples(wl.Pulse(0.05, 0.5, 20.0), dt, steps)[None]
+    c0 = wl.ground_state(lmax, n)
+
+    class W:
+        pass
+    w = W()
+    w.field, w.c0, w.dt = f, c0, dt
+    ev, _, _ = time_propagation(plan, w, "rk4", 0, 3, 1, torch)
+    per_launch = ev / 3 / (4 * steps)
+    b = algorithmic_bytes_per_product(lmax, n)
+    plan.close()
+    return {"workload": "Lmax=63 N=1000 RK4, 64 steps", "bytes_per_product": b,
+            "us_per_product": per_launch * 1e6, "GBps": b / per_launch / 1e9,
+            "frac_of_hbm_peak": b / per_launch / 1e9 / HBM_PEAK_GBS}
+
+
+def calibrate_copy(torch, mb: int = 1024, reps: int = 5):
+    """Plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    x = torch.ones(mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_MiB": mb, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-diag", action="store_true")
+    ap.add_argument("--method", choices=["rk4", "taylor"], default="rk4")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--truncate", type=int, default=0,
+                    help="profiling runs only: propagate the first STEPS time steps")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    if a.calibrate_copy:
+        calibrate_copy(torch)
+        return
+    from paper_1201_6062_amd import workloads as wl
+    from paper_1201_6062_amd.api import Plan
+
+    w = wl.single_large(a.method, 8)
+    if a.truncate:
+        w.nsteps = min(w.nsteps, a.truncate)
+        w.field = np.ascontiguousarray(w.field[:, : w.nsteps])
+    plan = Plan(w.ham.energies, w.ham.dipole)
+    ev_s, wall_s, cT = time_propagation(plan, w, a.method, 8, a.steps, a.warmup, torch)
+    ns = w.ham.nstates
+    products_per_step = 4 if a.method == "rk4" else 8
+    launches = w.nsteps * products_per_step
+    ms_per_step = ev_s / a.steps * 1e3
+    value = ns * w.nsteps * a.steps / ev_s
+    per_launch = ev_s / a.steps / launches
+    bpp = algorithmic_bytes_per_product(w.ham.lmax, w.ham.n)
+
+    err = None
+    gold = os.path.join(ROOT, "tests", "golden", f"single_large_{'rk4' if a.method == 'rk4' else 'taylor8'}.npz")
+    if os.path.exists(gold) and not a.truncate:
+        g = np.load(gold, allow_pickle=False)["cT"]
+        err = float(np.linalg.norm(cT[0] - g) / np.linalg.norm(g))
+
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic_vec_tiles_L15_N500.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            traffic = json.load(fh).get("bytes_per_launch")
+
+    out = {
+        "metric": "state-steps/s",
+        "value": value,
+        "unit": "state-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded hydrogen-like Hamiltonian and sin^2 pulse)",
+        "config": {"workload": f"single instance Lmax=15 N=500 (8000 states), "
+                               f"{'RK4 dt=0.005' if a.method == 'rk4' else 'Taylor-8 dt=0.02'}, "
+                               f"20-cycle pulse E0=0.05 w=0.5, {w.nsteps} time steps per propagation",
+                   "states": ns, "time_steps": w.nsteps, "products_per_propagation": launches},
+        "roofline": {"bound": "hbm", "achieved": bpp / per_launch / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": bpp / per_launch / 1e9 / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "vec_tiles_kernel", "bytes_per_launch": bpp,
+                     "us_per_launch": per_launch * 1e6},
+        "max_rel_err_vs_oracle": err,
+        "wall_s_host": wall_s,
+    }
+    plan.close()
+    if not a.no_diag:
+        out["hbm_diagnostic"] = hbm_diagnostic(torch)
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

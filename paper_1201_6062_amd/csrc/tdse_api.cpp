@@ -78,6 +78,7 @@ static hipError_t enqueue_steps(tdse_plan p, tdse_method m, int order, int64_t n
             L.comp = c;
             L.off = (int32_t)k;
             L.parity = parity;
+            L.slots = m == TDSE_RK4 ? 3 : 1;
             hipError_t e = p->lmax > 0 ? vec_launch_tiles(p->vb, L, s) : vec_launch_combine(p->vb, L, s);
             if (e != hipSuccess) return e;
             parity ^= 1;
@@ -86,11 +87,10 @@ static hipError_t enqueue_steps(tdse_plan p, tdse_method m, int order, int64_t n
     return hipSuccess;
 }
 
-static const int64_t CHUNK_STEPS = 64;  // even, so every chunk has an even launch count
 
 static tdse_status get_chunk_graph(tdse_plan p, tdse_method m, int order, hipGraphExec_t *out) {
     char key[64];
-    snprintf(key, sizeof key, "vec:%d:%d:%lld", (int)m, order, (long long)CHUNK_STEPS);
+    snprintf(key, sizeof key, "vec:%d:%d:%d", (int)m, order, CHUNK_STEPS);
     auto it = p->graphs.find(key);
     if (it != p->graphs.end()) {
         *out = it->second;
@@ -136,22 +136,28 @@ static tdse_status vec_propagate(tdse_plan p, tdse_method m, int order, double d
     TDSE_HIP(set_desc(p->vb.desc, d, s));
     int32_t parity = 0;
     TDSE_HIP(vec_launch_start(p->vb, parity, c0, m, s));
-    int64_t done = 0;
+    hipGraphExec_t ge = nullptr;
     if (graphs_enabled() && nsteps >= CHUNK_STEPS) {
-        hipGraphExec_t ge;
         tdse_status st = get_chunk_graph(p, m, order, &ge);
         if (st != TDSE_OK) return st;
-        for (; done + CHUNK_STEPS <= nsteps; done += CHUNK_STEPS) {
-            TDSE_HIP(set_desc_base(p->vb.desc, done, s));
-            TDSE_HIP(hipGraphLaunch(ge, s));
+    }
+    int64_t base = 0;
+    TDSE_HIP(chunk_begin(p->vb.desc, 0, s));
+    for (int64_t done = 0; done < nsteps; done += CHUNK_STEPS) {
+        base = done;
+        if (done > 0) TDSE_HIP(chunk_begin(p->vb.desc, done, s));
+        const int64_t len = nsteps - done < CHUNK_STEPS ? nsteps - done : CHUNK_STEPS;
+        if (ge && len == CHUNK_STEPS) {
+            TDSE_HIP(hipGraphLaunch(ge, s));  // even launch count: parity unchanged
+        } else {
+            TDSE_HIP(enqueue_steps(p, m, order, len, parity, s));
         }
     }
-    TDSE_HIP(set_desc_base(p->vb.desc, done, s));
-    TDSE_HIP(enqueue_steps(p, m, order, nsteps - done, parity, s));
     VecLaunch L{};
     L.comp = final_completion(m, order);
-    L.off = (int32_t)(nsteps - done);
+    L.off = (int32_t)(nsteps - base);
     L.parity = parity;
+    L.slots = m == TDSE_RK4 ? 3 : 1;
     L.finish = 1;
     L.out = cT;
     TDSE_HIP(vec_launch_combine(p->vb, L, s));
@@ -192,6 +198,7 @@ static tdse_status vec_alloc(tdse_plan p) {
     p->vb.n = p->n;
     p->vb.ld = p->ld;
     p->vb.T = p->T;
+    for (int q = 0; q <= 16; ++q) p->vb.seg[q] = (int32_t)split_start(p->n, p->T, q < p->T ? q : p->T);
     return TDSE_OK;
 }
 
@@ -219,24 +226,31 @@ tdse_status tdse_create(tdse_plan *out, const double *energies, const double *di
     p->n = n;
     p->batch = batch;
     TDSE_HIP(hipGetDevice(&p->device));
-    p->ld = n + (n & 1);
+    p->ld = VEC_TILE_MAX;
     p->T = (n + VEC_TILE_MAX - 1) / VEC_TILE_MAX;
+    if (p->T > 16) {
+        delete p;
+        return fail(TDSE_E_UNSUPPORTED, "n > 2048 states per partial wave is not supported");
+    }
     const size_t ns = (size_t)(lmax + 1) * n;
+    const size_t dip_elems = (size_t)lmax * n * n;
+    const size_t tiled_elems = (size_t)lmax * p->T * p->T * VEC_TILE_MAX * VEC_TILE_MAX;
+    double *stage = nullptr;
     hipError_t e = hipMalloc(&p->en, ns * sizeof(double));
-    if (e == hipSuccess && lmax > 0) e = hipMalloc(&p->dip, (size_t)lmax * n * p->ld * sizeof(double));
+    if (e == hipSuccess && lmax > 0) e = hipMalloc(&p->dip, tiled_elems * sizeof(double));
+    if (e == hipSuccess && lmax > 0) e = hipMalloc(&stage, dip_elems * sizeof(double));
     if (e != hipSuccess) {
         (void)hipGetLastError();
+        if (stage) (void)hipFree(stage);
         tdse_destroy(p);
         return fail(TDSE_E_NOMEM, "hipMalloc of the Hamiltonian failed");
     }
     e = hipMemcpyAsync(p->en, energies, ns * sizeof(double), hipMemcpyDefault, s);
     if (e == hipSuccess && lmax > 0)
-        e = hipMemcpy2DAsync(p->dip, p->ld * sizeof(double), dipole, n * sizeof(double),
-                             n * sizeof(double), (size_t)lmax * n, hipMemcpyDefault, s);
-    if (e == hipSuccess && lmax > 0 && p->ld != n)
-        e = hipMemset2DAsync(p->dip + n, p->ld * sizeof(double), 0, (p->ld - n) * sizeof(double),
-                             (size_t)lmax * n, s);
+        e = hipMemcpyAsync(stage, dipole, dip_elems * sizeof(double), hipMemcpyDefault, s);
+    if (e == hipSuccess && lmax > 0) e = vec_layout(stage, p->dip, lmax, n, p->T, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (stage) (void)hipFree(stage);
     if (e != hipSuccess) {
         tdse_destroy(p);
         return hip_fail(e, "copy of the Hamiltonian into the plan");
@@ -288,15 +302,18 @@ tdse_status tdse_hmul(tdse_plan p, const double *fields, const double *u, double
     d.dt = 1.0;
     d.slots = 1;
     TDSE_HIP(set_desc(p->vb.desc, d, s));
+    TDSE_HIP(chunk_begin(p->vb.desc, 0, s));
     TDSE_HIP(vec_launch_start(p->vb, 0, u, TDSE_RK4, s));
     VecLaunch L{};
     L.comp = {CK_RK4_END, 0, -1, 0, 1.0 / 6.0, 0.0};
     L.parity = 0;
+    L.slots = 1;
     if (p->lmax > 0) TDSE_HIP(vec_launch_tiles(p->vb, L, s));
     else TDSE_HIP(vec_launch_combine(p->vb, L, s));
     VecLaunch H{};
     H.comp = {CK_HMUL, 0, 0, 0, 0.0, 0.0};
     H.parity = 1;
+    H.slots = 1;
     H.out = y;
     TDSE_HIP(vec_launch_combine(p->vb, H, s));
     return TDSE_OK;

@@ -48,6 +48,8 @@ struct Completion {
 
 // Per-call values that a captured graph reads from device memory, so one
 // graph serves every call of the same shape.
+constexpr int CHUNK_STEPS = 64;  // steps per captured graph (even: even launch count)
+
 struct CallDesc {
     int64_t base_step;   // first step of the current chunk
     int64_t nsteps;
@@ -57,6 +59,13 @@ struct CallDesc {
     double dt;
     int32_t slots;       // S
     int32_t pad_;
+    // Field samples of steps base_step-1 .. base_step+CHUNK_STEPS-1 (zero outside
+    // [0, nsteps)), staged at a fixed address at the start of every chunk so a
+    // launch finds its sample without a dependent load.
+    double chunk_field[(CHUNK_STEPS + 1) * 3];
+    // Checkpoint row written by a completion that ends step base_step + x
+    // (x = 0 .. CHUNK_STEPS), or -1 when that step is not a checkpoint.
+    int64_t chunk_ckpt_row[CHUNK_STEPS + 1];
 };
 
 // ---------------------------------------------------------------------------
@@ -66,12 +75,13 @@ constexpr int VEC_THREADS = 512;    // 8 waves per tile workgroup
 
 struct VecBuffers {
     const double *en;      // [(lmax+1)*n]
-    const double *dip;     // [lmax][n][ld]
+    const double *dip;     // tiles [lmax][T][T][VEC_TILE_MAX][VEC_TILE_MAX]
     double2 *st[2][3];     // [parity][c, acc, u] each [(lmax+1)*n]
     double2 *rowp[2];      // [parity][lmax][T][T][VEC_TILE_MAX]
     double2 *colp[2];      // [parity][lmax][T(out seg j)][T(contrib i)][VEC_TILE_MAX]
     CallDesc *desc;
     int32_t lmax, n, ld, T;
+    int32_t seg[17];       // segment starts (Sec. 4.1 split of n over T), seg[T] = n
 };
 
 struct VecLaunch {
@@ -79,7 +89,7 @@ struct VecLaunch {
     int32_t off;     // step offset within chunk of the launch
     int32_t parity;  // launch parity: read st/partials[parity], write [parity^1]
     int32_t finish;  // 1: write c' to the caller's cT (finish launch)
-    int32_t pad_;
+    int32_t slots;   // field samples per step (3 RK4, 1 Taylor)
     double *out;     // caller cT for the finish launch
 };
 
@@ -87,7 +97,8 @@ hipError_t vec_launch_tiles(const VecBuffers &b, const VecLaunch &l, hipStream_t
 hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream_t s);
 hipError_t vec_launch_start(const VecBuffers &b, int32_t parity, const double *c0, int32_t method,
                             hipStream_t s);
-hipError_t set_desc_base(CallDesc *d, int64_t base, hipStream_t s);
+hipError_t chunk_begin(CallDesc *d, int64_t base, hipStream_t s);
+hipError_t vec_layout(const double *src, double *dst, int lmax, int n, int T, hipStream_t s);
 hipError_t set_desc(CallDesc *d, const CallDesc &v, hipStream_t s);
 
 }  // namespace tdse

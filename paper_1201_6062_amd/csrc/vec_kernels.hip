@@ -13,17 +13,78 @@
 // launch are reduced in fixed order by the prologue of the next launch, which
 // also completes the RK4 stage / Taylor term (the vector sums of Eqs.
 // RKDeriv / RKFinal) and forms the next product's input, so a whole stage is
-// one kernel.
+// one kernel. The prologue's loads are issued before the tile loads, so the
+// completion arithmetic runs while the tile is still streaming in.
 //
 // Tiles are assigned to workgroups so that a tile always lands on the same
-// XCD (workgroups are dispatched round-robin over the 8 XCDs); with a fixed
-// grid, each XCD's L2 keeps serving the same share of the dipole from one
-// launch to the next.
+// XCD (workgroups are dispatched round-robin over the 8 XCDs) and each XCD
+// works on a contiguous range of tiles.
 #include "tdse_internal.h"
 
 namespace tdse {
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// Streaming (non-temporal) access for partials and state, so that they do not
+// displace dipole lines from the caches.
+typedef double dv2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_nt(const double2 *p) {
+    dv2_t v = __builtin_nontemporal_load(reinterpret_cast<const dv2_t *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st_nt(double2 *p, double2 v) {
+    dv2_t w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<dv2_t *>(p));
+}
+// Store through a pointer that was itself loaded from memory: spelled as a
+// global-address-space store (a generic/flat store would also count against
+// the LDS counter and force waits on the tile stream).
+typedef __attribute__((address_space(1))) dv2_t gdv2_t;
+__device__ __forceinline__ void st_global(double2 *p, double2 v) {
+    dv2_t w = {v.x, v.y};
+    *(gdv2_t *)(p) = w;
+}
+
+// Workgroup barrier that orders LDS only. __syncthreads() also orders global
+// memory, which on gfx9 waits for every outstanding global load and store
+// (vmcnt(0)) -- including the tile stream this kernel wants to keep in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Cross-lane moves of a double through DPP (VALU, no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// value of lane (lane ^ H), H in {1, 2, 4, 8}
+template <int H>
+__device__ __forceinline__ double xor_lane(double v) {
+    if constexpr (H == 1) return dpp_f64<0xB1>(v);                       // quad_perm(1,0,3,2)
+    else if constexpr (H == 2) return dpp_f64<0x4E>(v);                  // quad_perm(2,3,0,1)
+    else if constexpr (H == 4) return dpp_f64<0x141>(dpp_f64<0x1B>(v));  // half-row mirror of xor 3
+    else return dpp_f64<0x128>(v);                                       // row rotate by 8
+}
+
+// Butterfly step over lane bit H: lanes keep half of the values and add the
+// partner's copy of that half.
+template <int H>
+__device__ __forceinline__ void butterfly(double *tr, double *ti, int lane) {
+    const bool up = (lane & H) != 0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        double sr = up ? tr[k] : tr[k + H], si = up ? ti[k] : ti[k + H];
+        double kr = up ? tr[k + H] : tr[k], ki = up ? ti[k + H] : ti[k];
+        tr[k] = kr + xor_lane<H>(sr);
+        ti[k] = ki + xor_lane<H>(si);
+    }
+}
 
 // y = H u_prev = E0 u + F z ; k = -i y. Then the RK4 / Taylor bookkeeping.
 __device__ __forceinline__ void apply_completion(const Completion &cp, double dt, double F,
@@ -75,163 +136,202 @@ __device__ __forceinline__ void apply_completion(const Completion &cp, double dt
     }
 }
 
-// z for state (m, segment q, entry e): row partials of tiles (m, q, *) then
-// column partials of tiles (m-1, *, q), each in ascending tile order.
-__device__ __forceinline__ double2 reduce_z(const VecBuffers &b, int par, int m, int q, int e) {
-    const int T = b.T;
-    double zx = 0.0, zy = 0.0;
-    if (m < b.lmax) {
-        const double2 *p = b.rowp[par] + ((size_t)(m * T + q) * T) * VEC_TILE_MAX + e;
-        for (int jj = 0; jj < T; ++jj) {
-            double2 v = p[(size_t)jj * VEC_TILE_MAX];
-            zx += v.x;
-            zy += v.y;
-        }
-    }
-    if (m > 0) {
-        const double2 *p = b.colp[par] + ((size_t)((m - 1) * T + q) * T) * VEC_TILE_MAX + e;
-        for (int ii = 0; ii < T; ++ii) {
-            double2 v = p[(size_t)ii * VEC_TILE_MAX];
-            zx += v.x;
-            zy += v.y;
-        }
-    }
-    return make_double2(zx, zy);
+// Buffer pointers by parity, selected without indexing the kernel-argument
+// struct at run time (that would turn into a dependent memory load).
+__device__ __forceinline__ double2 *st_ptr(const VecBuffers &b, int par, int v) {
+    if (v == 0) return par ? b.st[1][0] : b.st[0][0];
+    if (v == 1) return par ? b.st[1][1] : b.st[0][1];
+    return par ? b.st[1][2] : b.st[0][2];
 }
+__device__ __forceinline__ double2 *rowp_ptr(const VecBuffers &b, int par) { return par ? b.rowp[1] : b.rowp[0]; }
+__device__ __forceinline__ double2 *colp_ptr(const VecBuffers &b, int par) { return par ? b.colp[1] : b.colp[0]; }
 
 __device__ __forceinline__ bool is_end(int kind) { return kind == CK_RK4_END || kind == CK_TAY_END; }
 
-__device__ __forceinline__ double field_of(const CallDesc *d, const VecLaunch &L, int64_t &step) {
-    step = d->base_step + L.off + L.comp.step_delta;
-    return (step >= 0 && step < d->nsteps) ? d->field[step * d->slots + L.comp.slot] : 0.0;
+// Field sample of the product a launch completes, from the chunk's staged copy.
+__device__ __forceinline__ double field_of(const CallDesc *d, const VecLaunch &L) {
+    return d->chunk_field[(L.off + L.comp.step_delta + 1) * L.slots + L.comp.slot];
 }
 
-// One entry of the state: complete the previous product, return the next
-// input u, and (if this workgroup owns the entry) store the new state.
-__device__ __forceinline__ double2 complete_entry(const VecBuffers &b, const VecLaunch &L,
-                                                  const CallDesc *d, double dt, double F,
-                                                  int64_t step, int m, int q, int e, int s0,
-                                                  bool owner) {
-    const int par = L.parity;
-    size_t gi = (size_t)m * b.n + s0 + e;
-    double2 z = reduce_z(b, par, m, q, e);
-    double2 c = b.st[par][0][gi], acc = b.st[par][1][gi], u = b.st[par][2][gi];
-    apply_completion(L.comp, dt, F, b.en[gi], z, c, acc, u);
-    if (owner) {
-        b.st[par ^ 1][0][gi] = c;
-        b.st[par ^ 1][1][gi] = acc;
-        b.st[par ^ 1][2][gi] = u;
-        if (d->ckpt && is_end(L.comp.kind)) {
-            int64_t kk = step + 1;
-            if (kk % d->ckpt_every == 0) {
-                size_t ns = (size_t)(b.lmax + 1) * b.n;
-                reinterpret_cast<double2 *>(d->ckpt)[(size_t)(kk / d->ckpt_every) * ns + gi] = c;
-            }
-        }
+// Sum of the partials of one kind for state entry e of segment (m, q):
+// rows=true: row partials of tiles (m, q, 0..T-1); rows=false: column
+// partials of tiles (m-1, 0..T-1, q), in ascending tile order. The TP >= T
+// loads are unconditional (indices clamped into the buffer) and invalid terms
+// are dropped afterwards, so the loads issue back to back.
+template <int TP>
+__device__ __forceinline__ double2 sum_partials(const VecBuffers &b, int par, bool rows, int m,
+                                                int q, int e) {
+    // TP == T for T <= 8 (exact instantiations); TP == 16 covers 9..16.
+    const int T = TP <= 8 ? TP : b.T;
+    const bool valid = rows ? (m < b.lmax) : (m > 0);
+    const int hi = b.lmax > 0 ? b.lmax - 1 : 0;
+    int mb = rows ? m : m - 1;
+    mb = mb < 0 ? 0 : (mb > hi ? hi : mb);
+    double2 *pr = rowp_ptr(b, par), *pc = colp_ptr(b, par);
+    const double2 *base = (rows ? pr : pc) + ((size_t)(mb * T + q) * T) * VEC_TILE_MAX + e;
+    double2 v[TP];
+#pragma unroll
+    for (int k = 0; k < TP; ++k) v[k] = ld_nt(base + (size_t)(k < T ? k : T - 1) * VEC_TILE_MAX);
+    double zx = 0.0, zy = 0.0;
+#pragma unroll
+    for (int k = 0; k < TP; ++k) {
+        zx += k < T ? v[k].x : 0.0;
+        zy += k < T ? v[k].y : 0.0;
     }
-    return u;
+    return valid ? make_double2(zx, zy) : make_double2(0.0, 0.0);
 }
 
+// Where (if anywhere) a launch's completion writes a checkpoint: the values
+// are read from the descriptor at kernel entry, before the tile loads, so no
+// later wait has to include the tile stream.
+struct CkptTarget {
+    double2 *slot;  // checkpoint row for this launch's completed step, or null
+};
+
+__device__ __forceinline__ CkptTarget ckpt_target(const VecBuffers &b, const VecLaunch &L,
+                                                  const CallDesc *d) {
+    double *ck = d->ckpt;
+    const int64_t row = d->chunk_ckpt_row[L.off + L.comp.step_delta + 1];
+    CkptTarget t{nullptr};
+    if (ck && is_end(L.comp.kind) && row >= 0)
+        t.slot = reinterpret_cast<double2 *>(ck) + (size_t)row * (size_t)(b.lmax + 1) * b.n;
+    return t;
+}
+
+// Store the completed state of one entry (owner workgroup only) and, at the
+// end of a step that is a checkpoint, c into the caller's checkpoint buffer.
+__device__ __forceinline__ void store_state(const VecBuffers &b, const VecLaunch &L,
+                                            const CkptTarget &ct, size_t gi, double2 c,
+                                            double2 acc, double2 u) {
+    const int par = L.parity;
+    st_nt(st_ptr(b, par ^ 1, 0) + gi, c);
+    st_nt(st_ptr(b, par ^ 1, 1) + gi, acc);
+    st_nt(st_ptr(b, par ^ 1, 2) + gi, u);
+    if (ct.slot) st_global(ct.slot + gi, c);
+}
+
+template <int TP>
 __global__ __launch_bounds__(VEC_THREADS) void vec_tiles_kernel(VecBuffers b, VecLaunch L) {
-    const int T = b.T, n = b.n;
+    // TP == T for T <= 8, so the tile decode divides by compile-time constants.
+    const int T = TP <= 8 ? TP : b.T, n = b.n;
     const int ntiles = b.lmax * T * T;
     const int w = blockIdx.x;
-    const int tile = (int)split_start(ntiles, 8, w & 7) + (w >> 3);
+    const int xcd = w & 7, per = ntiles >> 3, extra = ntiles & 7;
+    const int tile = xcd * per + (xcd < extra ? xcd : extra) + (w >> 3);  // Sec. 4.1 split over XCDs
     const int l = tile / (T * T), rem = tile - l * T * T, i = rem / T, j = rem - i * T;
-    const int r0 = (int)split_start(n, T, i), RA = (int)split_len(n, T, i);
-    const int c0 = (int)split_start(n, T, j), RB = (int)split_len(n, T, j);
+    const int r0 = b.seg[i], RA = b.seg[i + 1] - r0;
+    const int c0 = b.seg[j], RB = b.seg[j + 1] - c0;
 
     __shared__ double2 uA[VEC_TILE_MAX], uB[VEC_TILE_MAX];
+    __shared__ double2 zc[2 * VEC_TILE_MAX];
     __shared__ double2 cpart[VEC_THREADS / 64][VEC_TILE_MAX];
+    __shared__ double2 rpart[VEC_THREADS / 64][4][16];
 
     const CallDesc *d = b.desc;
-    const double dt = d->dt;
-    int64_t step;
-    const double F = field_of(d, L, step);
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
+    const int par = L.parity;
 
-    // Issue this wave's tile loads first; they overlap the prologue.
+    // ---- prologue loads: entry pe of segment A = (l, i) or B = (l+1, j).
+    // Threads t and t+256 share an entry: the first loads the row partials
+    // and the state, the second the column partials.
+    const int pe = t & 255, half = __builtin_amdgcn_readfirstlane(t >> 8);  // wave-uniform
+    const bool isB = pe >= VEC_TILE_MAX;
+    const int e = pe & (VEC_TILE_MAX - 1);
+    const int m = isB ? l + 1 : l, q = isB ? j : i, len = isB ? RB : RA, s0 = isB ? c0 : r0;
+    const int ec = e < len ? e : len - 1;
+    const size_t gi = (size_t)m * n + s0 + ec;
+    const double2 zpart = sum_partials<TP>(b, par, half == 0, m, q, ec);
+    const double2 c_in = ld_nt(st_ptr(b, par, 0) + gi), acc_in = ld_nt(st_ptr(b, par, 1) + gi);
+    const double2 u_in = ld_nt(st_ptr(b, par, 2) + gi);
+    const double E0 = __builtin_nontemporal_load(b.en + gi);
+    const double F = field_of(d, L), dt = d->dt;
+    const CkptTarget ct = ckpt_target(b, L, d);
+
+    // ---- tile loads. Tiles are stored blocked with a 128-double row pitch,
+    // zero-padded beyond RB columns: lane L reads columns 2L, 2L+1 of a row
+    // (16 B per lane, 1 KB per wave and row).
     const int a0 = wv * 16;
-    const double *Drow = b.dip + ((size_t)l * n + r0) * b.ld + c0;
-    double dv0[16], dv1[16];
+    const double2 *Dt = reinterpret_cast<const double2 *>(b.dip) +
+                        (size_t)tile * (VEC_TILE_MAX * VEC_TILE_MAX / 2) + lane;
+    // Rows past RA re-read row RA-1 (an L1 hit) and are zeroed afterwards, so
+    // the loads are unconditional and the prologue can wait for its own loads
+    // while these are still in flight.
+    double2 dv[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const int a = a0 + r;
-        const double *p = Drow + (size_t)a * b.ld;
-        dv0[r] = (a < RA && lane < RB) ? p[lane] : 0.0;
-        dv1[r] = (a < RA && lane + 64 < RB) ? p[lane + 64] : 0.0;
+        const int a = a0 + r < RA ? a0 + r : RA - 1;
+        dv[r] = Dt[(size_t)a * (VEC_TILE_MAX / 2)];
     }
 
-    // Prologue: complete the previous product for segments A = (l, i), B = (l+1, j).
-    if (t < 2 * VEC_TILE_MAX) {
-        const bool isB = t >= VEC_TILE_MAX;
-        const int e = t & (VEC_TILE_MAX - 1);
-        const int m = isB ? l + 1 : l, q = isB ? j : i, len = isB ? RB : RA, s0 = isB ? c0 : r0;
+    // ---- completion of the previous product (overlaps the tile stream).
+    if (half == 1) zc[pe] = zpart;
+    lds_barrier();
+    if (half == 0) {
         double2 u = make_double2(0.0, 0.0);
         if (e < len) {
+            double2 c = c_in, acc = acc_in;
+            u = u_in;
+            apply_completion(L.comp, dt, F, E0, cadd(zpart, zc[pe]), c, acc, u);
             const bool owner = isB ? (l == b.lmax - 1 && i == 0) : (j == 0);
-            u = complete_entry(b, L, d, dt, F, step, m, q, e, s0, owner);
+            if (owner) store_state(b, L, ct, gi, c, acc, u);
         }
         (isB ? uB : uA)[e] = u;
     }
-    __syncthreads();
+    lds_barrier();
 
-    // Tile products.
-    const double2 ub0 = uB[lane], ub1 = uB[lane + 64];
+    // ---- tile products.
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (a0 + r >= RA) dv[r] = make_double2(0.0, 0.0);
+    const double2 ub0 = uB[2 * lane], ub1 = uB[2 * lane + 1];
     double2 cp0 = make_double2(0.0, 0.0), cp1 = make_double2(0.0, 0.0);
     double tr[16], ti[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const double2 ua = uA[(a0 + r) & (VEC_TILE_MAX - 1)];
-        cp0.x = fma(dv0[r], ua.x, cp0.x);
-        cp0.y = fma(dv0[r], ua.y, cp0.y);
-        cp1.x = fma(dv1[r], ua.x, cp1.x);
-        cp1.y = fma(dv1[r], ua.y, cp1.y);
-        tr[r] = fma(dv1[r], ub1.x, dv0[r] * ub0.x);
-        ti[r] = fma(dv1[r], ub1.y, dv0[r] * ub0.y);
+        const double2 ua = uA[a0 + r];
+        cp0.x = fma(dv[r].x, ua.x, cp0.x);
+        cp0.y = fma(dv[r].x, ua.y, cp0.y);
+        cp1.x = fma(dv[r].y, ua.x, cp1.x);
+        cp1.y = fma(dv[r].y, ua.y, cp1.y);
+        tr[r] = fma(dv[r].y, ub1.x, dv[r].x * ub0.x);
+        ti[r] = fma(dv[r].y, ub1.y, dv[r].x * ub0.y);
     }
-    // Transpose-reduce the 16 row partials over the 64 lanes: after the
-    // xor-8/4/2/1 exchanges lane L holds row (L & 15) summed over its 16-lane
-    // group; xor-16/32 finish the sum.
-#pragma unroll
-    for (int h = 8; h >= 1; h >>= 1) {
-        const bool up = (lane & h) != 0;
-#pragma unroll
-        for (int k = 0; k < h; ++k) {
-            double sr = up ? tr[k] : tr[k + h], si = up ? ti[k] : ti[k + h];
-            double kr = up ? tr[k + h] : tr[k], ki = up ? ti[k + h] : ti[k];
-            tr[k] = kr + __shfl_xor(sr, h);
-            ti[k] = ki + __shfl_xor(si, h);
-        }
-    }
-    double rs = tr[0] + __shfl_xor(tr[0], 16);
-    double is = ti[0] + __shfl_xor(ti[0], 16);
-    rs += __shfl_xor(rs, 32);
-    is += __shfl_xor(is, 32);
+    // Transpose-reduce the 16 row partials over each 16-lane group: after the
+    // xor-8/4/2/1 exchanges lane L holds row (L & 15) summed over its group;
+    // the four groups are added through LDS below.
+    butterfly<8>(tr, ti, lane);
+    butterfly<4>(tr, ti, lane);
+    butterfly<2>(tr, ti, lane);
+    butterfly<1>(tr, ti, lane);
+    rpart[wv][lane >> 4][lane & 15] = make_double2(tr[0], ti[0]);
+    cpart[wv][2 * lane] = cp0;
+    cpart[wv][2 * lane + 1] = cp1;
+    lds_barrier();
 
-    const int npar = L.parity ^ 1;
-    {
-        const int a = a0 + (lane & 15);
-        if (lane < 16 && a < RA) {
-            double2 *rp = b.rowp[npar] + ((size_t)(l * T + i) * T + j) * VEC_TILE_MAX;
-            rp[a] = make_double2(rs, is);
-        }
-    }
-    cpart[wv][lane] = cp0;
-    cpart[wv][lane + 64] = cp1;
-    __syncthreads();
-    if (t < VEC_TILE_MAX && t < RB) {
-        double2 s = cpart[0][t];
+    const int npar = par ^ 1;
+    if (t < VEC_TILE_MAX) {
+        if (t < RB) {  // column partial of column t: sum over the 8 waves' rows
+            double2 s = cpart[0][t];
 #pragma unroll
-        for (int k = 1; k < VEC_THREADS / 64; ++k) s = cadd(s, cpart[k][t]);
-        double2 *cpo = b.colp[npar] + ((size_t)(l * T + j) * T + i) * VEC_TILE_MAX;
-        cpo[t] = s;
+            for (int k = 1; k < VEC_THREADS / 64; ++k) s = cadd(s, cpart[k][t]);
+            double2 *cpo = colp_ptr(b, npar) + ((size_t)(l * T + j) * T + i) * VEC_TILE_MAX;
+            st_nt(cpo + t, s);
+        }
+    } else if (t < 2 * VEC_TILE_MAX) {  // row partial of row a: sum over the 4 lane groups
+        const int a = t - VEC_TILE_MAX, rw = a >> 4, rr = a & 15;
+        if (a < RA) {
+            double2 s = cadd(cadd(rpart[rw][0][rr], rpart[rw][1][rr]), cadd(rpart[rw][2][rr], rpart[rw][3][rr]));
+            double2 *rp = rowp_ptr(b, npar) + ((size_t)(l * T + i) * T + j) * VEC_TILE_MAX;
+            st_nt(rp + a, s);
+        }
     }
 }
 
-// Completion only (no products): the final completion of a propagation, and
-// every launch when lmax == 0 (no dipole blocks, z == 0).
+// Completion only (no products): the final completion of a propagation,
+// every launch when lmax == 0 (no dipole blocks, z == 0), and the single
+// product of tdse_hmul (kind CK_HMUL: y = E o u + F z).
+template <int TP>
 __global__ __launch_bounds__(VEC_TILE_MAX) void vec_combine_kernel(VecBuffers b, VecLaunch L) {
     const int T = b.T;
     const int seg = blockIdx.x;
@@ -240,19 +340,22 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_combine_kernel(VecBuffers b,
     const int e = threadIdx.x;
     if (e >= len) return;
     const CallDesc *d = b.desc;
-    int64_t step;
-    const double F = field_of(d, L, step);
-    size_t gi = (size_t)m * b.n + s0 + e;
-    if (L.comp.kind < 0) {  // hmul: y = E0 u + F z
-        double2 z = reduce_z(b, L.parity, m, q, e);
-        double2 u = b.st[L.parity][2][gi];
-        double yr = fma(F, z.x, b.en[gi] * u.x), yi = fma(F, z.y, b.en[gi] * u.y);
+    const int par = L.parity;
+    const double F = field_of(d, L);
+    const size_t gi = (size_t)m * b.n + s0 + e;
+    double2 z = make_double2(0.0, 0.0);
+    if (b.lmax > 0)
+        z = cadd(sum_partials<TP>(b, par, true, m, q, e), sum_partials<TP>(b, par, false, m, q, e));
+    double2 c = ld_nt(st_ptr(b, par, 0) + gi), acc = ld_nt(st_ptr(b, par, 1) + gi), u = ld_nt(st_ptr(b, par, 2) + gi);
+    const double E0 = b.en[gi];
+    if (L.comp.kind == CK_HMUL) {
+        double yr = fma(F, z.x, E0 * u.x), yi = fma(F, z.y, E0 * u.y);
         reinterpret_cast<double2 *>(L.out)[gi] = make_double2(yr, yi);
         return;
     }
-    double2 u = complete_entry(b, L, d, d->dt, F, step, m, q, e, s0, true);
-    (void)u;
-    if (L.finish) reinterpret_cast<double2 *>(L.out)[gi] = b.st[L.parity ^ 1][0][gi];
+    apply_completion(L.comp, d->dt, F, E0, z, c, acc, u);
+    store_state(b, L, ckpt_target(b, L, d), gi, c, acc, u);
+    if (L.finish) reinterpret_cast<double2 *>(L.out)[gi] = c;
 }
 
 __global__ void vec_start_kernel(VecBuffers b, int par, const double2 *c0, int taylor) {
@@ -277,25 +380,92 @@ __global__ void vec_start_kernel(VecBuffers b, int par, const double2 *c0, int t
     }
 }
 
-__global__ void set_desc_kernel(CallDesc *d, CallDesc v) { *d = v; }
-__global__ void set_desc_base_kernel(CallDesc *d, int64_t base) { d->base_step = base; }
+// Re-layout of the caller's row-major blocks [lmax][n][n] into tiles
+// [lmax][T][T][VEC_TILE_MAX][VEC_TILE_MAX], zero outside each tile's extent.
+__global__ void vec_layout_kernel(const double *src, double *dst, int lmax, int n, int T) {
+    const size_t tile_elems = (size_t)VEC_TILE_MAX * VEC_TILE_MAX;
+    const size_t total = (size_t)lmax * T * T * tile_elems;
+    for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (size_t)gridDim.x * blockDim.x) {
+        const size_t tile = g / tile_elems, w = g - tile * tile_elems;
+        const int a = (int)(w / VEC_TILE_MAX), bcol = (int)(w % VEC_TILE_MAX);
+        const int l = (int)(tile / (T * T)), rem = (int)(tile % (T * T)), i = rem / T, j = rem % T;
+        const int RA = (int)split_len(n, T, i), RB = (int)split_len(n, T, j);
+        double v = 0.0;
+        if (a < RA && bcol < RB) {
+            const int r = (int)split_start(n, T, i) + a, c = (int)split_start(n, T, j) + bcol;
+            v = src[((size_t)l * n + r) * n + c];
+        }
+        dst[g] = v;
+    }
+}
+
+hipError_t vec_layout(const double *src, double *dst, int lmax, int n, int T, hipStream_t s) {
+    hipLaunchKernelGGL(vec_layout_kernel, dim3(1024), dim3(256), 0, s, src, dst, lmax, n, T);
+    return hipGetLastError();
+}
+
+__global__ void set_desc_kernel(CallDesc *d, CallDesc v) {
+    d->base_step = v.base_step;
+    d->nsteps = v.nsteps;
+    d->field = v.field;
+    d->ckpt = v.ckpt;
+    d->ckpt_every = v.ckpt_every;
+    d->dt = v.dt;
+    d->slots = v.slots;
+}
+
+// Stage the field samples of steps base-1 .. base+CHUNK_STEPS-1.
+__global__ void chunk_begin_kernel(CallDesc *d, int64_t base) {
+    const int S = d->slots;
+    const int64_t nst = d->nsteps;
+    const double *f = d->field;
+    for (int x = threadIdx.x; x < (CHUNK_STEPS + 1) * S; x += blockDim.x) {
+        const int64_t step = base - 1 + x / S;
+        d->chunk_field[x] = (step >= 0 && step < nst) ? f[step * S + x % S] : 0.0;
+    }
+    const int64_t K = d->ckpt_every;
+    for (int x = threadIdx.x; x <= CHUNK_STEPS; x += blockDim.x) {
+        const int64_t ends = base + x;  // a completion at chunk offset x-1 ends this step
+        d->chunk_ckpt_row[x] = (ends <= nst && ends % K == 0) ? ends / K : -1;
+    }
+    if (threadIdx.x == 0) d->base_step = base;
+}
 
 hipError_t set_desc(CallDesc *d, const CallDesc &v, hipStream_t s) {
     hipLaunchKernelGGL(set_desc_kernel, dim3(1), dim3(1), 0, s, d, v);
     return hipGetLastError();
 }
-hipError_t set_desc_base(CallDesc *d, int64_t base, hipStream_t s) {
-    hipLaunchKernelGGL(set_desc_base_kernel, dim3(1), dim3(1), 0, s, d, base);
+hipError_t chunk_begin(CallDesc *d, int64_t base, hipStream_t s) {
+    hipLaunchKernelGGL(chunk_begin_kernel, dim3(1), dim3(256), 0, s, d, base);
     return hipGetLastError();
 }
 
+// Compiled bounds on the number of tiles per block dimension.
+#define TDSE_TP_DISPATCH(T, KERNEL, ...)                                        \
+    do {                                                                        \
+        switch (T) {                                                            \
+        case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;              \
+        case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;              \
+        case 3: hipLaunchKernelGGL(KERNEL<3>, __VA_ARGS__); break;              \
+        case 4: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;              \
+        case 5: hipLaunchKernelGGL(KERNEL<5>, __VA_ARGS__); break;              \
+        case 6: hipLaunchKernelGGL(KERNEL<6>, __VA_ARGS__); break;              \
+        case 7: hipLaunchKernelGGL(KERNEL<7>, __VA_ARGS__); break;              \
+        case 8: hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__); break;              \
+        default:                                                                \
+            if ((T) <= 16) hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__);         \
+            else return hipErrorInvalidValue;                                   \
+        }                                                                       \
+    } while (0)
+
 hipError_t vec_launch_tiles(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {
     const int ntiles = b.lmax * b.T * b.T;
-    hipLaunchKernelGGL(vec_tiles_kernel, dim3(ntiles), dim3(VEC_THREADS), 0, s, b, l);
+    TDSE_TP_DISPATCH(b.T, vec_tiles_kernel, dim3(ntiles), dim3(VEC_THREADS), 0, s, b, l);
     return hipGetLastError();
 }
 hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {
-    hipLaunchKernelGGL(vec_combine_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s, b, l);
+    TDSE_TP_DISPATCH(b.T, vec_combine_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s, b, l);
     return hipGetLastError();
 }
 hipError_t vec_launch_start(const VecBuffers &b, int32_t parity, const double *c0, int32_t method,
