@@ -202,6 +202,135 @@ static tdse_status vec_alloc(tdse_plan p) {
     return TDSE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched path.
+
+// Tile shape for a batched plan: TN from the padded column count, TM the
+// largest of 128/64/32 that still gives >= 256 workgroups (one per CU).
+// TDSE_TILE="TMxTN" overrides (the autotuner writes the same choice).
+static void bat_pick_tile(int lmax, int n, int batch, const TileChoice *force, int *tm, int *tn) {
+    const int ldu = ((2 * batch + 31) / 32) * 32;
+    *tn = ldu % 128 == 0 ? 128 : (ldu % 64 == 0 ? 64 : 32);
+    *tm = 32;
+    for (int cand : {128, 64, 32}) {
+        const int np = ((n + cand - 1) / cand) * cand;
+        if ((long)(lmax + 1) * (np / cand) * (ldu / *tn) >= 256) {
+            *tm = cand;
+            break;
+        }
+    }
+    TileChoice tc{0, *tm, *tn};
+    if (force) tc = *force;
+    else tune_lookup(lmax, n, batch, &tc);
+    if (tc.tm > 0) *tm = tc.tm;
+    if (tc.tn > 0) *tn = tc.tn;
+}
+
+static tdse_status bat_create(tdse_plan p, const double *energies, const double *dipole,
+                              hipStream_t s, const TileChoice *force) {
+    BatBuffers &b = p->bb;
+    b.lmax = p->lmax;
+    b.n = p->n;
+    b.batch = p->batch;
+    bat_pick_tile(p->lmax, p->n, p->batch, force, &b.tm, &b.tn);
+    b.np = ((p->n + b.tm - 1) / b.tm) * b.tm;
+    b.ldu = ((2 * p->batch + b.tn - 1) / b.tn) * b.tn;
+    const size_t ns_pad = (size_t)(p->lmax + 1) * b.np;
+    const size_t dsz = (size_t)p->lmax * b.np * b.np;
+    const size_t usz = ns_pad * b.ldu;
+    const size_t total = ns_pad + 2 * dsz + 4 * usz;
+    double *mem = nullptr;
+    if (hipMalloc(&mem, total * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(TDSE_E_NOMEM, "hipMalloc of the batched plan failed");
+    }
+    p->bat_mem = mem;
+    b.en = mem;
+    b.d = b.en + ns_pad;
+    b.dT = b.d + dsz;
+    b.u[0] = b.dT + dsz;
+    b.u[1] = b.u[0] + usz;
+    b.c = b.u[1] + usz;
+    b.acc = b.c + usz;
+    const size_t ns = (size_t)(p->lmax + 1) * p->n;
+    double *stage_en = nullptr, *stage_d = nullptr;
+    hipError_t e = hipMalloc(&stage_en, ns * sizeof(double));
+    if (e == hipSuccess && p->lmax > 0) e = hipMalloc(&stage_d, (size_t)p->lmax * p->n * p->n * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpyAsync(stage_en, energies, ns * sizeof(double), hipMemcpyDefault, s);
+    if (e == hipSuccess && p->lmax > 0)
+        e = hipMemcpyAsync(stage_d, dipole, (size_t)p->lmax * p->n * p->n * sizeof(double), hipMemcpyDefault, s);
+    if (e == hipSuccess) e = hipMemsetAsync(b.u[0], 0, 4 * usz * sizeof(double), s);
+    if (e == hipSuccess) e = bat_layout(stage_d, stage_en, b, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (stage_en) (void)hipFree(stage_en);
+    if (stage_d) (void)hipFree(stage_d);
+    if (e != hipSuccess) return hip_fail(e, "batched plan setup");
+    return TDSE_OK;
+}
+
+static void bat_schedule(tdse_method m, int order, std::vector<BatLaunch> &out) {
+    out.clear();
+    if (m == TDSE_RK4) {
+        //            kind        slot first parity w_acc      a_next
+        out.push_back({CK_RK4_MID, 0, 1, 0, 1.0 / 6.0, 0.5, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr});
+        out.push_back({CK_RK4_MID, 1, 0, 0, 2.0 / 6.0, 0.5, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr});
+        out.push_back({CK_RK4_MID, 1, 0, 0, 2.0 / 6.0, 1.0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr});
+        out.push_back({CK_RK4_END, 2, 0, 0, 1.0 / 6.0, 0.0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr});
+    } else {
+        for (int t = 1; t <= order; ++t)
+            out.push_back({t == order ? CK_TAY_END : CK_TAY_MID, 0, t == 1 ? 1 : 0, 0, 0.0, 1.0 / t, 0, 0, 0,
+                           0, 0, 0, 0, nullptr, nullptr});
+    }
+}
+
+static tdse_status bat_propagate(tdse_plan p, tdse_method m, int order, double dt, int64_t nsteps,
+                                 const double *field, const double *c0, double *cT, double *ckpt,
+                                 int32_t K, hipStream_t s) {
+    BatBuffers b = p->bb;
+    b.field = field;
+    TDSE_HIP(bat_pack(b, c0, m == TDSE_TAYLOR ? 1 : 0, s));
+    const int rows = ckpt ? (int)(nsteps / K + 1) : 0;
+    if (ckpt) TDSE_HIP(bat_ckpt0(b, c0, ckpt, rows, s));
+    std::vector<BatLaunch> sched;
+    bat_schedule(m, order, sched);
+    int parity = 0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        for (BatLaunch L : sched) {
+            L.parity = parity;
+            L.dt = dt;
+            L.step = k;
+            L.nsteps = nsteps;
+            L.slots = m == TDSE_RK4 ? 3 : 1;
+            if (ckpt && (k + 1) % K == 0) {
+                L.ckpt = ckpt;
+                L.ckpt_row = (int32_t)((k + 1) / K);
+                L.ckpt_rows = rows;
+            }
+            TDSE_HIP(bat_launch_stage(b, L, s));
+            parity ^= 1;
+        }
+    }
+    // the current c lives in b.c whatever the parity
+    TDSE_HIP(bat_unpack(b, cT, s));
+    return TDSE_OK;
+}
+
+static tdse_status bat_hmul(tdse_plan p, const double *fields, const double *u, double *y, hipStream_t s) {
+    BatBuffers b = p->bb;
+    b.field = fields;
+    TDSE_HIP(bat_pack(b, u, 0, s));
+    BatLaunch L{};
+    L.kind = CK_HMUL;
+    L.parity = 0;
+    L.dt = 1.0;
+    L.step = 0;
+    L.nsteps = 1;
+    L.slots = 1;
+    L.out = y;
+    TDSE_HIP(bat_launch_stage(b, L, s));
+    return TDSE_OK;
+}
+
 }  // namespace tdse
 
 using namespace tdse;
@@ -218,16 +347,40 @@ tdse_status tdse_create(tdse_plan *out, const double *energies, const double *di
     std::string why;
     tdse_status st = validate_create(out, energies, dipole, lmax, n, batch, &why);
     if (st != TDSE_OK) return fail(st, why);
-    if (batch != 1) return fail(TDSE_E_UNSUPPORTED, "batch > 1 is not built yet");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return create_plan(out, energies, dipole, lmax, n, batch, reinterpret_cast<hipStream_t>(stream), nullptr);
+}
+
+}  // extern "C"
+
+namespace tdse {
+
+tdse_status create_plan(tdse_plan *out, const double *energies, const double *dipole, int32_t lmax,
+                        int32_t n, int32_t batch, hipStream_t s, const TileChoice *force) {
+    tdse_status st;
     tdse_plan p = new (std::nothrow) tdse_plan_s();
     if (!p) return fail(TDSE_E_NOMEM, "host allocation failed");
     p->lmax = lmax;
     p->n = n;
     p->batch = batch;
     TDSE_HIP(hipGetDevice(&p->device));
+    if (batch > 1) {
+        st = bat_create(p, energies, dipole, s, force);
+        if (st != TDSE_OK) {
+            std::string msg = g_last_error;
+            tdse_destroy(p);
+            return fail(st, msg);
+        }
+        *out = p;
+        return TDSE_OK;
+    }
     p->ld = VEC_TILE_MAX;
     p->T = (n + VEC_TILE_MAX - 1) / VEC_TILE_MAX;
+    {
+        TileChoice tc{0, 0, 0};
+        if (force) tc = *force;
+        else tune_lookup(lmax, n, 1, &tc);
+        if (tc.T >= p->T && tc.T <= n) p->T = tc.T;
+    }
     if (p->T > 16) {
         delete p;
         return fail(TDSE_E_UNSUPPORTED, "n > 2048 states per partial wave is not supported");
@@ -265,6 +418,10 @@ tdse_status tdse_create(tdse_plan *out, const double *energies, const double *di
     return TDSE_OK;
 }
 
+}  // namespace tdse
+
+extern "C" {
+
 tdse_status tdse_destroy(tdse_plan p) {
     clear_error();
     if (!p) return TDSE_OK;
@@ -272,6 +429,7 @@ tdse_status tdse_destroy(tdse_plan p) {
     for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipGraph_t g : p->graph_defs) (void)hipGraphDestroy(g);
     if (p->scratch) (void)hipFree(p->scratch);
+    if (p->bat_mem) (void)hipFree(p->bat_mem);
     if (p->dip) (void)hipFree(p->dip);
     if (p->en) (void)hipFree(p->en);
     delete p;
@@ -295,6 +453,7 @@ tdse_status tdse_hmul(tdse_plan p, const double *fields, const double *u, double
         return st;
     if (u == y) return fail(TDSE_E_INVAL, "u and y must not alias");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (p->batch > 1) return bat_hmul(p, fields, u, y, s);
     CallDesc d{};
     d.nsteps = 1;
     d.field = fields;
@@ -331,6 +490,9 @@ tdse_status tdse_propagate(tdse_plan p, tdse_method method, int32_t order, doubl
     if ((st = check_dev(c0, "c0")) || (st = check_dev(cT, "cT"))) return st;
     if (ckpt && (st = check_dev(ckpt, "ckpt"))) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (p->batch > 1)
+        return bat_propagate(p, method, method == TDSE_RK4 ? 4 : order, dt, nsteps, field, c0, cT, ckpt,
+                             ckpt_every, s);
     return vec_propagate(p, method, method == TDSE_RK4 ? 4 : order, dt, nsteps, field, c0, cT, ckpt,
                          ckpt_every, s);
 }
@@ -368,10 +530,5 @@ tdse_status tdse_group_destroy(tdse_group g) {
     return TDSE_OK;
 }
 
-tdse_status tdse_tune(int32_t lmax, int32_t n, int32_t batch, const char *cache_path) {
-    clear_error();
-    (void)lmax; (void)n; (void)batch; (void)cache_path;
-    return fail(TDSE_E_UNSUPPORTED, "tuner not built yet");
-}
 
 }  // extern "C"

@@ -101,6 +101,48 @@ hipError_t chunk_begin(CallDesc *d, int64_t base, hipStream_t s);
 hipError_t vec_layout(const double *src, double *dst, int lmax, int n, int T, hipStream_t s);
 hipError_t set_desc(CallDesc *d, const CallDesc &v, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Batched (batch > 1) matrix-core path.
+struct BatBuffers {
+    double *en;            // [(lmax+1)][np]
+    double *d;             // [lmax][np][np]  D_l row-major, zero-padded
+    double *dT;            // [lmax][np][np]  D_l^T row-major, zero-padded
+    double *u[2];          // [parity][(lmax+1)][np][ldu] stage inputs
+    double *c, *acc;       // [(lmax+1)][np][ldu]
+    const double *field;   // caller [batch][nsteps][S]
+    int32_t lmax, n, np, ldu, batch, tm, tn, pad_;
+};
+
+struct BatLaunch {
+    int32_t kind;          // CompletionKind of this stage's own product
+    int32_t slot, first, parity;
+    double w_acc, a_next, dt;
+    int64_t step, nsteps;
+    int32_t slots, ckpt_row, ckpt_rows, pad_;
+    double *ckpt;          // caller checkpoints [batch][ckpt_rows][2n], or null
+    double *out;           // tdse_hmul output (caller layout)
+};
+
+hipError_t bat_layout(const double *src_dip, const double *src_en, BatBuffers &b, hipStream_t s);
+hipError_t bat_pack(const BatBuffers &b, const double *c0, int taylor, hipStream_t s);
+hipError_t bat_unpack(const BatBuffers &b, double *out, hipStream_t s);
+hipError_t bat_ckpt0(const BatBuffers &b, const double *c0, double *ckpt, int rows, hipStream_t s);
+hipError_t bat_launch_stage(const BatBuffers &b, const BatLaunch &l, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Tile choices (autotuner cache).
+struct TileChoice {
+    int32_t T;        // single-vector path: tiles per block dimension (0 = default)
+    int32_t tm, tn;   // batched path: output tile (0 = default)
+};
+
+// Reads $TDSE_TUNE_CACHE (written by tdse_tune) and $TDSE_TILE; leaves the
+// arguments unchanged when there is no entry for (lmax, n, batch).
+void tune_lookup(int lmax, int n, int batch, TileChoice *tc);
+// Plan creation with an optional forced tile choice (used by the tuner).
+tdse_status create_plan(tdse_plan *out, const double *energies, const double *dipole, int32_t lmax,
+                        int32_t n, int32_t batch, hipStream_t s, const TileChoice *force);
+
 }  // namespace tdse
 
 // ---------------------------------------------------------------------------
@@ -116,6 +158,9 @@ struct tdse_plan_s {
     double *scratch = nullptr;   // one allocation holding states, partials, descriptor
     size_t scratch_bytes = 0;
     tdse::VecBuffers vb{};
+    // batched path
+    tdse::BatBuffers bb{};
+    double *bat_mem = nullptr;
     // captured chunk graphs keyed by (method, order, chunk steps, parity)
     std::map<std::string, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_defs;

@@ -1,0 +1,213 @@
+// Autotuner: times the candidate tile shapes of a (lmax, n, batch) problem on
+// the current device and records the fastest in a small JSON cache, which
+// tdse_create consults through $TDSE_TUNE_CACHE.
+//
+// Cache format (one entry per line, written and read by this file only):
+//   {"arch": "gfx950", "entries": {
+//   "L15_N500_B1": {"T": 4, "tm": 0, "tn": 0, "us_per_step": 29.8},
+//   "L15_N500_B256": {"T": 0, "tm": 128, "tn": 128, "us_per_step": 441.0}
+//   }}
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "tdse_internal.h"
+
+namespace tdse {
+
+static std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "unknown";
+    }
+    std::string a = p.gcnArchName;
+    size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+static std::string key_of(int lmax, int n, int batch) {
+    char k[64];
+    snprintf(k, sizeof k, "L%d_N%d_B%d", lmax, n, batch);
+    return k;
+}
+
+struct CacheEntry {
+    TileChoice tc;
+    double us;
+};
+
+static bool read_cache(const char *path, std::string *arch, std::map<std::string, CacheEntry> *ent) {
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        char *a = strstr(line, "\"arch\": \"");
+        if (a) {
+            a += 9;
+            char *e = strchr(a, '"');
+            if (e) *arch = std::string(a, e - a);
+        }
+        char key[64];
+        CacheEntry ce{};
+        if (sscanf(line, " \"%63[^\"]\": {\"T\": %d, \"tm\": %d, \"tn\": %d, \"us_per_step\": %lf", key,
+                   &ce.tc.T, &ce.tc.tm, &ce.tc.tn, &ce.us) == 5)
+            (*ent)[key] = ce;
+    }
+    fclose(f);
+    return true;
+}
+
+static bool write_cache(const char *path, const std::string &arch,
+                        const std::map<std::string, CacheEntry> &ent) {
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    fprintf(f, "{\"arch\": \"%s\", \"entries\": {\n", arch.c_str());
+    size_t i = 0;
+    for (const auto &kv : ent) {
+        fprintf(f, "\"%s\": {\"T\": %d, \"tm\": %d, \"tn\": %d, \"us_per_step\": %.3f}%s\n", kv.first.c_str(),
+                kv.second.tc.T, kv.second.tc.tm, kv.second.tc.tn, kv.second.us,
+                ++i < ent.size() ? "," : "");
+    }
+    fprintf(f, "}}\n");
+    fclose(f);
+    return rename(tmp.c_str(), path) == 0;
+}
+
+void tune_lookup(int lmax, int n, int batch, TileChoice *tc) {
+    const char *force = getenv("TDSE_TILE");
+    if (force && force[0]) {
+        int a = 0, b = 0;
+        if (sscanf(force, "T=%d", &a) == 1 && batch == 1) tc->T = a;
+        else if (sscanf(force, "%dx%d", &a, &b) == 2 && batch > 1) {
+            tc->tm = a;
+            tc->tn = b;
+        }
+        return;
+    }
+    const char *path = getenv("TDSE_TUNE_CACHE");
+    if (!path || !path[0]) return;
+    std::string arch;
+    std::map<std::string, CacheEntry> ent;
+    if (!read_cache(path, &arch, &ent) || arch != arch_name()) return;
+    auto it = ent.find(key_of(lmax, n, batch));
+    if (it == ent.end()) return;
+    if (batch == 1 && it->second.tc.T > 0) tc->T = it->second.tc.T;
+    if (batch > 1 && it->second.tc.tm > 0) {
+        tc->tm = it->second.tc.tm;
+        tc->tn = it->second.tc.tn;
+    }
+}
+
+// Deterministic synthetic inputs of the requested shape.
+static void synth(int lmax, int n, std::vector<double> &en, std::vector<double> &dip) {
+    uint64_t s = 0x9E3779B97F4A7C15ull ^ ((uint64_t)lmax << 32) ^ (uint64_t)n;
+    auto u01 = [&]() {
+        s ^= s << 13;
+        s ^= s >> 7;
+        s ^= s << 17;
+        return (double)(s >> 11) * (1.0 / 9007199254740992.0);
+    };
+    en.resize((size_t)(lmax + 1) * n);
+    for (auto &e : en) e = -0.5 + 3.0 * u01();
+    dip.resize((size_t)lmax * n * n);
+    for (auto &d : dip) d = 0.02 * (u01() - 0.5);
+}
+
+static tdse_status time_choice(int lmax, int n, int batch, const TileChoice &tc, const double *den,
+                               const double *ddip, const double *dfield, double *dc0, double *dcT,
+                               int64_t nsteps, hipStream_t s, double *us_per_step) {
+    tdse_plan p = nullptr;
+    tdse_status st = create_plan(&p, den, ddip, lmax, n, batch, s, &tc);
+    if (st != TDSE_OK) return st;
+    hipEvent_t e0, e1;
+    TDSE_HIP(hipEventCreate(&e0));
+    TDSE_HIP(hipEventCreate(&e1));
+    st = tdse_propagate(p, TDSE_RK4, 0, 1e-3, nsteps, dfield, dc0, dcT, nullptr, 0, s);
+    if (st == TDSE_OK) {
+        (void)hipEventRecord(e0, s);
+        st = tdse_propagate(p, TDSE_RK4, 0, 1e-3, nsteps, dfield, dc0, dcT, nullptr, 0, s);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        *us_per_step = ms * 1e3 / (double)nsteps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    tdse_destroy(p);
+    return st;
+}
+
+}  // namespace tdse
+
+using namespace tdse;
+
+extern "C" tdse_status tdse_tune(int32_t lmax, int32_t n, int32_t batch, const char *cache_path) {
+    clear_error();
+    if (lmax < 0 || n < 1 || batch < 1) return fail(TDSE_E_INVAL, "invalid shape");
+    const char *path = cache_path ? cache_path : getenv("TDSE_TUNE_CACHE");
+    std::vector<double> en, dip;
+    synth(lmax, n, en, dip);
+    const size_t ns = (size_t)(lmax + 1) * n;
+    const int64_t nsteps = batch == 1 ? 256 : 4;
+    std::vector<double> field((size_t)batch * nsteps * 3, 0.05), c0((size_t)batch * 2 * ns, 0.0);
+    for (int b = 0; b < batch; ++b) c0[(size_t)b * 2 * ns] = 1.0;
+    double *den = nullptr, *ddip = nullptr, *dfield = nullptr, *dc0 = nullptr, *dcT = nullptr;
+    hipStream_t s;
+    TDSE_HIP(hipStreamCreate(&s));
+    hipError_t e = hipMalloc(&den, en.size() * 8);
+    if (e == hipSuccess) e = hipMalloc(&ddip, (dip.size() ? dip.size() : 1) * 8);
+    if (e == hipSuccess) e = hipMalloc(&dfield, field.size() * 8);
+    if (e == hipSuccess) e = hipMalloc(&dc0, c0.size() * 8);
+    if (e == hipSuccess) e = hipMalloc(&dcT, c0.size() * 8);
+    if (e == hipSuccess) e = hipMemcpy(den, en.data(), en.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess && dip.size()) e = hipMemcpy(ddip, dip.data(), dip.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dfield, field.data(), field.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dc0, c0.data(), c0.size() * 8, hipMemcpyHostToDevice);
+    tdse_status st = e == hipSuccess ? TDSE_OK : hip_fail(e, "tuner buffers");
+
+    std::vector<TileChoice> cands;
+    if (batch == 1) {
+        const int t0 = (n + VEC_TILE_MAX - 1) / VEC_TILE_MAX;
+        for (int T = t0; T <= t0 + 3 && T <= 16 && T <= n; ++T) cands.push_back({T, 0, 0});
+    } else {
+        const int shapes[7][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}, {64, 32}, {32, 64}, {32, 32}};
+        for (auto &sh : shapes) cands.push_back({0, sh[0], sh[1]});
+    }
+    CacheEntry best{{0, 0, 0}, 1e300};
+    for (const TileChoice &tc : cands) {
+        if (st != TDSE_OK) break;
+        double us = 0.0;
+        tdse_status r = time_choice(lmax, n, batch, tc, den, ddip, dfield, dc0, dcT, nsteps, s, &us);
+        if (r == TDSE_OK && us < best.us) best = {tc, us};
+        if (r == TDSE_E_HIP) st = r;
+    }
+    (void)hipFree(den);
+    (void)hipFree(ddip);
+    (void)hipFree(dfield);
+    (void)hipFree(dc0);
+    (void)hipFree(dcT);
+    (void)hipStreamDestroy(s);
+    if (st != TDSE_OK) return st;
+    if (best.us >= 1e300) return fail(TDSE_E_HIP, "no candidate tile shape ran");
+    if (path && path[0]) {
+        std::string arch = arch_name(), old_arch;
+        std::map<std::string, CacheEntry> ent;
+        if (read_cache(path, &old_arch, &ent) && old_arch != arch) ent.clear();
+        ent[key_of(lmax, n, batch)] = best;
+        if (!write_cache(path, arch, ent)) return fail(TDSE_E_INVAL, std::string("cannot write ") + path);
+    }
+    char msg[128];
+    snprintf(msg, sizeof msg, "best T=%d tm=%d tn=%d: %.3f us per step", best.tc.T, best.tc.tm, best.tc.tn,
+             best.us);
+    set_error(msg);  // informational text for the caller; status is TDSE_OK
+    return TDSE_OK;
+}

@@ -1,0 +1,128 @@
+"""Batched (many pulses, one Hamiltonian) matrix-core path vs the CPU oracle.
+
+Each pulse is compared with the oracle run on that pulse alone. Bar: relative
+L2 error of c(T) <= 1e-10 per pulse; 1e-13 for a single product. Shapes cover
+ragged rows (n not a multiple of the tile), ragged pulse columns (2B not a
+multiple of the tile) and every compiled tile shape.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch  # noqa: F401
+
+import oracle
+from paper_1201_6062_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = 1e-10
+TILES = ["128x128", "128x64", "64x128", "64x64", "64x32", "32x64", "32x32"]
+
+
+def rel_l2(a, b):
+    a, b = np.atleast_2d(a), np.atleast_2d(b)
+    return np.max(np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1))
+
+
+def make_plan(h, batch):
+    from paper_1201_6062_amd.api import Plan
+    return Plan(h.energies, h.dipole, batch=batch)
+
+
+def pulses_field(count, dt, nsteps, seed, method="rk4"):
+    ps = wl.random_pulses(np.random.default_rng(seed), count, ncyc=2.0)
+    ps = [wl.Pulse(p.e0 * 5, p.omega, p.ncyc) for p in ps]  # stronger fields: more coupling in few steps
+    f = wl.rk4_samples if method == "rk4" else wl.taylor_samples
+    return np.stack([f(p, dt, nsteps) for p in ps])
+
+
+@pytest.mark.parametrize("lmax,n,batch", [(1, 1, 2), (2, 3, 2), (3, 50, 4), (2, 130, 3), (0, 9, 5),
+                                          (15, 500, 8)])
+def test_batched_hmul(lmax, n, batch):
+    h = wl.hamiltonian(lmax, n, 11)
+    rng = np.random.default_rng(batch)
+    u = rng.standard_normal((batch, 2 * h.nstates))
+    f = rng.uniform(-1, 1, batch)
+    plan = make_plan(h, batch)
+    y = plan.hmul(f, u).cpu().numpy()
+    for b in range(batch):
+        ref = oracle.hmul(h.energies, h.dipole, f[b], u[b], n=n)
+        assert rel_l2(y[b], ref) <= 1e-13, (b, rel_l2(y[b], ref))
+
+
+@pytest.mark.parametrize("lmax,n,batch,nsteps", [(1, 1, 2, 40), (2, 3, 2, 50), (3, 50, 5, 40),
+                                                 (2, 130, 17, 20), (0, 6, 3, 30), (15, 500, 32, 6)])
+def test_batched_rk4(lmax, n, batch, nsteps):
+    h = wl.hamiltonian(lmax, n, 4)
+    dt = 0.01
+    f = pulses_field(batch, dt, nsteps, 7)
+    c0 = wl.random_state(np.random.default_rng(3), h.nstates, batch)
+    plan = make_plan(h, batch)
+    got = plan.propagate(f, c0, dt, "rk4").cpu().numpy()
+    ref = oracle.rk4(h.energies, h.dipole, dt, f, c0, n=n)
+    assert rel_l2(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("order", [1, 3, 8])
+def test_batched_taylor(order):
+    h = wl.hamiltonian(3, 70, 5)
+    dt, nsteps, batch = 0.02, 25, 6
+    f = pulses_field(batch, dt, nsteps, 9, "taylor")
+    c0 = wl.random_state(np.random.default_rng(order), h.nstates, batch)
+    plan = make_plan(h, batch)
+    got = plan.propagate(f, c0, dt, "taylor", order=order).cpu().numpy()
+    ref = oracle.taylor(h.energies, h.dipole, order, dt, f, c0, n=70)
+    assert rel_l2(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_every_tile_shape(tile, monkeypatch):
+    monkeypatch.setenv("TDSE_TILE", tile)
+    h = wl.hamiltonian(3, 70, 6)
+    dt, nsteps, batch = 0.01, 12, 20
+    f = pulses_field(batch, dt, nsteps, 13)
+    c0 = wl.random_state(np.random.default_rng(5), h.nstates, batch)
+    plan = make_plan(h, batch)
+    got = plan.propagate(f, c0, dt, "rk4").cpu().numpy()
+    ref = oracle.rk4(h.energies, h.dipole, dt, f, c0, n=70)
+    assert rel_l2(got, ref) <= TOL
+
+
+def test_batched_checkpoints():
+    h = wl.hamiltonian(2, 40, 8)
+    dt, nsteps, k, batch = 0.01, 50, 16, 3
+    f = pulses_field(batch, dt, nsteps, 17)
+    c0 = wl.ground_state(2, 40, batch)
+    plan = make_plan(h, batch)
+    cT, ck = plan.propagate(f, c0, dt, "rk4", ckpt_every=k)
+    ck = ck.cpu().numpy()
+    assert ck.shape == (batch, nsteps // k + 1, 2 * h.nstates)
+    for j in range(nsteps // k + 1):
+        ref = oracle.rk4(h.energies, h.dipole, dt, np.ascontiguousarray(f[:, : j * k]), c0)
+        assert rel_l2(ck[:, j], ref) <= TOL, j
+
+
+def test_batched_matches_single_vector_path():
+    """The same pulses through the batch-1 streaming kernels and the batched kernels."""
+    h = wl.hamiltonian(3, 90, 2)
+    dt, nsteps, batch = 0.01, 70, 4
+    f = pulses_field(batch, dt, nsteps, 19)
+    c0 = wl.random_state(np.random.default_rng(8), h.nstates, batch)
+    bat = make_plan(h, batch).propagate(f, c0, dt, "rk4").cpu().numpy()
+    one = make_plan(h, 1)
+    for b in range(batch):
+        got = one.propagate(f[b:b + 1], c0[b:b + 1], dt, "rk4").cpu().numpy()
+        assert rel_l2(got, bat[b:b + 1]) <= 1e-12
+
+
+def test_batched_full_size_short():
+    """256 pulses on the Lmax=15, N=500 Hamiltonian, 3 steps; 6 sampled pulses vs the oracle."""
+    w = wl.batched(256)
+    nst = 3
+    f = np.ascontiguousarray(w.field[:, :nst])
+    plan = make_plan(w.ham, 256)
+    got = plan.propagate(f, w.c0, w.dt, "rk4").cpu().numpy()
+    for b in (0, 1, 77, 128, 200, 255):
+        ref = oracle.rk4(w.ham.energies, w.ham.dipole, w.dt, f[b:b + 1], w.c0[b:b + 1])
+        assert rel_l2(got[b:b + 1], ref) <= TOL, b
