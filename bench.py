@@ -105,6 +105,36 @@ def hbm_diagnostic(torch, steps=64):
             "frac_of_hbm_peak": b / per_launch / 1e9 / HBM_PEAK_GBS}
 
 
+def batched_measure(torch, batch: int = 256, steps: int = 100, tile: str | None = None):
+    """256 pulses on the Lmax=15 N=500 Hamiltonian (RK4 dt=0.005): FP64 matrix-core rate."""
+    from paper_1201_6062_amd import workloads as wl
+    from paper_1201_6062_amd.api import Plan
+    if tile:
+        os.environ["TDSE_TILE"] = tile
+    w = wl.batched(batch)
+    plan = Plan(w.ham.energies, w.ham.dipole, batch=batch)
+    if tile:
+        del os.environ["TDSE_TILE"]
+    f = torch.as_tensor(np.ascontiguousarray(w.field[:, :steps]), device="cuda")
+    c0 = torch.as_tensor(w.c0, device="cuda")
+    plan.propagate(f[:, :2], c0, w.dt, "rk4")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plan.propagate(f, c0, w.dt, "rk4")
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3
+    lmax, n = w.ham.lmax, w.ham.n
+    flop_stage = 8.0 * lmax * n * n * batch
+    tf = flop_stage * 4 * steps / s / 1e12
+    plan.close()
+    return {"workload": f"{batch} pulses, Lmax=15 N=500, RK4 dt=0.005, first {steps} of {w.nsteps} steps",
+            "state_steps_per_s": w.ham.nstates * batch * steps / s,
+            "us_per_stage": s / (4 * steps) * 1e6, "flop_per_stage": flop_stage,
+            "tflops": tf, "frac_of_fp64_peak": tf / FP64_PEAK_TFLOPS}
+
+
 def calibrate_copy(torch, mb: int = 1024, reps: int = 5):
     """Plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
     x = torch.ones(mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
@@ -122,6 +152,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-diag", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true")
+    ap.add_argument("--tile", default=None, help="batched tile TMxTN (tuning experiments)")
     ap.add_argument("--method", choices=["rk4", "taylor"], default="rk4")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--truncate", type=int, default=0,
@@ -140,6 +173,9 @@ def main():
     from paper_1201_6062_amd import workloads as wl
     from paper_1201_6062_amd.api import Plan
 
+    if a.batched_only:
+        print(json.dumps(batched_measure(torch, steps=a.truncate or 100, tile=a.tile)))
+        return
     w = wl.single_large(a.method, 8)
     if a.truncate:
         w.nsteps = min(w.nsteps, a.truncate)
@@ -194,6 +230,8 @@ def main():
     plan.close()
     if not a.no_diag:
         out["hbm_diagnostic"] = hbm_diagnostic(torch)
+    if not a.no_batched:
+        out["batched"] = batched_measure(torch)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

@@ -46,7 +46,7 @@ struct BatTile {
 };
 
 template <int TM, int TN, int KC>
-__global__ __launch_bounds__(256) void bat_stage_kernel(BatBuffers b, BatLaunch L) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void bat_stage_kernel(BatBuffers b, BatLaunch L) {
     using C = BatTile<TM, TN, KC>;
     static_assert(C::A_PER_T >= 1 && C::B_PER_T >= 1, "tile too small for 256 threads");
     const int Np = b.np, ldu = b.ldu, lmax = b.lmax;
@@ -307,18 +307,22 @@ hipError_t bat_ckpt0(const BatBuffers &b, const double *c0, double *ckpt, int ro
 hipError_t bat_launch_stage(const BatBuffers &b, const BatLaunch &l, hipStream_t s) {
     const int ntiles = (b.lmax + 1) * (b.np / b.tm) * (b.ldu / b.tn);
     const dim3 g(ntiles), blk(256);
-#define TDSE_BAT(TM_, TN_)                                                                     \
-    if (b.tm == TM_ && b.tn == TN_) {                                                          \
-        hipLaunchKernelGGL((bat_stage_kernel<TM_, TN_, 16>), g, blk, 0, s, b, l);            \
+#define TDSE_BAT(TM_, TN_, KC_)                                                                \
+    if (b.tm == TM_ && b.tn == TN_ && b.kc == KC_) {                                           \
+        hipLaunchKernelGGL((bat_stage_kernel<TM_, TN_, KC_>), g, blk, 0, s, b, l);           \
         return hipGetLastError();                                                              \
     }
-    TDSE_BAT(128, 128)
-    TDSE_BAT(128, 64)
-    TDSE_BAT(64, 128)
-    TDSE_BAT(64, 64)
-    TDSE_BAT(64, 32)
-    TDSE_BAT(32, 64)
-    TDSE_BAT(32, 32)
+    TDSE_BAT(128, 128, 16)
+    TDSE_BAT(128, 64, 16)
+    TDSE_BAT(64, 128, 16)
+    TDSE_BAT(64, 64, 16)
+    TDSE_BAT(64, 32, 16)
+    TDSE_BAT(32, 64, 16)
+    TDSE_BAT(32, 32, 16)
+    TDSE_BAT(128, 64, 32)
+    TDSE_BAT(64, 128, 32)
+    TDSE_BAT(64, 64, 32)
+    TDSE_BAT(32, 64, 32)
 #undef TDSE_BAT
     return hipErrorInvalidValue;
 }

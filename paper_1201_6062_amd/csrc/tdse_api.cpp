@@ -208,22 +208,26 @@ static tdse_status vec_alloc(tdse_plan p) {
 // Tile shape for a batched plan: TN from the padded column count, TM the
 // largest of 128/64/32 that still gives >= 256 workgroups (one per CU).
 // TDSE_TILE="TMxTN" overrides (the autotuner writes the same choice).
-static void bat_pick_tile(int lmax, int n, int batch, const TileChoice *force, int *tm, int *tn) {
+static void bat_pick_tile(int lmax, int n, int batch, const TileChoice *force, int *tm, int *tn, int *kc) {
+    // Default: 128 x 64 tiles where the grid still fills the chip (two
+    // workgroups per CU measured fastest at Lmax=15, N=500, 256 pulses).
     const int ldu = ((2 * batch + 31) / 32) * 32;
-    *tn = ldu % 128 == 0 ? 128 : (ldu % 64 == 0 ? 64 : 32);
+    *tn = ldu % 64 == 0 ? 64 : 32;
     *tm = 32;
     for (int cand : {128, 64, 32}) {
         const int np = ((n + cand - 1) / cand) * cand;
-        if ((long)(lmax + 1) * (np / cand) * (ldu / *tn) >= 256) {
+        if ((long)(lmax + 1) * (np / cand) * (ldu / *tn) >= 512) {
             *tm = cand;
             break;
         }
     }
-    TileChoice tc{0, *tm, *tn};
+    *kc = 16;
+    TileChoice tc{0, *tm, *tn, *kc};
     if (force) tc = *force;
     else tune_lookup(lmax, n, batch, &tc);
     if (tc.tm > 0) *tm = tc.tm;
     if (tc.tn > 0) *tn = tc.tn;
+    if (tc.kc > 0) *kc = tc.kc;
 }
 
 static tdse_status bat_create(tdse_plan p, const double *energies, const double *dipole,
@@ -232,7 +236,7 @@ static tdse_status bat_create(tdse_plan p, const double *energies, const double 
     b.lmax = p->lmax;
     b.n = p->n;
     b.batch = p->batch;
-    bat_pick_tile(p->lmax, p->n, p->batch, force, &b.tm, &b.tn);
+    bat_pick_tile(p->lmax, p->n, p->batch, force, &b.tm, &b.tn, &b.kc);
     b.np = ((p->n + b.tm - 1) / b.tm) * b.tm;
     b.ldu = ((2 * p->batch + b.tn - 1) / b.tn) * b.tn;
     const size_t ns_pad = (size_t)(p->lmax + 1) * b.np;
@@ -376,7 +380,7 @@ tdse_status create_plan(tdse_plan *out, const double *energies, const double *di
     p->ld = VEC_TILE_MAX;
     p->T = (n + VEC_TILE_MAX - 1) / VEC_TILE_MAX;
     {
-        TileChoice tc{0, 0, 0};
+        TileChoice tc{0, 0, 0, 0};
         if (force) tc = *force;
         else tune_lookup(lmax, n, 1, &tc);
         if (tc.T >= p->T && tc.T <= n) p->T = tc.T;

@@ -110,7 +110,7 @@ struct BatBuffers {
     double *u[2];          // [parity][(lmax+1)][np][ldu] stage inputs
     double *c, *acc;       // [(lmax+1)][np][ldu]
     const double *field;   // caller [batch][nsteps][S]
-    int32_t lmax, n, np, ldu, batch, tm, tn, pad_;
+    int32_t lmax, n, np, ldu, batch, tm, tn, kc;
 };
 
 struct BatLaunch {
@@ -134,6 +134,7 @@ hipError_t bat_launch_stage(const BatBuffers &b, const BatLaunch &l, hipStream_t
 struct TileChoice {
     int32_t T;        // single-vector path: tiles per block dimension (0 = default)
     int32_t tm, tn;   // batched path: output tile (0 = default)
+    int32_t kc;       // batched path: contraction chunk staged per LDS buffer (0 = default)
 };
 
 // Reads $TDSE_TUNE_CACHE (written by tdse_tune) and $TDSE_TILE; leaves the

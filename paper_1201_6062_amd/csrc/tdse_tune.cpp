@@ -4,8 +4,8 @@
 //
 // Cache format (one entry per line, written and read by this file only):
 //   {"arch": "gfx950", "entries": {
-//   "L15_N500_B1": {"T": 4, "tm": 0, "tn": 0, "us_per_step": 29.8},
-//   "L15_N500_B256": {"T": 0, "tm": 128, "tn": 128, "us_per_step": 441.0}
+//   "L15_N500_B1": {"T": 4, "tm": 0, "tn": 0, "kc": 0, "us_per_step": 29.8},
+//   "L15_N500_B256": {"T": 0, "tm": 128, "tn": 64, "kc": 32, "us_per_step": 441.0}
 //   }}
 #include <math.h>
 #include <stdio.h>
@@ -56,8 +56,8 @@ static bool read_cache(const char *path, std::string *arch, std::map<std::string
         }
         char key[64];
         CacheEntry ce{};
-        if (sscanf(line, " \"%63[^\"]\": {\"T\": %d, \"tm\": %d, \"tn\": %d, \"us_per_step\": %lf", key,
-                   &ce.tc.T, &ce.tc.tm, &ce.tc.tn, &ce.us) == 5)
+        if (sscanf(line, " \"%63[^\"]\": {\"T\": %d, \"tm\": %d, \"tn\": %d, \"kc\": %d, \"us_per_step\": %lf",
+                   key, &ce.tc.T, &ce.tc.tm, &ce.tc.tn, &ce.tc.kc, &ce.us) == 6)
             (*ent)[key] = ce;
     }
     fclose(f);
@@ -72,8 +72,8 @@ static bool write_cache(const char *path, const std::string &arch,
     fprintf(f, "{\"arch\": \"%s\", \"entries\": {\n", arch.c_str());
     size_t i = 0;
     for (const auto &kv : ent) {
-        fprintf(f, "\"%s\": {\"T\": %d, \"tm\": %d, \"tn\": %d, \"us_per_step\": %.3f}%s\n", kv.first.c_str(),
-                kv.second.tc.T, kv.second.tc.tm, kv.second.tc.tn, kv.second.us,
+        fprintf(f, "\"%s\": {\"T\": %d, \"tm\": %d, \"tn\": %d, \"kc\": %d, \"us_per_step\": %.3f}%s\n",
+                kv.first.c_str(), kv.second.tc.T, kv.second.tc.tm, kv.second.tc.tn, kv.second.tc.kc, kv.second.us,
                 ++i < ent.size() ? "," : "");
     }
     fprintf(f, "}}\n");
@@ -86,9 +86,14 @@ void tune_lookup(int lmax, int n, int batch, TileChoice *tc) {
     if (force && force[0]) {
         int a = 0, b = 0;
         if (sscanf(force, "T=%d", &a) == 1 && batch == 1) tc->T = a;
-        else if (sscanf(force, "%dx%d", &a, &b) == 2 && batch > 1) {
-            tc->tm = a;
-            tc->tn = b;
+        else if (batch > 1) {
+            int k = 0;
+            int got = sscanf(force, "%dx%dx%d", &a, &b, &k);
+            if (got >= 2) {
+                tc->tm = a;
+                tc->tn = b;
+                tc->kc = got == 3 ? k : 16;
+            }
         }
         return;
     }
@@ -103,6 +108,7 @@ void tune_lookup(int lmax, int n, int batch, TileChoice *tc) {
     if (batch > 1 && it->second.tc.tm > 0) {
         tc->tm = it->second.tc.tm;
         tc->tn = it->second.tc.tn;
+        tc->kc = it->second.tc.kc > 0 ? it->second.tc.kc : 16;
     }
 }
 
@@ -177,12 +183,14 @@ extern "C" tdse_status tdse_tune(int32_t lmax, int32_t n, int32_t batch, const c
     std::vector<TileChoice> cands;
     if (batch == 1) {
         const int t0 = (n + VEC_TILE_MAX - 1) / VEC_TILE_MAX;
-        for (int T = t0; T <= t0 + 3 && T <= 16 && T <= n; ++T) cands.push_back({T, 0, 0});
+        for (int T = t0; T <= t0 + 3 && T <= 16 && T <= n; ++T) cands.push_back({T, 0, 0, 0});
     } else {
-        const int shapes[7][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}, {64, 32}, {32, 64}, {32, 32}};
-        for (auto &sh : shapes) cands.push_back({0, sh[0], sh[1]});
+        const int shapes[11][3] = {{128, 128, 16}, {128, 64, 16}, {64, 128, 16}, {64, 64, 16}, {64, 32, 16},
+                                   {32, 64, 16},   {32, 32, 16},  {128, 64, 32}, {64, 128, 32}, {64, 64, 32},
+                                   {32, 64, 32}};
+        for (auto &sh : shapes) cands.push_back({0, sh[0], sh[1], sh[2]});
     }
-    CacheEntry best{{0, 0, 0}, 1e300};
+    CacheEntry best{{0, 0, 0, 0}, 1e300};
     for (const TileChoice &tc : cands) {
         if (st != TDSE_OK) break;
         double us = 0.0;
