@@ -45,7 +45,13 @@ struct BatTile {
     static constexpr int A_PER_T = A_ELEMS / 2 / THREADS, B_PER_T = B_ELEMS / 2 / THREADS;  // double2 each
 };
 
-template <int TM, int TN, int KC>
+// ADJ = false: forward RK4 / Taylor stage (or a single product).
+// ADJ = true: one stage of the discrete adjoint of an RK4 step, run in
+// reverse: the product input is the co-state kbar of the stage derivative,
+// ubar = i H(F) kbar (since (-iH)^H = iH for real symmetric H), the co-state
+// of c accumulates sum ubar, and the field gradient Im((D kbar)^H u) is
+// reduced per row tile (u = the forward input of the stage).
+template <int TM, int TN, int KC, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void bat_stage_kernel(BatBuffers b, BatLaunch L) {
     using C = BatTile<TM, TN, KC>;
     static_assert(C::A_PER_T >= 1 && C::B_PER_T >= 1, "tile too small for 256 threads");
@@ -147,12 +153,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
         }
     }
 
-    // ---- epilogue: k = -i (E0 u + F z) per complex entry, then the stage update.
+    // ---- epilogue
     const int B = b.batch;
     const int64_t step = L.step;
     const double dt = L.dt;
-    const double *Unext_base = par ? b.u[0] : b.u[1];
-    double *Un = const_cast<double *>(Unext_base);
+    double *Un = par ? b.u[0] : b.u[1];
+    double gsum[C::SN];
+#pragma unroll
+    for (int j = 0; j < C::SN; ++j) gsum[j] = 0.0;
 #pragma unroll
     for (int i = 0; i < C::SM; ++i) {
 #pragma unroll
@@ -169,53 +177,90 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
                 const double E0 = b.en[(size_t)m * Np + row];
                 const double z = acc[i][j][r], zp = bat_xor1(z);
                 const double uo = U[gi], up = bat_xor1(uo);
-                // own component of y = E0 u + F z and of k = -i y:
-                // k_re = y_im, k_im = -y_re
-                const double yre = is_im ? fma(F, zp, E0 * up) : fma(F, z, E0 * uo);
-                const double yim = is_im ? fma(F, z, E0 * uo) : fma(F, zp, E0 * up);
-                const double k = is_im ? -yre : yim;
-                if (L.kind == CK_HMUL) {  // single product y = H u (tdse_hmul)
-                    if (pulse < B && row < b.n)
-                        L.out[(size_t)pulse * 2 * (lmax + 1) * b.n + 2 * ((size_t)m * b.n + row) +
-                              (is_im ? 1 : 0)] = is_im ? yim : yre;
-                    continue;
-                }
-                double c = b.c[gi];
-                double a = b.acc[gi];
-                double unext;
-                switch (L.kind) {
-                case CK_RK4_MID:
-                    a = L.first ? L.w_acc * k : fma(L.w_acc, k, a);
-                    unext = fma(L.a_next * dt, k, c);
-                    b.acc[gi] = a;
-                    break;
-                case CK_RK4_END:
-                    c = fma(dt, fma(L.w_acc, k, a), c);
-                    unext = c;
-                    b.c[gi] = c;
-                    break;
-                case CK_TAY_MID: {
-                    const double tm = L.a_next * dt * k;
-                    a = (L.first ? c : a) + tm;
-                    unext = tm;
-                    b.acc[gi] = a;
-                    break;
-                }
-                default: {  // CK_TAY_END
-                    const double tm = L.a_next * dt * k;
-                    c = (L.first ? c : a) + tm;
-                    unext = c;
-                    b.c[gi] = c;
-                    break;
-                }
-                }
-                Un[gi] = unext;
-                if (L.ckpt && (L.kind == CK_RK4_END || L.kind == CK_TAY_END) && pulse < B && row < b.n) {
-                    // caller layout [B][rows][2 n]
-                    L.ckpt[((size_t)pulse * L.ckpt_rows + L.ckpt_row) * 2 * (size_t)(lmax + 1) * b.n +
-                           2 * ((size_t)m * b.n + row) + (is_im ? 1 : 0)] = c;
+                if constexpr (ADJ) {
+                    // ubar = i (E0 kbar + F w): re = -(E0 kbar_im + F w_im), im = E0 kbar_re + F w_re
+                    const double ub = (is_im ? 1.0 : -1.0) * fma(F, zp, E0 * up);
+                    const double us = L.ustore[gi], usp = bat_xor1(us);
+                    // Im(w^H u) = sum (w_re u_im - w_im u_re)
+                    gsum[j] += (is_im ? -z : z) * usp;
+                    const double lam = b.c[gi];
+                    const double cb = (L.first ? lam : b.acc[gi]) + ub;
+                    if (L.kind == CK_ADJ_MID) {
+                        b.acc[gi] = cb;
+                        Un[gi] = fma(L.p_lam, lam, L.p_ub * ub);
+                    } else {  // CK_ADJ_LAST: cb is the co-state of c at the step's start
+                        b.c[gi] = cb;
+                        Un[gi] = L.p_lam * cb;
+                    }
+                } else {
+                    // own component of y = E0 u + F z and of k = -i y:
+                    // k_re = y_im, k_im = -y_re
+                    const double yre = is_im ? fma(F, zp, E0 * up) : fma(F, z, E0 * uo);
+                    const double yim = is_im ? fma(F, z, E0 * uo) : fma(F, zp, E0 * up);
+                    const double k = is_im ? -yre : yim;
+                    if (L.kind == CK_HMUL) {  // single product y = H u (tdse_hmul)
+                        if (pulse < B && row < b.n)
+                            L.out[(size_t)pulse * 2 * (lmax + 1) * b.n + 2 * ((size_t)m * b.n + row) +
+                                  (is_im ? 1 : 0)] = is_im ? yim : yre;
+                        continue;
+                    }
+                    if (L.ustore) L.ustore[gi] = uo;  // forward recompute for the adjoint
+                    double c = b.c[gi];
+                    double a = b.acc[gi];
+                    double unext;
+                    switch (L.kind) {
+                    case CK_RK4_MID:
+                        a = L.first ? L.w_acc * k : fma(L.w_acc, k, a);
+                        unext = fma(L.a_next * dt, k, c);
+                        b.acc[gi] = a;
+                        break;
+                    case CK_RK4_END:
+                        c = fma(dt, fma(L.w_acc, k, a), c);
+                        unext = c;
+                        b.c[gi] = c;
+                        break;
+                    case CK_TAY_MID: {
+                        const double tm = L.a_next * dt * k;
+                        a = (L.first ? c : a) + tm;
+                        unext = tm;
+                        b.acc[gi] = a;
+                        break;
+                    }
+                    default: {  // CK_TAY_END
+                        const double tm = L.a_next * dt * k;
+                        c = (L.first ? c : a) + tm;
+                        unext = c;
+                        b.c[gi] = c;
+                        break;
+                    }
+                    }
+                    Un[gi] = unext;
+                    if (L.ckpt && (L.kind == CK_RK4_END || L.kind == CK_TAY_END) && pulse < B && row < b.n) {
+                        // caller layout [B][rows][2 n]
+                        L.ckpt[((size_t)pulse * L.ckpt_rows + L.ckpt_row) * 2 * (size_t)(lmax + 1) * b.n +
+                               2 * ((size_t)m * b.n + row) + (is_im ? 1 : 0)] = c;
+                    }
                 }
             }
+        }
+    }
+    if constexpr (ADJ) {
+        // Gradient partial of this row tile for each pulse of the column tile:
+        // rows of one lane (i, r), then the four 16-lane row groups, then the
+        // real/imaginary column pair, then the two row halves of the tile.
+        __shared__ double gred[2][TN];
+#pragma unroll
+        for (int j = 0; j < C::SN; ++j) {
+            double g = gsum[j];
+            g += __shfl_xor(g, 16);
+            g += __shfl_xor(g, 32);
+            g += bat_xor1(g);
+            if (lane < 16) gred[wy][wx * C::WN + j * 16 + lane] = g;
+        }
+        bat_lds_barrier();
+        if (t < TN / 2) {
+            const int pulse = c0 / 2 + t;
+            if (pulse < B) L.gpart[(size_t)(m * RT + rt) * B + pulse] = gred[0][2 * t] + gred[1][2 * t];
         }
     }
 }
@@ -304,12 +349,13 @@ hipError_t bat_ckpt0(const BatBuffers &b, const double *c0, double *ckpt, int ro
     return hipGetLastError();
 }
 
-hipError_t bat_launch_stage(const BatBuffers &b, const BatLaunch &l, hipStream_t s) {
+template <bool ADJ>
+static hipError_t bat_launch(const BatBuffers &b, const BatLaunch &l, hipStream_t s) {
     const int ntiles = (b.lmax + 1) * (b.np / b.tm) * (b.ldu / b.tn);
     const dim3 g(ntiles), blk(256);
 #define TDSE_BAT(TM_, TN_, KC_)                                                                \
     if (b.tm == TM_ && b.tn == TN_ && b.kc == KC_) {                                           \
-        hipLaunchKernelGGL((bat_stage_kernel<TM_, TN_, KC_>), g, blk, 0, s, b, l);           \
+        hipLaunchKernelGGL((bat_stage_kernel<TM_, TN_, KC_, ADJ>), g, blk, 0, s, b, l);      \
         return hipGetLastError();                                                              \
     }
     TDSE_BAT(128, 128, 16)
@@ -325,6 +371,63 @@ hipError_t bat_launch_stage(const BatBuffers &b, const BatLaunch &l, hipStream_t
     TDSE_BAT(32, 64, 32)
 #undef TDSE_BAT
     return hipErrorInvalidValue;
+}
+
+hipError_t bat_launch_stage(const BatBuffers &b, const BatLaunch &l, hipStream_t s) {
+    return bat_launch<false>(b, l, s);
+}
+hipError_t bat_launch_adjoint(const BatBuffers &b, const BatLaunch &l, hipStream_t s) {
+    return bat_launch<true>(b, l, s);
+}
+
+__global__ void bat_pack_strided_kernel(BatBuffers b, const double *src, size_t pulse_stride, double u_scale) {
+    const size_t total = (size_t)(b.lmax + 1) * b.np * b.ldu;
+    for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (size_t)gridDim.x * blockDim.x) {
+        const int col = (int)(g % b.ldu);
+        const size_t rowg = g / b.ldu;
+        const int row = (int)(rowg % b.np), m = (int)(rowg / b.np);
+        const int pulse = col >> 1, comp = col & 1;
+        double v = 0.0;
+        if (pulse < b.batch && row < b.n) v = src[(size_t)pulse * pulse_stride + 2 * ((size_t)m * b.n + row) + comp];
+        b.c[g] = v;
+        b.u[0][g] = u_scale * v;
+        b.acc[g] = 0.0;
+    }
+}
+
+hipError_t bat_pack_strided(const BatBuffers &b, const double *src, size_t pulse_stride, double u_scale,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(bat_pack_strided_kernel, dim3(1024), dim3(256), 0, s, b, src, pulse_stride, u_scale);
+    return hipGetLastError();
+}
+
+// gpart layout for one segment: [step][stage j-1][row tiles][batch];
+// stage 1 -> slot 0, stages 2 and 3 -> slot 1, stage 4 -> slot 2.
+__global__ void bat_reduce_grad_kernel(const double *gpart, int rowtiles, int batch, int64_t k0, int64_t len,
+                                       int64_t nsteps, double *grad) {
+    const int64_t total = (int64_t)batch * len;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int pulse = (int)(g / len);
+        const int64_t kl = g % len;
+        double sj[4];
+        for (int j = 0; j < 4; ++j) {
+            const double *p = gpart + ((size_t)(kl * 4 + j) * rowtiles) * batch + pulse;
+            double acc = 0.0;
+            for (int rt = 0; rt < rowtiles; ++rt) acc += p[(size_t)rt * batch];
+            sj[j] = acc;
+        }
+        double *out = grad + ((size_t)pulse * nsteps + (k0 + kl)) * 3;
+        out[0] = sj[0];
+        out[1] = sj[2] + sj[1];
+        out[2] = sj[3];
+    }
+}
+
+hipError_t bat_reduce_grad(const double *gpart, int rowtiles, int batch, int64_t k0, int64_t len,
+                           int64_t nsteps, double *grad, hipStream_t s) {
+    hipLaunchKernelGGL(bat_reduce_grad_kernel, dim3(64), dim3(256), 0, s, gpart, rowtiles, batch, k0, len, nsteps,
+                       grad);
+    return hipGetLastError();
 }
 
 }  // namespace tdse

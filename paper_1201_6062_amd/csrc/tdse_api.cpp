@@ -335,6 +335,149 @@ static tdse_status bat_hmul(tdse_plan p, const double *fields, const double *u, 
     return TDSE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Discrete adjoint of the batched RK4 map (reverse sweep over checkpointed
+// segments; the forward states inside a segment are recomputed from its
+// checkpoint and the four stage inputs of every step are kept).
+
+static tdse_status adj_workspace(tdse_plan p, int32_t K, bool need_ckpt, int64_t nsteps, double **fwd,
+                                 double **ustore, double **gpart, double **ickpt) {
+    const BatBuffers &b = p->bb;
+    const size_t usz = (size_t)(b.lmax + 1) * b.np * b.ldu;
+    const int rowtiles = (b.lmax + 1) * (b.np / b.tm);
+    const size_t ns = (size_t)(b.lmax + 1) * b.n;
+    const size_t n_fwd = 4 * usz, n_us = (size_t)K * 4 * usz, n_gp = (size_t)K * 4 * rowtiles * b.batch;
+    const size_t n_ck = need_ckpt ? (size_t)b.batch * (size_t)(nsteps / K + 1) * 2 * ns + (size_t)b.batch * 2 * ns : 0;
+    const size_t bytes = (n_fwd + n_us + n_gp + n_ck) * sizeof(double);
+    if (bytes > p->adj_bytes) {
+        if (p->adj_mem) (void)hipFree(p->adj_mem);
+        p->adj_mem = nullptr;
+        p->adj_bytes = 0;
+        if (hipMalloc(&p->adj_mem, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(TDSE_E_NOMEM, "hipMalloc of the adjoint workspace failed");
+        }
+        p->adj_bytes = bytes;
+    }
+    *fwd = p->adj_mem;
+    *ustore = *fwd + n_fwd;
+    *gpart = *ustore + n_us;
+    *ickpt = need_ckpt ? *gpart + n_gp : nullptr;
+    return TDSE_OK;
+}
+
+static tdse_status bat_adjoint(tdse_plan p, double dt, int64_t nsteps, const double *field, const double *c0,
+                               const double *ckpt, int32_t K, const double *lambdaT, double *grad,
+                               double *lambda0, hipStream_t s) {
+    const BatBuffers &pb = p->bb;
+    const size_t ns = (size_t)(pb.lmax + 1) * pb.n;
+    const size_t usz = (size_t)(pb.lmax + 1) * pb.np * pb.ldu;
+    const int rowtiles = (pb.lmax + 1) * (pb.np / pb.tm);
+    const int64_t rows = nsteps / K + 1;
+    double *fwd, *ustore, *gpart, *ickpt;
+    tdse_status st = adj_workspace(p, K, ckpt == nullptr, nsteps, &fwd, &ustore, &gpart, &ickpt);
+    if (st != TDSE_OK) return st;
+    if (!ckpt) {
+        // forward pass writing checkpoints into the workspace (c(T) goes to its tail)
+        double *cT = ickpt + (size_t)pb.batch * rows * 2 * ns;
+        st = bat_propagate(p, TDSE_RK4, 4, dt, nsteps, field, c0, cT, ickpt, K, s);
+        if (st != TDSE_OK) return st;
+        ckpt = ickpt;
+    }
+    // forward-recompute view: same Hamiltonian, its own state buffers
+    BatBuffers fb = pb;
+    fb.field = field;
+    fb.u[0] = fwd;
+    fb.u[1] = fwd + usz;
+    fb.c = fwd + 2 * usz;
+    fb.acc = fwd + 3 * usz;
+    // adjoint state: c = lambda, acc = co-state sum, u = kbar
+    BatBuffers ab = pb;
+    ab.field = field;
+    TDSE_HIP(bat_pack_strided(ab, lambdaT, 2 * ns, dt / 6.0, s));
+    int apar = 0;
+    std::vector<BatLaunch> fsched;
+    bat_schedule(TDSE_RK4, 4, fsched);
+    const int64_t nseg = (nsteps + K - 1) / K;
+    for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+        const int64_t k0 = sg * K, len = nsteps - k0 < K ? nsteps - k0 : K;
+        TDSE_HIP(bat_pack_strided(fb, ckpt + (size_t)sg * 2 * ns, (size_t)rows * 2 * ns, 1.0, s));
+        int fpar = 0;
+        for (int64_t k = k0; k < k0 + len; ++k) {
+            for (int j = 0; j < 4; ++j) {
+                BatLaunch L = fsched[j];
+                L.parity = fpar;
+                L.dt = dt;
+                L.step = k;
+                L.nsteps = nsteps;
+                L.slots = 3;
+                L.ustore = ustore + ((size_t)(k - k0) * 4 + j) * usz;
+                TDSE_HIP(bat_launch_stage(fb, L, s));
+                fpar ^= 1;
+            }
+        }
+        for (int64_t k = k0 + len - 1; k >= k0; --k) {
+            for (int j = 4; j >= 1; --j) {
+                BatLaunch L{};
+                L.kind = j > 1 ? CK_ADJ_MID : CK_ADJ_LAST;
+                L.slot = j == 4 ? 2 : (j == 1 ? 0 : 1);
+                L.first = j == 4 ? 1 : 0;
+                L.parity = apar;
+                L.dt = dt;
+                L.step = k;
+                L.nsteps = nsteps;
+                L.slots = 3;
+                L.ustore = ustore + ((size_t)(k - k0) * 4 + (j - 1)) * usz;
+                L.gpart = gpart + ((size_t)(k - k0) * 4 + (j - 1)) * rowtiles * pb.batch;
+                // next co-state input: kbar_{j-1} = b_{j-1} dt lambda + alpha_j dt ubar_j
+                if (j == 4) { L.p_lam = dt / 3.0; L.p_ub = dt; }
+                else if (j == 3) { L.p_lam = dt / 3.0; L.p_ub = dt / 2.0; }
+                else if (j == 2) { L.p_lam = dt / 6.0; L.p_ub = dt / 2.0; }
+                else { L.p_lam = dt / 6.0; L.p_ub = 0.0; }
+                TDSE_HIP(bat_launch_adjoint(ab, L, s));
+                apar ^= 1;
+            }
+        }
+        TDSE_HIP(bat_reduce_grad(gpart, rowtiles, pb.batch, k0, len, nsteps, grad, s));
+    }
+    if (lambda0) TDSE_HIP(bat_unpack(ab, lambda0, s));
+    return TDSE_OK;
+}
+
+// A batched (matrix-core) plan of batch 1 over the same Hamiltonian, built
+// from a single-vector plan's device copies; used for that plan's adjoint.
+static tdse_status create_batched_twin(tdse_plan p, hipStream_t s) {
+    tdse_plan q = new (std::nothrow) tdse_plan_s();
+    if (!q) return fail(TDSE_E_NOMEM, "host allocation failed");
+    q->lmax = p->lmax;
+    q->n = p->n;
+    q->batch = 1;
+    q->device = p->device;
+    double *rowmajor = nullptr;
+    if (p->lmax > 0) {
+        if (hipMalloc(&rowmajor, (size_t)p->lmax * p->n * p->n * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            delete q;
+            return fail(TDSE_E_NOMEM, "hipMalloc for the adjoint twin plan failed");
+        }
+        hipError_t e = vec_untile(p->dip, rowmajor, p->lmax, p->n, p->T, s);
+        if (e != hipSuccess) {
+            (void)hipFree(rowmajor);
+            delete q;
+            return hip_fail(e, "untile of the dipole");
+        }
+    }
+    tdse_status st = bat_create(q, p->en, rowmajor, s, nullptr);
+    if (rowmajor) (void)hipFree(rowmajor);
+    if (st != TDSE_OK) {
+        std::string msg = g_last_error;
+        tdse_destroy(q);
+        return fail(st, msg);
+    }
+    p->adj_plan = q;
+    return TDSE_OK;
+}
+
 }  // namespace tdse
 
 using namespace tdse;
@@ -434,6 +577,8 @@ tdse_status tdse_destroy(tdse_plan p) {
     for (hipGraph_t g : p->graph_defs) (void)hipGraphDestroy(g);
     if (p->scratch) (void)hipFree(p->scratch);
     if (p->bat_mem) (void)hipFree(p->bat_mem);
+    if (p->adj_mem) (void)hipFree(p->adj_mem);
+    if (p->adj_plan) tdse_destroy(p->adj_plan);
     if (p->dip) (void)hipFree(p->dip);
     if (p->en) (void)hipFree(p->en);
     delete p;
@@ -506,11 +651,27 @@ tdse_status tdse_adjoint(tdse_plan p, tdse_method method, int32_t order, double 
                          int32_t ckpt_every, const double *lambdaT, double *grad_field,
                          double *lambda0, void *stream) {
     clear_error();
-    (void)order; (void)dt; (void)nsteps; (void)field; (void)c0; (void)ckpt; (void)ckpt_every;
-    (void)lambdaT; (void)grad_field; (void)lambda0; (void)stream;
-    if (!p) return fail(TDSE_E_INVAL, "plan is NULL");
+    std::string why;
+    tdse_status st = validate_propagate(p != nullptr, (int)method, method == TDSE_TAYLOR ? order : 4, dt, nsteps,
+                                        true, ckpt_every, &why);
+    if (st != TDSE_OK) return fail(st, why);
     if (method != TDSE_RK4) return fail(TDSE_E_UNSUPPORTED, "the adjoint is implemented for RK4 only");
-    return fail(TDSE_E_UNSUPPORTED, "adjoint not built yet");
+    if (nsteps > 0 && (st = check_dev(field, "field"))) return st;
+    if ((st = check_dev(c0, "c0")) || (st = check_dev(lambdaT, "lambdaT"))) return st;
+    if (nsteps > 0 && (st = check_dev(grad_field, "grad_field"))) return st;
+    if (ckpt && (st = check_dev(ckpt, "ckpt"))) return st;
+    if (lambda0 && (st = check_dev(lambda0, "lambda0"))) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    tdse_plan q = p;
+    if (p->batch == 1) {
+        // batch-1 plans run the adjoint on a batched twin of themselves
+        if (!p->adj_plan) {
+            st = create_batched_twin(p, s);
+            if (st != TDSE_OK) return st;
+        }
+        q = p->adj_plan;
+    }
+    return bat_adjoint(q, dt, nsteps, field, c0, ckpt, ckpt_every, lambdaT, grad_field, lambda0, s);
 }
 
 tdse_status tdse_group_create(tdse_group *out, int32_t count, const tdse_plan *plans, void *stream) {

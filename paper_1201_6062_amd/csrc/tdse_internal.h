@@ -35,6 +35,8 @@ enum CompletionKind : int32_t {
     CK_TAY_MID = 2,   // completed Taylor term m < p
     CK_TAY_END = 3,   // completed Taylor term p (finishes a step)
     CK_HMUL = -1,     // no completion: write y = E o u + F z (single product)
+    CK_ADJ_MID = 4,   // adjoint stage j > 1 of a reversed RK4 step
+    CK_ADJ_LAST = 5,  // adjoint stage 1: finishes the reversed step
 };
 
 struct Completion {
@@ -99,6 +101,7 @@ hipError_t vec_launch_start(const VecBuffers &b, int32_t parity, const double *c
                             hipStream_t s);
 hipError_t chunk_begin(CallDesc *d, int64_t base, hipStream_t s);
 hipError_t vec_layout(const double *src, double *dst, int lmax, int n, int T, hipStream_t s);
+hipError_t vec_untile(const double *tiles, double *dst, int lmax, int n, int T, hipStream_t s);
 hipError_t set_desc(CallDesc *d, const CallDesc &v, hipStream_t s);
 
 // ---------------------------------------------------------------------------
@@ -121,10 +124,23 @@ struct BatLaunch {
     int32_t slots, ckpt_row, ckpt_rows, pad_;
     double *ckpt;          // caller checkpoints [batch][ckpt_rows][2n], or null
     double *out;           // tdse_hmul output (caller layout)
+    // forward recompute: copy this stage's input u to ustore (internal layout)
+    // adjoint: ustore holds the forward input of the stage being reversed
+    double *ustore;
+    double *gpart;         // adjoint: per row-tile gradient partials [row tiles][batch]
+    double p_lam, p_ub;    // adjoint: next input = p_lam * lambda + p_ub * ubar
 };
 
 hipError_t bat_layout(const double *src_dip, const double *src_en, BatBuffers &b, hipStream_t s);
 hipError_t bat_pack(const BatBuffers &b, const double *c0, int taylor, hipStream_t s);
+// c = state, u[0] = u_scale * state, acc = 0, reading the caller layout with
+// pulse_stride doubles between pulses.
+hipError_t bat_pack_strided(const BatBuffers &b, const double *src, size_t pulse_stride, double u_scale,
+                            hipStream_t s);
+hipError_t bat_launch_adjoint(const BatBuffers &b, const BatLaunch &l, hipStream_t s);
+// grad[b][k][slot] for the steps k0 .. k0+len-1 from the partials of one segment
+hipError_t bat_reduce_grad(const double *gpart, int rowtiles, int batch, int64_t k0, int64_t len,
+                           int64_t nsteps, double *grad, hipStream_t s);
 hipError_t bat_unpack(const BatBuffers &b, double *out, hipStream_t s);
 hipError_t bat_ckpt0(const BatBuffers &b, const double *c0, double *ckpt, int rows, hipStream_t s);
 hipError_t bat_launch_stage(const BatBuffers &b, const BatLaunch &l, hipStream_t s);
@@ -162,6 +178,11 @@ struct tdse_plan_s {
     // batched path
     tdse::BatBuffers bb{};
     double *bat_mem = nullptr;
+    // adjoint workspace (allocated on first use): forward-recompute state,
+    // segment store of stage inputs, gradient partials, internal checkpoints
+    double *adj_mem = nullptr;
+    size_t adj_bytes = 0;
+    tdse_plan adj_plan = nullptr;   // batched twin of a batch-1 plan, for the adjoint
     // captured chunk graphs keyed by (method, order, chunk steps, parity)
     std::map<std::string, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_defs;

@@ -400,6 +400,27 @@ __global__ void vec_layout_kernel(const double *src, double *dst, int lmax, int 
     }
 }
 
+// Inverse of vec_layout_kernel: tiles back to row-major [lmax][n][n].
+__global__ void vec_untile_kernel(const double *tiles, double *dst, int lmax, int n, int T) {
+    const size_t total = (size_t)lmax * n * n;
+    for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(g % n);
+        const size_t rg = g / n;
+        const int r = (int)(rg % n), l = (int)(rg / n);
+        int i = 0, j = 0;
+        while (i + 1 < T && split_start(n, T, i + 1) <= r) ++i;
+        while (j + 1 < T && split_start(n, T, j + 1) <= c) ++j;
+        const int a = r - (int)split_start(n, T, i), bcol = c - (int)split_start(n, T, j);
+        dst[g] = tiles[(((size_t)l * T + i) * T + j) * VEC_TILE_MAX * VEC_TILE_MAX + (size_t)a * VEC_TILE_MAX + bcol];
+    }
+}
+
+hipError_t vec_untile(const double *tiles, double *dst, int lmax, int n, int T, hipStream_t s) {
+    hipLaunchKernelGGL(vec_untile_kernel, dim3(1024), dim3(256), 0, s, tiles, dst, lmax, n, T);
+    return hipGetLastError();
+}
+
 hipError_t vec_layout(const double *src, double *dst, int lmax, int n, int T, hipStream_t s) {
     hipLaunchKernelGGL(vec_layout_kernel, dim3(1024), dim3(256), 0, s, src, dst, lmax, n, T);
     return hipGetLastError();

@@ -1,0 +1,126 @@
+"""Discrete adjoint (co-state sweep) on the GPU vs the CPU oracle, finite
+differences, the dot-product identity, and through torch.autograd.
+
+Gradients are compared to the oracle's discrete adjoint at 1e-10 relative
+to the largest gradient entry; finite differences (h = 1e-6, the Y(E+h) and
+Y(E-h) runs batched as separate pulses) at 1e-6 relative to the largest
+sampled finite-difference gradient.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1201_6062_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def make_plan(h, batch):
+    from paper_1201_6062_amd.api import Plan
+    return Plan(h.energies, h.dipole, batch=batch)
+
+
+def case(lmax=2, n=13, batch=3, nsteps=40, dt=0.05, seed=0):
+    h = wl.hamiltonian(lmax, n, seed)
+    rng = np.random.default_rng(seed + 1)
+    ps = [wl.Pulse(0.5 + 0.2 * b, 0.8 + 0.1 * b, 1.0) for b in range(batch)]
+    f = np.stack([wl.rk4_samples(p, dt, nsteps) for p in ps]) + 0.05 * rng.standard_normal((batch, nsteps, 3))
+    c0 = wl.ground_state(lmax, n, batch)
+    return h, np.ascontiguousarray(f), c0, dt
+
+
+def oracle_grads(h, f, c0, dt):
+    gs, l0s = [], []
+    for b in range(f.shape[0]):
+        cT = oracle.rk4(h.energies, h.dipole, dt, f[b:b + 1], c0[b:b + 1])[0]
+        lam = oracle.yield_seed(h.energies, cT)[0]
+        l0, g = oracle.rk4_adjoint(h.energies, h.dipole, dt, f[b], c0[b], lam)
+        gs.append(g)
+        l0s.append(l0)
+    return np.stack(gs), np.stack(l0s)
+
+
+def yield_seed_dev(plan, cT):
+    en = torch.as_tensor(plan.energies, device="cuda")
+    mask = (en > 0).to(torch.float64).repeat_interleave(2)
+    return 2.0 * cT * mask[None, :]
+
+
+@pytest.mark.parametrize("batch,lmax,n,nsteps,k", [(3, 2, 13, 40, 16), (2, 1, 11, 33, 7), (1, 3, 20, 50, 64),
+                                                  (5, 2, 70, 20, 8)])
+def test_adjoint_matches_oracle(batch, lmax, n, nsteps, k):
+    h, f, c0, dt = case(lmax, n, batch, nsteps)
+    plan = make_plan(h, batch)
+    cT, ck = plan.propagate(f, c0, dt, "rk4", ckpt_every=k)
+    lam = yield_seed_dev(plan, cT)
+    g, l0 = plan.adjoint(f, c0, dt, lam, ckpt=ck, ckpt_every=k)
+    g, l0 = g.cpu().numpy(), l0.cpu().numpy()
+    g_ref, l0_ref = oracle_grads(h, f, c0, dt)
+    assert np.abs(g_ref).max() > 1e-6
+    assert np.abs(g - g_ref).max() <= 1e-10 * np.abs(g_ref).max()
+    assert np.abs(l0 - l0_ref).max() <= 1e-10 * np.abs(l0_ref).max()
+
+
+def test_adjoint_without_checkpoints_recomputes():
+    h, f, c0, dt = case(2, 13, 3, 40)
+    plan = make_plan(h, 3)
+    cT = plan.propagate(f, c0, dt, "rk4")
+    lam = yield_seed_dev(plan, cT)
+    g1, l1 = plan.adjoint(f, c0, dt, lam, ckpt=None, ckpt_every=16)
+    _, ck = plan.propagate(f, c0, dt, "rk4", ckpt_every=16)
+    g2, l2 = plan.adjoint(f, c0, dt, lam, ckpt=ck, ckpt_every=16)
+    assert torch.equal(g1, g2) and torch.equal(l1, l2)
+
+
+def test_dot_product_identity_gpu():
+    """Re<lambda_0, dc0> = Re<lambda_T, dc_T> for the linear map c0 -> c_T."""
+    h, f, c0, dt = case(3, 30, 2, 45)
+    plan = make_plan(h, 2)
+    rng = np.random.default_rng(4)
+    lam_t = torch.as_tensor(rng.standard_normal((2, 2 * h.nstates)), device="cuda")
+    dc0 = rng.standard_normal((2, 2 * h.nstates))
+    _, l0 = plan.adjoint(f, c0, dt, lam_t, ckpt=None, ckpt_every=10)
+    dcT = plan.propagate(f, dc0, dt, "rk4").cpu().numpy()
+    lhs = np.sum(l0.cpu().numpy() * dc0, axis=1)
+    rhs = np.sum(lam_t.cpu().numpy() * dcT, axis=1)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-11)
+
+
+def test_autograd_function():
+    from paper_1201_6062_amd.api import Propagate, ionization_yield
+    h, f, c0, dt = case(2, 13, 3, 40)
+    plan = make_plan(h, 3)
+    field = torch.as_tensor(f, device="cuda").requires_grad_(True)
+    c0t = torch.as_tensor(c0, device="cuda").requires_grad_(True)
+    cT = Propagate.apply(field, c0t, plan, dt, 16)
+    y = ionization_yield(cT, h.energies).sum()
+    y.backward()
+    g_ref, l0_ref = oracle_grads(h, f, c0, dt)
+    assert np.abs(field.grad.cpu().numpy() - g_ref).max() <= 1e-10 * np.abs(g_ref).max()
+    assert np.abs(c0t.grad.cpu().numpy() - l0_ref).max() <= 1e-10 * np.abs(l0_ref).max()
+
+
+def test_adjoint_vs_central_fd_batched_perturbations():
+    """16 sampled field entries; Y(E +- h) of each run as 32 pulses of one batch."""
+    h, f, c0, dt = case(3, 40, 1, 60, seed=3)
+    plan1 = make_plan(h, 1)
+    cT, ck = plan1.propagate(f, c0, dt, "rk4", ckpt_every=16)
+    g, _ = plan1.adjoint(f, c0, dt, yield_seed_dev(plan1, cT), ckpt=ck, ckpt_every=16)
+    g = g.cpu().numpy()[0]
+    idx = np.argsort(-np.abs(g).ravel())[:8].tolist()
+    idx += np.linspace(0, g.size - 1, 8).astype(int).tolist()
+    hstep = 1e-6
+    fp = np.repeat(f, 32, axis=0)
+    for q, i in enumerate(idx):
+        fp[2 * q].flat[i] += hstep
+        fp[2 * q + 1].flat[i] -= hstep
+    plan32 = make_plan(h, 32)
+    cT32 = plan32.propagate(fp, np.repeat(c0, 32, axis=0), dt, "rk4").cpu().numpy()
+    y = oracle.ionization_yield(h.energies, cT32)
+    fd = (y[0::2] - y[1::2]) / (2 * hstep)
+    ga = np.array([g.flat[i] for i in idx])
+    assert np.abs(ga - fd).max() <= 1e-6 * np.abs(fd).max(), (ga, fd)
