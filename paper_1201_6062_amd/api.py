@@ -123,6 +123,54 @@ class Plan:
         return g, l0
 
 
+class Group:
+    """Several batch-1 plans (any Lmax, N) advanced together, each with its own
+    pulse and step count (RK4); every stage-round of all active instances is
+    one launch over a shared work list."""
+
+    def __init__(self, plans):
+        self._lib = _capi.load()
+        self.plans = list(plans)
+        self.device = self.plans[0].device
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = ctypes.c_void_p()
+        check(self._lib.tdse_group_create(ctypes.byref(h), len(self.plans), arr, _stream(self.device)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.tdse_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def propagate(self, fields, c0s, dt: float):
+        """fields[i]: [nsteps_i, 3] RK4 samples; c0s[i]: [2 n_i]. Returns the list of c_i(T)."""
+        n = len(self.plans)
+        fs = [_dev_f64(f, self.device).reshape(-1, 3).contiguous() for f in fields]
+        cs = [p._state(c).reshape(-1).contiguous() for p, c in zip(self.plans, c0s)]
+        outs = [torch.empty_like(c) for c in cs]
+        nst = (ctypes.c_int64 * n)(*[f.shape[0] for f in fs])
+        fp = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+        cp = (ctypes.c_void_p * n)(*[c.data_ptr() for c in cs])
+        op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        check(self._lib.tdse_group_propagate(self._h, TDSE_RK4, 0, float(dt), nst, fp, cp, op,
+                                             _stream(self.device)))
+        self._keep = (fs, cs)  # inputs stay referenced until the next call
+        return outs
+
+
+def tune(lmax: int, n: int, batch: int, cache_path: str):
+    """Run the autotuner for one problem shape; returns the tuner's summary line."""
+    lib = _capi.load()
+    check(lib.tdse_tune(int(lmax), int(n), int(batch), cache_path.encode()))
+    return lib.tdse_last_error().decode()
+
+
 def ionization_yield(cT: torch.Tensor, energies) -> torch.Tensor:
     """Y_b = sum over states with E > 0 of |c_b,j|^2 (torch ops; autograd-friendly)."""
     en = torch.as_tensor(energies, dtype=torch.float64, device=cT.device).reshape(-1)
@@ -150,4 +198,4 @@ class Propagate(torch.autograd.Function):
         return g.reshape(field.shape), l0.reshape(c0.shape), None, None, None
 
 
-__all__ = ["Plan", "Propagate", "ionization_yield", "TdseError", "METHODS"]
+__all__ = ["Plan", "Group", "Propagate", "ionization_yield", "tune", "TdseError", "METHODS"]

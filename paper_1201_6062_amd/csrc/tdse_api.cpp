@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 
@@ -676,24 +677,134 @@ tdse_status tdse_adjoint(tdse_plan p, tdse_method method, int32_t order, double 
 
 tdse_status tdse_group_create(tdse_group *out, int32_t count, const tdse_plan *plans, void *stream) {
     clear_error();
-    (void)out; (void)count; (void)plans; (void)stream;
-    return fail(TDSE_E_UNSUPPORTED, "groups not built yet");
+    (void)stream;
+    if (!out) return fail(TDSE_E_INVAL, "out is NULL");
+    if (count < 1) return fail(TDSE_E_INVAL, "count must be >= 1");
+    if (!plans) return fail(TDSE_E_INVAL, "plans is NULL");
+    for (int32_t k = 0; k < count; ++k) {
+        const tdse_plan p = plans[k];
+        if (!p) return fail(TDSE_E_INVAL, "plans[" + std::to_string(k) + "] is NULL");
+        if (p->batch != 1) return fail(TDSE_E_INVAL, "group members must be batch-1 plans");
+        if (p->T > 8) return fail(TDSE_E_UNSUPPORTED, "group members need n <= 1024 (at most 8 tiles per block)");
+        if (p->device != plans[0]->device) return fail(TDSE_E_INVAL, "group members must share one device");
+    }
+    tdse_group g = new (std::nothrow) tdse_group_s();
+    if (!g) return fail(TDSE_E_NOMEM, "host allocation failed");
+    g->plans.assign(plans, plans + count);
+    *out = g;
+    return TDSE_OK;
 }
 
 tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order, double dt,
                                  const int64_t *nsteps, const double *const *fields,
                                  const double *const *c0, double *const *cT, void *stream) {
     clear_error();
-    (void)g; (void)method; (void)order; (void)dt; (void)nsteps; (void)fields; (void)c0; (void)cT;
-    (void)stream;
-    return fail(TDSE_E_UNSUPPORTED, "groups not built yet");
+    (void)order;
+    if (!g) return fail(TDSE_E_INVAL, "group is NULL");
+    if (method != TDSE_RK4 && method != TDSE_TAYLOR) return fail(TDSE_E_INVAL, "unknown method");
+    if (method != TDSE_RK4) return fail(TDSE_E_UNSUPPORTED, "groups propagate with RK4 only");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(TDSE_E_INVAL, "dt must be finite and > 0");
+    if (!nsteps || !fields || !c0 || !cT) return fail(TDSE_E_INVAL, "nsteps, fields, c0 and cT must not be NULL");
+    const int count = (int)g->plans.size();
+    tdse_status st;
+    for (int k = 0; k < count; ++k) {
+        if (nsteps[k] < 0) return fail(TDSE_E_INVAL, "nsteps[" + std::to_string(k) + "] < 0");
+        if (nsteps[k] > 0 && (st = check_dev(fields[k], "fields[k]"))) return st;
+        if ((st = check_dev(c0[k], "c0[k]")) || (st = check_dev(cT[k], "cT[k]"))) return st;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // Instances without dipole blocks run on their own; the others are
+    // ordered by step count (descending) so the active set of every round is
+    // a prefix of the work list.
+    std::vector<int> order_idx;
+    for (int k = 0; k < count; ++k) {
+        if (g->plans[k]->lmax == 0)
+            TDSE_HIP_ST(tdse_propagate(g->plans[k], TDSE_RK4, 0, dt, nsteps[k], fields[k], c0[k], cT[k], nullptr,
+                                       0, stream));
+        else
+            order_idx.push_back(k);
+    }
+    std::stable_sort(order_idx.begin(), order_idx.end(), [&](int a, int b) { return nsteps[a] > nsteps[b]; });
+    g->tiles.clear();
+    g->insts.clear();
+    std::vector<int64_t> prefix(1, 0);
+    for (size_t q = 0; q < order_idx.size(); ++q) {
+        const tdse_plan p = g->plans[order_idx[q]];
+        GroupInst gi{};
+        gi.b = p->vb;
+        gi.field = fields[order_idx[q]];
+        gi.nsteps = nsteps[order_idx[q]];
+        g->insts.push_back(gi);
+        for (int l = 0; l < p->lmax; ++l)
+            for (int i = 0; i < p->T; ++i)
+                for (int j = 0; j < p->T; ++j) g->tiles.push_back({(int32_t)q, (int16_t)l, (int8_t)i, (int8_t)j});
+        prefix.push_back((int64_t)g->tiles.size());
+    }
+    if (order_idx.empty()) return TDSE_OK;
+    if (g->tiles.size() > g->tiles_cap) {
+        if (g->d_tiles) (void)hipFree(g->d_tiles);
+        g->d_tiles = nullptr;
+        g->tiles_cap = 0;
+        if (hipMalloc(&g->d_tiles, g->tiles.size() * sizeof(GroupTile)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(TDSE_E_NOMEM, "hipMalloc of the group work list failed");
+        }
+        g->tiles_cap = g->tiles.size();
+    }
+    if (g->insts.size() > g->insts_cap) {
+        if (g->d_insts) (void)hipFree(g->d_insts);
+        g->d_insts = nullptr;
+        g->insts_cap = 0;
+        if (hipMalloc(&g->d_insts, g->insts.size() * sizeof(GroupInst)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(TDSE_E_NOMEM, "hipMalloc of the group instance table failed");
+        }
+        g->insts_cap = g->insts.size();
+    }
+    TDSE_HIP(hipMemcpyAsync(g->d_tiles, g->tiles.data(), g->tiles.size() * sizeof(GroupTile),
+                            hipMemcpyHostToDevice, s));
+    TDSE_HIP(hipMemcpyAsync(g->d_insts, g->insts.data(), g->insts.size() * sizeof(GroupInst),
+                            hipMemcpyHostToDevice, s));
+    for (int k : order_idx) TDSE_HIP(vec_launch_start(g->plans[k]->vb, 0, c0[k], TDSE_RK4, s));
+    const int64_t rounds = 4 * nsteps[order_idx[0]];
+    size_t active = order_idx.size();
+    for (int64_t r = 0; r < rounds; ++r) {
+        while (active > 0 && 4 * nsteps[order_idx[active - 1]] <= r) --active;
+        const int64_t nt = prefix[active];
+        if (nt > 0) TDSE_HIP(group_launch_round(g->d_tiles, (int)nt, g->d_insts, r, dt, s));
+    }
+    // final completion of every instance (c(T) -> cT)
+    for (int k : order_idx) {
+        tdse_plan p = g->plans[k];
+        CallDesc d{};
+        d.nsteps = nsteps[k];
+        d.field = fields[k];
+        d.ckpt_every = 1;
+        d.dt = dt;
+        d.slots = 3;
+        TDSE_HIP(set_desc(p->vb.desc, d, s));
+        const int64_t base = nsteps[k] > 0 ? ((nsteps[k] - 1) / CHUNK_STEPS) * CHUNK_STEPS : 0;
+        TDSE_HIP(chunk_begin(p->vb.desc, base, s));
+        VecLaunch L{};
+        L.comp = final_completion(TDSE_RK4, 4);
+        L.off = (int32_t)(nsteps[k] - base);
+        L.parity = 0;
+        L.finish = 1;
+        L.slots = 3;
+        L.out = cT[k];
+        TDSE_HIP(vec_launch_combine(p->vb, L, s));
+    }
+    return TDSE_OK;
 }
 
 tdse_status tdse_group_destroy(tdse_group g) {
     clear_error();
-    (void)g;
+    if (!g) return TDSE_OK;
+    (void)hipDeviceSynchronize();
+    if (g->d_tiles) (void)hipFree(g->d_tiles);
+    if (g->d_insts) (void)hipFree(g->d_insts);
+    delete g;
     return TDSE_OK;
 }
-
 
 }  // extern "C"

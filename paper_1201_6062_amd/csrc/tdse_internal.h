@@ -26,6 +26,12 @@ tdse_status hip_fail(hipError_t e, const char *what);
         if (e_ != hipSuccess) return ::tdse::hip_fail(e_, #call); \
     } while (0)
 
+#define TDSE_HIP_ST(call)                                     \
+    do {                                                      \
+        tdse_status s_ = (call);                              \
+        if (s_ != TDSE_OK) return s_;                         \
+    } while (0)
+
 // ---------------------------------------------------------------------------
 // Completion of one product (the RK4 stage or Taylor term whose dipole
 // product the previous launch computed) and formation of the next input.
@@ -95,6 +101,20 @@ struct VecLaunch {
     double *out;     // caller cT for the finish launch
 };
 
+// Uneven group (several batch-1 plans advanced together).
+struct GroupTile {
+    int32_t inst;           // instance (index into the GroupInst array)
+    int16_t l;              // block of the tile
+    int8_t i, j;            // row / column segment
+};
+struct GroupInst {
+    VecBuffers b;           // the instance plan's buffers (its own T and segments)
+    const double *field;    // [nsteps][3]
+    int64_t nsteps;
+};
+hipError_t group_launch_round(const GroupTile *tiles, int ntiles, const GroupInst *insts, int64_t round,
+                              double dt, hipStream_t s);
+
 hipError_t vec_launch_tiles(const VecBuffers &b, const VecLaunch &l, hipStream_t s);
 hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream_t s);
 hipError_t vec_launch_start(const VecBuffers &b, int32_t parity, const double *c0, int32_t method,
@@ -163,6 +183,17 @@ tdse_status create_plan(tdse_plan *out, const double *energies, const double *di
 }  // namespace tdse
 
 // ---------------------------------------------------------------------------
+struct tdse_group_s {
+    std::vector<tdse_plan> plans;
+    // work list and instance table of the last call (host copies stay alive
+    // until the next call, so the asynchronous uploads can read them)
+    std::vector<tdse::GroupTile> tiles;
+    std::vector<tdse::GroupInst> insts;
+    tdse::GroupTile *d_tiles = nullptr;
+    tdse::GroupInst *d_insts = nullptr;
+    size_t tiles_cap = 0, insts_cap = 0;
+};
+
 struct tdse_plan_s {
     int32_t lmax = 0, n = 0, batch = 1;
     int device = 0;

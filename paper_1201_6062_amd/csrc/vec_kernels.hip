@@ -159,10 +159,8 @@ __device__ __forceinline__ double field_of(const CallDesc *d, const VecLaunch &L
 // loads are unconditional (indices clamped into the buffer) and invalid terms
 // are dropped afterwards, so the loads issue back to back.
 template <int TP>
-__device__ __forceinline__ double2 sum_partials(const VecBuffers &b, int par, bool rows, int m,
+__device__ __forceinline__ double2 sum_partials(const VecBuffers &b, int T, int par, bool rows, int m,
                                                 int q, int e) {
-    // TP == T for T <= 8 (exact instantiations); TP == 16 covers 9..16.
-    const int T = TP <= 8 ? TP : b.T;
     const bool valid = rows ? (m < b.lmax) : (m > 0);
     const int hi = b.lmax > 0 ? b.lmax - 1 : 0;
     int mb = rows ? m : m - 1;
@@ -210,24 +208,22 @@ __device__ __forceinline__ void store_state(const VecBuffers &b, const VecLaunch
     if (ct.slot) st_global(ct.slot + gi, c);
 }
 
+// One tile workgroup: completes the previous product for segments A = (l, i)
+// and B = (l+1, j) and produces this launch's row and column partials of
+// tile (l, i, j). T is the number of tiles per block dimension (a compile-time
+// constant where TP == T), F the field sample of the completed product.
 template <int TP>
-__global__ __launch_bounds__(VEC_THREADS) void vec_tiles_kernel(VecBuffers b, VecLaunch L) {
-    // TP == T for T <= 8, so the tile decode divides by compile-time constants.
-    const int T = TP <= 8 ? TP : b.T, n = b.n;
-    const int ntiles = b.lmax * T * T;
-    const int w = blockIdx.x;
-    const int xcd = w & 7, per = ntiles >> 3, extra = ntiles & 7;
-    const int tile = xcd * per + (xcd < extra ? xcd : extra) + (w >> 3);  // Sec. 4.1 split over XCDs
-    const int l = tile / (T * T), rem = tile - l * T * T, i = rem / T, j = rem - i * T;
-    const int r0 = b.seg[i], RA = b.seg[i + 1] - r0;
-    const int c0 = b.seg[j], RB = b.seg[j + 1] - c0;
+__device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &L, int T, int l, int i, int j,
+                                          int r0, int RA, int c0, int RB, double F, double dt,
+                                          const CkptTarget &ct) {
+    const int n = b.n;
+    const int tile = (l * T + i) * T + j;
 
     __shared__ double2 uA[VEC_TILE_MAX], uB[VEC_TILE_MAX];
     __shared__ double2 zc[2 * VEC_TILE_MAX];
     __shared__ double2 cpart[VEC_THREADS / 64][VEC_TILE_MAX];
     __shared__ double2 rpart[VEC_THREADS / 64][4][16];
 
-    const CallDesc *d = b.desc;
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
     const int par = L.parity;
@@ -241,12 +237,10 @@ __global__ __launch_bounds__(VEC_THREADS) void vec_tiles_kernel(VecBuffers b, Ve
     const int m = isB ? l + 1 : l, q = isB ? j : i, len = isB ? RB : RA, s0 = isB ? c0 : r0;
     const int ec = e < len ? e : len - 1;
     const size_t gi = (size_t)m * n + s0 + ec;
-    const double2 zpart = sum_partials<TP>(b, par, half == 0, m, q, ec);
+    const double2 zpart = sum_partials<TP>(b, T, par, half == 0, m, q, ec);
     const double2 c_in = ld_nt(st_ptr(b, par, 0) + gi), acc_in = ld_nt(st_ptr(b, par, 1) + gi);
     const double2 u_in = ld_nt(st_ptr(b, par, 2) + gi);
     const double E0 = __builtin_nontemporal_load(b.en + gi);
-    const double F = field_of(d, L), dt = d->dt;
-    const CkptTarget ct = ckpt_target(b, L, d);
 
     // ---- tile loads. Tiles are stored blocked with a 128-double row pitch,
     // zero-padded beyond RB columns: lane L reads columns 2L, 2L+1 of a row
@@ -328,12 +322,54 @@ __global__ __launch_bounds__(VEC_THREADS) void vec_tiles_kernel(VecBuffers b, Ve
     }
 }
 
+template <int TP>
+__global__ __launch_bounds__(VEC_THREADS) void vec_tiles_kernel(VecBuffers b, VecLaunch L) {
+    // TP == T for T <= 8, so the tile decode divides by compile-time constants.
+    const int T = TP <= 8 ? TP : b.T;
+    const int ntiles = b.lmax * T * T;
+    const int w = blockIdx.x;
+    const int xcd = w & 7, per = ntiles >> 3, extra = ntiles & 7;
+    const int tile = xcd * per + (xcd < extra ? xcd : extra) + (w >> 3);  // Sec. 4.1 split over XCDs
+    const int l = tile / (T * T), rem = tile - l * T * T, i = rem / T, j = rem - i * T;
+    const CallDesc *d = b.desc;
+    const double F = field_of(d, L), dt = d->dt;
+    const CkptTarget ct = ckpt_target(b, L, d);
+    const int r0 = b.seg[i], RA = b.seg[i + 1] - r0;
+    const int c0 = b.seg[j], RB = b.seg[j + 1] - c0;
+    tile_body<TP>(b, L, T, l, i, j, r0, RA, c0, RB, F, dt, ct);
+}
+
+// Uneven group: one launch runs one RK4 stage-round of every active
+// instance. Workgroup w takes entry w of the work list (instance, l, i, j);
+// each instance brings its own buffers, tile count and field samples.
+__global__ __launch_bounds__(VEC_THREADS) void vec_group_kernel(const GroupTile *tiles, const GroupInst *insts,
+                                                                 int64_t round, double dt) {
+    const GroupTile gt = tiles[blockIdx.x];
+    const GroupInst &gi = insts[gt.inst];
+    const VecBuffers b = gi.b;
+    // RK4 launch schedule: launch 4k+s completes stage s of step k (stage 4 of
+    // step k-1 for s == 0) and forms the input of the next stage.
+    const int s = (int)(round & 3);
+    VecLaunch L{};
+    L.parity = (int)(round & 1);
+    L.slots = 3;
+    if (s == 0) L.comp = {CK_RK4_END, 2, -1, 0, 1.0 / 6.0, 0.0};
+    else if (s == 1) L.comp = {CK_RK4_MID, 0, 0, 1, 1.0 / 6.0, 0.5};
+    else if (s == 2) L.comp = {CK_RK4_MID, 1, 0, 0, 2.0 / 6.0, 0.5};
+    else L.comp = {CK_RK4_MID, 1, 0, 0, 2.0 / 6.0, 1.0};
+    const int64_t step = (round >> 2) + L.comp.step_delta;
+    const double F = (step >= 0 && step < gi.nsteps) ? gi.field[step * 3 + L.comp.slot] : 0.0;
+    const int r0 = (int)split_start(b.n, b.T, gt.i), RA = (int)split_len(b.n, b.T, gt.i);
+    const int c0 = (int)split_start(b.n, b.T, gt.j), RB = (int)split_len(b.n, b.T, gt.j);
+    tile_body<8>(b, L, b.T, gt.l, gt.i, gt.j, r0, RA, c0, RB, F, dt, CkptTarget{nullptr});
+}
+
 // Completion only (no products): the final completion of a propagation,
 // every launch when lmax == 0 (no dipole blocks, z == 0), and the single
 // product of tdse_hmul (kind CK_HMUL: y = E o u + F z).
 template <int TP>
 __global__ __launch_bounds__(VEC_TILE_MAX) void vec_combine_kernel(VecBuffers b, VecLaunch L) {
-    const int T = b.T;
+    const int T = TP <= 8 ? TP : b.T;
     const int seg = blockIdx.x;
     const int m = seg / T, q = seg - m * T;
     const int s0 = (int)split_start(b.n, T, q), len = (int)split_len(b.n, T, q);
@@ -345,7 +381,7 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_combine_kernel(VecBuffers b,
     const size_t gi = (size_t)m * b.n + s0 + e;
     double2 z = make_double2(0.0, 0.0);
     if (b.lmax > 0)
-        z = cadd(sum_partials<TP>(b, par, true, m, q, e), sum_partials<TP>(b, par, false, m, q, e));
+        z = cadd(sum_partials<TP>(b, T, par, true, m, q, e), sum_partials<TP>(b, T, par, false, m, q, e));
     double2 c = ld_nt(st_ptr(b, par, 0) + gi), acc = ld_nt(st_ptr(b, par, 1) + gi), u = ld_nt(st_ptr(b, par, 2) + gi);
     const double E0 = b.en[gi];
     if (L.comp.kind == CK_HMUL) {
@@ -489,6 +525,12 @@ hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream
     TDSE_TP_DISPATCH(b.T, vec_combine_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s, b, l);
     return hipGetLastError();
 }
+hipError_t group_launch_round(const GroupTile *tiles, int ntiles, const GroupInst *insts, int64_t round,
+                              double dt, hipStream_t s) {
+    hipLaunchKernelGGL(vec_group_kernel, dim3(ntiles), dim3(VEC_THREADS), 0, s, tiles, insts, round, dt);
+    return hipGetLastError();
+}
+
 hipError_t vec_launch_start(const VecBuffers &b, int32_t parity, const double *c0, int32_t method,
                             hipStream_t s) {
     hipLaunchKernelGGL(vec_start_kernel, dim3(256), dim3(256), 0, s, b, parity,

@@ -1,0 +1,69 @@
+"""Uneven multi-instance group (different Lmax, N, pulses and step counts in
+one schedule) vs the CPU oracle and vs each instance propagated alone."""
+import os
+
+import numpy as np
+import pytest
+import torch  # noqa: F401
+
+import oracle
+from paper_1201_6062_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = 1e-10
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def plan_of(h):
+    from paper_1201_6062_amd.api import Plan
+    return Plan(h.energies, h.dipole if h.lmax else np.zeros((0, h.n, h.n)))
+
+
+def test_group_small_uneven():
+    from paper_1201_6062_amd.api import Group
+    shapes = [(2, 130, 90), (3, 50, 70), (1, 7, 0), (0, 9, 40), (4, 257, 33), (2, 64, 129)]
+    hs, fs, cs = [], [], []
+    for q, (lmax, n, nst) in enumerate(shapes):
+        h = wl.hamiltonian(lmax, n, 100 + q)
+        p = wl.Pulse(0.1 + 0.02 * q, 0.5 + 0.1 * q, 2.0)
+        hs.append(h)
+        fs.append(wl.rk4_samples(p, 0.01, nst))
+        cs.append(wl.random_state(np.random.default_rng(q), h.nstates)[0])
+    plans = [plan_of(h) for h in hs]
+    out = Group(plans).propagate(fs, cs, 0.01)
+    for h, f, c, o in zip(hs, fs, cs, out):
+        ref = oracle.rk4(h.energies, h.dipole, 0.01, f[None], c[None], n=h.n)[0]
+        assert rel_l2(o.cpu().numpy(), ref) <= TOL
+
+
+def test_group_equals_single_instance_runs():
+    """Same kernels, same summation order: bitwise equal to propagating alone."""
+    from paper_1201_6062_amd.api import Group
+    specs = wl.uneven_specs(64)[:6]
+    hs = [wl.hamiltonian(s.lmax, s.n, s.seed) for s in specs]
+    fs = [wl.rk4_samples(s.pulse, 0.005, 60 + 13 * q) for q, s in enumerate(specs)]
+    cs = [wl.ground_state(s.lmax, s.n)[0] for s in specs]
+    plans = [plan_of(h) for h in hs]
+    out = Group(plans).propagate(fs, cs, 0.005)
+    for p, f, c, o in zip(plans, fs, cs, out):
+        alone = p.propagate(f[None], c[None], 0.005, "rk4")
+        assert torch.equal(alone.reshape(-1), o)
+
+
+def test_group_full_length_sampled_instances():
+    """Instances 16, 21, 39 of the 64-instance workload, whole pulses, vs stored oracle results."""
+    from paper_1201_6062_amd.api import Group
+    specs = wl.uneven_specs(64)
+    ids = [16, 21, 39]
+    hs = [wl.hamiltonian(specs[i].lmax, specs[i].n, specs[i].seed) for i in ids]
+    fs = [wl.rk4_samples(specs[i].pulse, 0.005, specs[i].nsteps) for i in ids]
+    cs = [wl.ground_state(specs[i].lmax, specs[i].n)[0] for i in ids]
+    out = Group([plan_of(h) for h in hs]).propagate(fs, cs, 0.005)
+    for i, o in zip(ids, out):
+        gold = np.load(os.path.join(HERE, "golden", f"uneven_inst{i:02d}.npz"), allow_pickle=False)
+        assert int(gold["nsteps"]) == specs[i].nsteps
+        assert rel_l2(o.cpu().numpy(), gold["cT"]) <= TOL
