@@ -135,6 +135,54 @@ def batched_measure(torch, batch: int = 256, steps: int = 100, tile: str | None 
             "tflops": tf, "frac_of_fp64_peak": tf / FP64_PEAK_TFLOPS}
 
 
+def small_measure(torch, force_tiles: bool = False):
+    """Lmax=3, N=50 (200 states), 12567 RK4 steps: the latency-bound small problem."""
+    from paper_1201_6062_amd import workloads as wl
+    from paper_1201_6062_amd.api import Plan
+    w = wl.single_small()
+    if force_tiles:
+        os.environ["TDSE_TILE"] = "T=1"
+    plan = Plan(w.ham.energies, w.ham.dipole)
+    if force_tiles:
+        del os.environ["TDSE_TILE"]
+    ev, _, _ = time_propagation(plan, w, "rk4", 0, 3, 1, torch)
+    plan.close()
+    t = ev / 3
+    return {"workload": "Lmax=3 N=50, RK4 dt=0.01, 12567 steps", "path": "tiles" if force_tiles else "one workgroup",
+            "ms_per_propagation": t * 1e3, "state_steps_per_s": w.ham.nstates * w.nsteps / t,
+            "us_per_step": t / w.nsteps * 1e6}
+
+
+def group_measure(torch, steps: int = 400):
+    """64 uneven instances (Lmax 7..31, N 200..1000), first `steps` RK4 steps of each."""
+    from paper_1201_6062_amd import workloads as wl
+    from paper_1201_6062_amd.api import Group, Plan
+    specs = wl.uneven_specs(64)
+    plans, fs, cs = [], [], []
+    for sp in specs:
+        h = wl.hamiltonian(sp.lmax, sp.n, sp.seed)
+        plans.append(Plan(h.energies, h.dipole))
+        fs.append(torch.as_tensor(wl.rk4_samples(sp.pulse, 0.005, min(steps, sp.nsteps)), device="cuda"))
+        cs.append(torch.as_tensor(wl.ground_state(sp.lmax, sp.n)[0], device="cuda"))
+    g = Group(plans)
+    g.propagate([f[:8] for f in fs], cs, 0.005)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.propagate(fs, cs, 0.005)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3
+    nbytes = sum(4 * f.shape[0] * algorithmic_bytes_per_product(sp.lmax, sp.n) for sp, f in zip(specs, fs))
+    ss = sum((sp.lmax + 1) * sp.n * f.shape[0] for sp, f in zip(specs, fs))
+    g.close()
+    for p in plans:
+        p.close()
+    return {"workload": f"64 instances (Lmax 7..31, N 200..1000, {sum(sp.lmax * sp.n ** 2 * 8 for sp in specs) / 1e9:.2f} GB "
+                        f"of dipole), first {steps} RK4 steps each", "seconds": s,
+            "state_steps_per_s": ss / s, "GBps": nbytes / s / 1e9, "frac_of_hbm_peak": nbytes / s / 1e9 / HBM_PEAK_GBS}
+
+
 def calibrate_copy(torch, mb: int = 1024, reps: int = 5):
     """Plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
     x = torch.ones(mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
@@ -153,6 +201,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-diag", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the small-problem and group measurements")
     ap.add_argument("--batched-only", action="store_true")
     ap.add_argument("--tile", default=None, help="batched tile TMxTN (tuning experiments)")
     ap.add_argument("--method", choices=["rk4", "taylor"], default="rk4")
@@ -232,6 +281,10 @@ def main():
         out["hbm_diagnostic"] = hbm_diagnostic(torch)
     if not a.no_batched:
         out["batched"] = batched_measure(torch)
+    if not a.no_extra:
+        out["single_small"] = small_measure(torch)
+        out["single_small_tiles"] = small_measure(torch, force_tiles=True)
+        out["uneven_group"] = group_measure(torch)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

@@ -1,0 +1,183 @@
+// Whole propagation in one workgroup, for small problems ((lmax+1) n <= 256
+// states, n <= 64): the latency-bound regime where a launch per product would
+// cost more than the product itself.
+//
+// Each state entry (m, a) is owned by a group of 4 lanes. Row a of H's
+// off-diagonal blocks (Sec. 4, the block product after Eq. ode) is the
+// concatenation of row a of D_m (towards u_{m+1}) and column a of D_{m-1}
+// (towards u_{m-1}); its 2n dipole elements are split over the 4 lanes and
+// held in registers for the whole run. Per product every lane forms its
+// partial dot product against u (double-buffered in LDS), the group sums the
+// 4 partials with DPP in fixed order, and the group's first lane completes
+// the RK4 stage or Taylor term (appendix B) with c and the stage accumulator
+// kept in its registers. One LDS barrier per product; field samples are
+// staged into LDS 64 steps at a time, one chunk ahead.
+#include "tdse_internal.h"
+
+namespace tdse {
+
+
+__device__ __forceinline__ double small_dpp(double v, int ctrl_sel) {
+    long long b = __double_as_longlong(v);
+    int lo, hi;
+    if (ctrl_sel == 1) {  // xor 1
+        lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0xB1, 0xF, 0xF, true);
+        hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, true);
+    } else {  // xor 2
+        lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x4E, 0xF, 0xF, true);
+        hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x4E, 0xF, 0xF, true);
+    }
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+struct SmallArgs {
+    const double *en;      // [(lmax+1) n]
+    const double *dip;     // tiles of the single-vector layout (T == 1)
+    const double *field;   // [nsteps][S]
+    const double *c0;
+    double *cT;
+    double *ckpt;          // [nsteps/K + 1][2 ns] or null
+    int64_t nsteps, ckpt_every;
+    double dt;
+    int32_t lmax, n, method, order;
+};
+
+// EPL: compiled bound on the dipole elements per lane, ceil(2n / 4) <= EPL.
+template <int EPL>
+__global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
+    const int n = A.n, lmax = A.lmax, ns = (lmax + 1) * n;
+    const int S = A.method == TDSE_RK4 ? 3 : 1;
+    const int t = threadIdx.x;
+    const int entry = t >> 2, g = t & 3;
+    const bool live = entry < ns;
+    const int es = live ? entry : 0;
+    const int m = es / n, a = es - m * n;
+    const int epl = (2 * n + 3) / 4;
+
+    __shared__ double2 ubuf[2][256];
+    __shared__ double fbuf[2][64 * 3];
+
+    // dipole elements of this lane (zero where the element does not exist);
+    // element e < n multiplies u_{m+1}[e], element e >= n multiplies u_{m-1}[e-n]
+    double d[EPL];
+    const size_t tile = (size_t)VEC_TILE_MAX * VEC_TILE_MAX;
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
+        const int e = g * epl + k;
+        double v = 0.0;
+        if (live && k < epl && e < 2 * n) {
+            if (e < n) {  // row a of D_m
+                if (m < lmax) v = A.dip[(size_t)m * tile + (size_t)a * VEC_TILE_MAX + e];
+            } else {      // column a of D_{m-1}
+                if (m > 0) v = A.dip[(size_t)(m - 1) * tile + (size_t)(e - n) * VEC_TILE_MAX + a];
+            }
+        }
+        d[k] = v;
+    }
+    const int e0 = g * epl;
+    const int row_base = (m + 1) * n, col_base = (m - 1) * n - n;
+    const double E0 = live ? A.en[es] : 0.0;
+    double2 c = make_double2(0.0, 0.0), acc = c;
+    if (live) c = reinterpret_cast<const double2 *>(A.c0)[es];
+    if (live && g == 0) {
+        ubuf[0][es] = c;
+        if (A.ckpt) reinterpret_cast<double2 *>(A.ckpt)[es] = c;
+    }
+    // field samples of steps 0..63
+    for (int x = t; x < 64 * S; x += blockDim.x) {
+        const int64_t st = x / S;
+        fbuf[0][x] = st < A.nsteps ? A.field[st * S + x % S] : 0.0;
+    }
+    __syncthreads();
+
+    const double dt = A.dt;
+    const int nprod = A.method == TDSE_RK4 ? 4 : A.order;
+    int par = 0;
+    for (int64_t step = 0; step < A.nsteps; ++step) {
+        const int fb = (int)((step >> 6) & 1), fo = (int)(step & 63);
+        // stage next chunk's field samples (read at the next chunk boundary)
+        if (fo == 0) {
+            for (int x = t; x < 64 * S; x += blockDim.x) {
+                const int64_t st = step + 64 + x / S;
+                fbuf[fb ^ 1][x] = st < A.nsteps ? A.field[st * S + x % S] : 0.0;
+            }
+        }
+        for (int p = 0; p < nprod; ++p) {
+            // partial dot product of this lane
+            double zr = 0.0, zi = 0.0;
+#pragma unroll
+            for (int k = 0; k < EPL; ++k) {
+                if (k < epl) {
+                    const int e = e0 + k;
+                    int idx = e < n ? row_base + e : col_base + e;
+                    idx = (idx >= 0 && idx < ns) ? idx : 0;  // d[k] == 0 there
+                    const double2 u = ubuf[par][idx];
+                    zr = fma(d[k], u.x, zr);
+                    zi = fma(d[k], u.y, zi);
+                }
+                // keep at most 8 LDS reads in flight (register budget at 1024 threads)
+                if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+            }
+            zr += small_dpp(zr, 1);
+            zi += small_dpp(zi, 1);
+            zr += small_dpp(zr, 2);
+            zi += small_dpp(zi, 2);
+            if (live && g == 0) {
+                const double2 u = ubuf[par][es];
+                int slot = 0;
+                if (A.method == TDSE_RK4) slot = p == 0 ? 0 : (p == 3 ? 2 : 1);
+                const double F = fbuf[fb][fo * S + slot];
+                // k = -i (E0 u + F z)
+                const double yr = fma(F, zr, E0 * u.x), yi = fma(F, zi, E0 * u.y);
+                const double kr = yi, ki = -yr;
+                double2 un;
+                if (A.method == TDSE_RK4) {
+                    if (p == 0) {
+                        acc = make_double2(kr / 6.0, ki / 6.0);
+                        un = make_double2(fma(0.5 * dt, kr, c.x), fma(0.5 * dt, ki, c.y));
+                    } else if (p < 3) {
+                        acc = make_double2(fma(1.0 / 3.0, kr, acc.x), fma(1.0 / 3.0, ki, acc.y));
+                        const double al = p == 1 ? 0.5 * dt : dt;
+                        un = make_double2(fma(al, kr, c.x), fma(al, ki, c.y));
+                    } else {
+                        c = make_double2(fma(dt, fma(1.0 / 6.0, kr, acc.x), c.x),
+                                         fma(dt, fma(1.0 / 6.0, ki, acc.y), c.y));
+                        un = c;
+                    }
+                } else {
+                    // Taylor term T_{p+1} = (dt / (p+1)) k, accumulated onto c
+                    const double sc = dt / (double)(p + 1);
+                    un = make_double2(sc * kr, sc * ki);
+                    acc = p == 0 ? make_double2(c.x + un.x, c.y + un.y)
+                                 : make_double2(acc.x + un.x, acc.y + un.y);
+                    if (p == nprod - 1) {
+                        c = acc;
+                        un = c;
+                    }
+                }
+                ubuf[par ^ 1][es] = un;
+            }
+            par ^= 1;
+            __syncthreads();
+        }
+        if (A.ckpt && live && g == 0 && (step + 1) % A.ckpt_every == 0)
+            reinterpret_cast<double2 *>(A.ckpt)[(size_t)((step + 1) / A.ckpt_every) * ns + es] = c;
+    }
+    if (live && g == 0) reinterpret_cast<double2 *>(A.cT)[es] = c;
+}
+
+bool small_eligible(int lmax, int n) { return n <= 64 && (lmax + 1) * n <= 256; }
+
+hipError_t small_propagate(const double *en, const double *dip, int lmax, int n, int method, int order, double dt,
+                           int64_t nsteps, const double *field, const double *c0, double *cT, double *ckpt,
+                           int64_t ckpt_every, hipStream_t s) {
+    SmallArgs A{en, dip, field, c0, cT, ckpt, nsteps, ckpt_every > 0 ? ckpt_every : 1, dt, lmax, n, method, order};
+    const int threads = (((lmax + 1) * n * 4 + 63) / 64) * 64;
+    const int epl = (2 * n + 3) / 4;
+    if (epl <= 16) hipLaunchKernelGGL(small_propagate_kernel<16>, dim3(1), dim3(threads), 0, s, A);
+    else if (epl <= 26) hipLaunchKernelGGL(small_propagate_kernel<26>, dim3(1), dim3(threads), 0, s, A);
+    else hipLaunchKernelGGL(small_propagate_kernel<32>, dim3(1), dim3(threads), 0, s, A);
+    return hipGetLastError();
+}
+
+}  // namespace tdse

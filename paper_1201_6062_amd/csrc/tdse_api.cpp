@@ -126,6 +126,11 @@ static bool graphs_enabled() {
 static tdse_status vec_propagate(tdse_plan p, tdse_method m, int order, double dt, int64_t nsteps,
                                  const double *field, const double *c0, double *cT, double *ckpt,
                                  int32_t K, hipStream_t s) {
+    if (p->small) {
+        TDSE_HIP(small_propagate(p->en, p->dip, p->lmax, p->n, (int)m, order, dt, nsteps, field, c0, cT, ckpt,
+                                 ckpt ? K : 1, s));
+        return TDSE_OK;
+    }
     CallDesc d{};
     d.base_step = 0;
     d.nsteps = nsteps;
@@ -528,6 +533,8 @@ tdse_status create_plan(tdse_plan *out, const double *energies, const double *di
         if (force) tc = *force;
         else tune_lookup(lmax, n, 1, &tc);
         if (tc.T >= p->T && tc.T <= n) p->T = tc.T;
+        // a forced tile count selects the tiled kernels even for small problems
+        p->small = tc.T == 0 && small_eligible(lmax, n);
     }
     if (p->T > 16) {
         delete p;

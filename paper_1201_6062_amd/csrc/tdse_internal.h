@@ -112,6 +112,12 @@ struct GroupInst {
     const double *field;    // [nsteps][3]
     int64_t nsteps;
 };
+// Single-workgroup propagation of small problems ((lmax+1) n <= 256, n <= 64).
+bool small_eligible(int lmax, int n);
+hipError_t small_propagate(const double *en, const double *dip, int lmax, int n, int method, int order, double dt,
+                           int64_t nsteps, const double *field, const double *c0, double *cT, double *ckpt,
+                           int64_t ckpt_every, hipStream_t s);
+
 hipError_t group_launch_round(const GroupTile *tiles, int ntiles, const GroupInst *insts, int64_t round,
                               double dt, hipStream_t s);
 
@@ -203,6 +209,7 @@ struct tdse_plan_s {
     int32_t ld = 0;
     // single-vector path
     int32_t T = 1;
+    bool small = false;          // whole propagation in one workgroup
     double *scratch = nullptr;   // one allocation holding states, partials, descriptor
     size_t scratch_bytes = 0;
     tdse::VecBuffers vb{};

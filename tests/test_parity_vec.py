@@ -34,6 +34,17 @@ def make_plan(h, batch=1):
     return Plan(h.energies, h.dipole if h.lmax > 0 else np.zeros((0, h.n, h.n)), batch=batch)
 
 
+@pytest.fixture(params=["auto", "tiles"])
+def path(request):
+    """auto: the library's choice (one-workgroup kernel for small problems);
+    tiles: the tiled per-product kernels, forced through TDSE_TILE."""
+    return request.param
+
+
+def force_tiles(monkeypatch, n):
+    monkeypatch.setenv("TDSE_TILE", f"T={(n + 127) // 128}")
+
+
 SHAPES = [(1, 1), (2, 3), (3, 50), (0, 7), (2, 130), (3, 257), (1, 128), (2, 129)]
 
 
@@ -59,7 +70,9 @@ def _rk4_case(lmax, n, nsteps, dt, seed=0, e0=0.08, w=0.6):
 
 @pytest.mark.parametrize("lmax,n,nsteps", [(1, 1, 50), (2, 3, 130), (3, 50, 300), (0, 7, 65),
                                             (2, 130, 100), (3, 257, 70), (2, 129, 64)])
-def test_rk4_parity(torch_dev, lmax, n, nsteps):
+def test_rk4_parity(torch_dev, lmax, n, nsteps, path, monkeypatch):
+    if path == "tiles":
+        force_tiles(monkeypatch, n)
     h, f, c0 = _rk4_case(lmax, n, nsteps, 0.01)
     plan = make_plan(h)
     got = plan.propagate(f, c0, 0.01, "rk4").cpu().numpy()
@@ -69,7 +82,9 @@ def test_rk4_parity(torch_dev, lmax, n, nsteps):
 
 @pytest.mark.parametrize("order", [1, 2, 4, 8, 10])
 @pytest.mark.parametrize("lmax,n,nsteps", [(2, 3, 70), (3, 130, 66), (0, 5, 64)])
-def test_taylor_parity(torch_dev, order, lmax, n, nsteps):
+def test_taylor_parity(torch_dev, order, lmax, n, nsteps, path, monkeypatch):
+    if path == "tiles":
+        force_tiles(monkeypatch, n)
     h = wl.hamiltonian(lmax, n, 3)
     dt = 0.02
     f = wl.taylor_samples(wl.Pulse(0.08, 0.6, 2.0), dt, nsteps)[None]
@@ -80,8 +95,10 @@ def test_taylor_parity(torch_dev, order, lmax, n, nsteps):
     assert rel_l2(got, ref) <= TOL
 
 
-def test_single_small_full_length(torch_dev):
+def test_single_small_full_length(torch_dev, path, monkeypatch):
     """Lmax=3, N=50, 12567 RK4 steps against the stored full-length oracle result."""
+    if path == "tiles":
+        force_tiles(monkeypatch, 50)
     w = wl.single_small()
     gold = np.load(os.path.join(HERE, "golden", "single_small_rk4.npz"), allow_pickle=False)
     assert int(gold["nsteps"]) == w.nsteps
@@ -118,8 +135,10 @@ def test_single_large_full_length(torch_dev, name, method, order):
     assert rel_l2(got, gold["cT"][None]) <= TOL
 
 
-def test_nsteps_zero_and_alias(torch_dev):
+def test_nsteps_zero_and_alias(torch_dev, path, monkeypatch):
     torch = torch_dev
+    if path == "tiles":
+        force_tiles(monkeypatch, 9)
     h, f, c0 = _rk4_case(2, 9, 40, 0.01)
     plan = make_plan(h)
     out = plan.propagate(np.zeros((1, 0, 3)), c0, 0.01, "rk4").cpu().numpy()
@@ -131,12 +150,13 @@ def test_nsteps_zero_and_alias(torch_dev):
 
 
 @pytest.mark.parametrize("method,order", [("rk4", 0), ("taylor", 6)])
-def test_checkpoints(torch_dev, method, order):
-    h = wl.hamiltonian(2, 140, 2)
+@pytest.mark.parametrize("lmax,n", [(2, 140), (3, 40)])
+def test_checkpoints(torch_dev, method, order, lmax, n):
+    h = wl.hamiltonian(lmax, n, 2)
     dt, nsteps, k = 0.01, 150, 64
     pulse = wl.Pulse(0.1, 0.5, 2.0)
     f = (wl.rk4_samples if method == "rk4" else wl.taylor_samples)(pulse, dt, nsteps)[None]
-    c0 = wl.ground_state(2, 140)
+    c0 = wl.ground_state(lmax, n)
     plan = make_plan(h)
     cT, ck = plan.propagate(f, c0, dt, method, order=order or 8, ckpt_every=k)
     ck = ck.cpu().numpy()
