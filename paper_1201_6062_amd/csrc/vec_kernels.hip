@@ -323,7 +323,7 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
 }
 
 template <int TP>
-__global__ __launch_bounds__(VEC_THREADS) void vec_tiles_kernel(VecBuffers b, VecLaunch L) {
+__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_tiles_kernel(VecBuffers b, VecLaunch L) {
     // TP == T for T <= 8, so the tile decode divides by compile-time constants.
     const int T = TP <= 8 ? TP : b.T;
     const int ntiles = b.lmax * T * T;
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(VEC_THREADS) void vec_tiles_kernel(VecBuffers b, Ve
 // Uneven group: one launch runs one RK4 stage-round of every active
 // instance. Workgroup w takes entry w of the work list (instance, l, i, j);
 // each instance brings its own buffers, tile count and field samples.
-__global__ __launch_bounds__(VEC_THREADS) void vec_group_kernel(const GroupTile *tiles, const GroupInst *insts,
+__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_group_kernel(const GroupTile *tiles, const GroupInst *insts,
                                                                  int64_t round, double dt) {
     const GroupTile gt = tiles[blockIdx.x];
     const GroupInst &gi = insts[gt.inst];
