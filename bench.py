@@ -29,6 +29,33 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 matrix / vector
 
 
+METRIC = "state-steps/s (matvec % HBM peak; batched % FP64 MFMA) at 1e-10 vs oracle"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vec_tiles_L15_N500.json")
+# sources that determine the tile kernel's memory traffic
+TILE_KERNEL_SOURCES = ["vec_kernels.hip", "tdse_internal.h", "tdse_split.h"]
+
+
+def tile_kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TILE_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1201_6062_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per tile-kernel launch from the committed FETCH_SIZE / WRITE_SIZE
+    measurement, or None when the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha256") != tile_kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
 def algorithmic_bytes_per_product(lmax: int, n: int) -> int:
     """Dipole read once (8 L N^2) + energies (8 n) + one complex vector in and out (32 n)."""
     ns = (lmax + 1) * n
@@ -202,7 +229,8 @@ def main():
     ap.add_argument("--no-diag", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the small-problem and group measurements")
-    ap.add_argument("--batched-only", action="store_true")
+    ap.add_argument("--only", choices=["single", "diag", "batched", "small", "small_tiles", "group"], default=None,
+                    help="profiling runs: measure one workload and print its record alone")
     ap.add_argument("--tile", default=None, help="batched tile TMxTN (tuning experiments)")
     ap.add_argument("--method", choices=["rk4", "taylor"], default="rk4")
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -222,8 +250,13 @@ def main():
     from paper_1201_6062_amd import workloads as wl
     from paper_1201_6062_amd.api import Plan
 
-    if a.batched_only:
-        print(json.dumps(batched_measure(torch, steps=a.truncate or 100, tile=a.tile)))
+    only = {"diag": lambda: hbm_diagnostic(torch),
+            "batched": lambda: batched_measure(torch, steps=a.truncate or 100, tile=a.tile),
+            "small": lambda: small_measure(torch),
+            "small_tiles": lambda: small_measure(torch, force_tiles=True),
+            "group": lambda: group_measure(torch, steps=a.truncate or 400)}
+    if a.only in only:
+        print(json.dumps(only[a.only]()))
         return
     w = wl.single_large(a.method, 8)
     if a.truncate:
@@ -245,14 +278,10 @@ def main():
         g = np.load(gold, allow_pickle=False)["cT"]
         err = float(np.linalg.norm(cT[0] - g) / np.linalg.norm(g))
 
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic_vec_tiles_L15_N500.json")
-    if os.path.exists(tfile):
-        with open(tfile) as fh:
-            traffic = json.load(fh).get("bytes_per_launch")
+    traffic = measured_traffic()
 
     out = {
-        "metric": "state-steps/s",
+        "metric": METRIC,
         "value": value,
         "unit": "state-steps/s",
         "n_gpus": 1,
@@ -277,6 +306,9 @@ def main():
         "wall_s_host": wall_s,
     }
     plan.close()
+    if a.only == "single":
+        print(json.dumps(out))
+        return
     if not a.no_diag:
         out["hbm_diagnostic"] = hbm_diagnostic(torch)
     if not a.no_batched:

@@ -67,9 +67,9 @@ __global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
         double v = 0.0;
         if (live && k < epl && e < 2 * n) {
             if (e < n) {  // row a of D_m
-                if (m < lmax) v = A.dip[(size_t)m * tile + (size_t)a * VEC_TILE_MAX + e];
+                if (m < lmax) v = A.dip[(size_t)m * tile + tile_pos(a, e)];
             } else {      // column a of D_{m-1}
-                if (m > 0) v = A.dip[(size_t)(m - 1) * tile + (size_t)(e - n) * VEC_TILE_MAX + a];
+                if (m > 0) v = A.dip[(size_t)(m - 1) * tile + tile_pos(e - n, a)];
             }
         }
         d[k] = v;

@@ -10,6 +10,7 @@
 
 #include "../../include/tdse.h"
 #include "tdse_split.h"
+#include "tdse_tile.h"
 
 namespace tdse {
 
@@ -81,9 +82,10 @@ struct CallDesc {
 constexpr int VEC_TILE_MAX = 128;   // max rows/cols of one dipole tile
 constexpr int VEC_THREADS = 512;    // 8 waves per tile workgroup
 
+
 struct VecBuffers {
     const double *en;      // [(lmax+1)*n]
-    const double *dip;     // tiles [lmax][T][T][VEC_TILE_MAX][VEC_TILE_MAX]
+    const double *dip;     // tiles [lmax][T][T][VEC_TILE_MAX * VEC_TILE_MAX], order tile_pos
     double2 *st[2][3];     // [parity][c, acc, u] each [(lmax+1)*n]
     double2 *rowp[2];      // [parity][lmax][T][T][VEC_TILE_MAX]
     double2 *colp[2];      // [parity][lmax][T(out seg j)][T(contrib i)][VEC_TILE_MAX]

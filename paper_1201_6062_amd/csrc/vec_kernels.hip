@@ -54,38 +54,6 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Cross-lane moves of a double through DPP (VALU, no LDS round trip).
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-    long long b = __double_as_longlong(v);
-    int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
-    int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// value of lane (lane ^ H), H in {1, 2, 4, 8}
-template <int H>
-__device__ __forceinline__ double xor_lane(double v) {
-    if constexpr (H == 1) return dpp_f64<0xB1>(v);                       // quad_perm(1,0,3,2)
-    else if constexpr (H == 2) return dpp_f64<0x4E>(v);                  // quad_perm(2,3,0,1)
-    else if constexpr (H == 4) return dpp_f64<0x141>(dpp_f64<0x1B>(v));  // half-row mirror of xor 3
-    else return dpp_f64<0x128>(v);                                       // row rotate by 8
-}
-
-// Butterfly step over lane bit H: lanes keep half of the values and add the
-// partner's copy of that half.
-template <int H>
-__device__ __forceinline__ void butterfly(double *tr, double *ti, int lane) {
-    const bool up = (lane & H) != 0;
-#pragma unroll
-    for (int k = 0; k < H; ++k) {
-        double sr = up ? tr[k] : tr[k + H], si = up ? ti[k] : ti[k + H];
-        double kr = up ? tr[k + H] : tr[k], ki = up ? ti[k + H] : ti[k];
-        tr[k] = kr + xor_lane<H>(sr);
-        ti[k] = ki + xor_lane<H>(si);
-    }
-}
-
 // y = H u_prev = E0 u + F z ; k = -i y. Then the RK4 / Taylor bookkeeping.
 __device__ __forceinline__ void apply_completion(const Completion &cp, double dt, double F,
                                                  double E0, double2 z, double2 &c,
@@ -159,24 +127,42 @@ __device__ __forceinline__ double field_of(const CallDesc *d, const VecLaunch &L
 // loads are unconditional (indices clamped into the buffer) and invalid terms
 // are dropped afterwards, so the loads issue back to back.
 template <int TP>
-__device__ __forceinline__ double2 sum_partials(const VecBuffers &b, int T, int par, bool rows, int m,
-                                                int q, int e) {
-    const bool valid = rows ? (m < b.lmax) : (m > 0);
+struct PartialLoads {
+    double2 v[TP];
+    bool valid;
+};
+
+template <int TP>
+__device__ __forceinline__ PartialLoads<TP> load_partials(const VecBuffers &b, int T, int par, bool rows, int m,
+                                                          int q, int e) {
+    PartialLoads<TP> p;
+    p.valid = rows ? (m < b.lmax) : (m > 0);
     const int hi = b.lmax > 0 ? b.lmax - 1 : 0;
     int mb = rows ? m : m - 1;
     mb = mb < 0 ? 0 : (mb > hi ? hi : mb);
     double2 *pr = rowp_ptr(b, par), *pc = colp_ptr(b, par);
     const double2 *base = (rows ? pr : pc) + ((size_t)(mb * T + q) * T) * VEC_TILE_MAX + e;
-    double2 v[TP];
 #pragma unroll
-    for (int k = 0; k < TP; ++k) v[k] = ld_nt(base + (size_t)(k < T ? k : T - 1) * VEC_TILE_MAX);
+    for (int k = 0; k < TP; ++k) p.v[k] = ld_nt(base + (size_t)(k < T ? k : T - 1) * VEC_TILE_MAX);
+    return p;
+}
+
+// Fixed-order sum of the loaded partials (contributions k = 0 .. T-1).
+template <int TP>
+__device__ __forceinline__ double2 add_partials(const PartialLoads<TP> &p, int T) {
     double zx = 0.0, zy = 0.0;
 #pragma unroll
     for (int k = 0; k < TP; ++k) {
-        zx += k < T ? v[k].x : 0.0;
-        zy += k < T ? v[k].y : 0.0;
+        zx += k < T ? p.v[k].x : 0.0;
+        zy += k < T ? p.v[k].y : 0.0;
     }
-    return valid ? make_double2(zx, zy) : make_double2(0.0, 0.0);
+    return p.valid ? make_double2(zx, zy) : make_double2(0.0, 0.0);
+}
+
+template <int TP>
+__device__ __forceinline__ double2 sum_partials(const VecBuffers &b, int T, int par, bool rows, int m,
+                                                int q, int e) {
+    return add_partials<TP>(load_partials<TP>(b, T, par, rows, m, q, e), T);
 }
 
 // Where (if anywhere) a launch's completion writes a checkpoint: the values
@@ -212,6 +198,30 @@ __device__ __forceinline__ void store_state(const VecBuffers &b, const VecLaunch
 // and B = (l+1, j) and produces this launch's row and column partials of
 // tile (l, i, j). T is the number of tiles per block dimension (a compile-time
 // constant where TP == T), F the field sample of the completed product.
+// Swap of 32-bit lane data between two registers: permlane32_swap exchanges
+// the upper 32 lanes of x with the lower 32 lanes of y, permlane16_swap the
+// odd 16-lane rows of x with the even rows of y. Adding the two results
+// reduces x over lane bit 5 (resp. 4) in the lanes where that bit is clear and
+// y in the lanes where it is set.
+template <int BIT>
+__device__ __forceinline__ double swap_reduce(double x, double y) {
+    const long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+    const unsigned xl = (unsigned)bx, xh = (unsigned)(bx >> 32), yl = (unsigned)by, yh = (unsigned)(by >> 32);
+    unsigned rl0, rl1, rh0, rh1;
+    if constexpr (BIT == 5) {
+        auto l = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+        auto h = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+        rl0 = l[0], rl1 = l[1], rh0 = h[0], rh1 = h[1];
+    } else {
+        auto l = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+        auto h = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+        rl0 = l[0], rl1 = l[1], rh0 = h[0], rh1 = h[1];
+    }
+    const double a = __longlong_as_double(((long long)rh0 << 32) | rl0);
+    const double c = __longlong_as_double(((long long)rh1 << 32) | rl1);
+    return a + c;
+}
+
 template <int TP>
 __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &L, int T, int l, int i, int j,
                                           int r0, int RA, int c0, int RB, double F, double dt,
@@ -221,8 +231,8 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
 
     __shared__ double2 uA[VEC_TILE_MAX], uB[VEC_TILE_MAX];
     __shared__ double2 zc[2 * VEC_TILE_MAX];
-    __shared__ double2 cpart[VEC_THREADS / 64][VEC_TILE_MAX];
-    __shared__ double2 rpart[VEC_THREADS / 64][4][16];
+    __shared__ double2 rbuf[VEC_THREADS / 64][VEC_TILE_MAX];  // [wave][row]
+    __shared__ double2 cbuf[VEC_TILE_MAX][17];                // [column][row class q], padded
 
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
@@ -237,26 +247,30 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
     const int m = isB ? l + 1 : l, q = isB ? j : i, len = isB ? RB : RA, s0 = isB ? c0 : r0;
     const int ec = e < len ? e : len - 1;
     const size_t gi = (size_t)m * n + s0 + ec;
-    const double2 zpart = sum_partials<TP>(b, T, par, half == 0, m, q, ec);
+    const PartialLoads<TP> pl = load_partials<TP>(b, T, par, half == 0, m, q, ec);
     const double2 c_in = ld_nt(st_ptr(b, par, 0) + gi), acc_in = ld_nt(st_ptr(b, par, 1) + gi);
     const double2 u_in = ld_nt(st_ptr(b, par, 2) + gi);
     const double E0 = __builtin_nontemporal_load(b.en + gi);
 
-    // ---- tile loads. Tiles are stored blocked with a 128-double row pitch,
-    // zero-padded beyond RB columns: lane L reads columns 2L, 2L+1 of a row
-    // (16 B per lane, 1 KB per wave and row).
-    const int a0 = wv * 16;
+    // ---- tile loads (stored in lane order, tile_pos): load jj of wave wv
+    // reads 64 consecutive double2, one per lane. Rows and columns past the
+    // segment are stored as zeros.
     const double2 *Dt = reinterpret_cast<const double2 *>(b.dip) +
-                        (size_t)tile * (VEC_TILE_MAX * VEC_TILE_MAX / 2) + lane;
-    // Rows past RA re-read row RA-1 (an L1 hit) and are zeroed afterwards, so
-    // the loads are unconditional and the prologue can wait for its own loads
-    // while these are still in flight.
+                        (size_t)tile * (VEC_TILE_MAX * VEC_TILE_MAX / 2) + wv * 16 * 64 + lane;
+    // The partial sums wait for the partial loads only (issued first); they
+    // are placed after the first EARLY tile loads are in flight, so the tile
+    // stream is not held back by the prologue. With 8 partials per entry the
+    // remaining loads are issued after the sum to stay within 128 VGPRs (with
+    // 16 partials, all of them).
+    constexpr int EARLY = TP <= 4 ? 16 : (TP <= 8 ? 8 : 0);
     double2 dv[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int a = a0 + r < RA ? a0 + r : RA - 1;
-        dv[r] = Dt[(size_t)a * (VEC_TILE_MAX / 2)];
-    }
+    for (int r = 0; r < EARLY; ++r) dv[r] = Dt[r * 64];
+    __builtin_amdgcn_sched_barrier(0);
+    const double2 zpart = add_partials<TP>(pl, T);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = EARLY; r < 16; ++r) dv[r] = Dt[r * 64];
 
     // ---- completion of the previous product (overlaps the tile stream).
     if (half == 1) zc[pe] = zpart;
@@ -274,48 +288,65 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
     }
     lds_barrier();
 
-    // ---- tile products.
+    // ---- tile products. Lane (h, qq) holds rows qq + 16k and columns
+    // cb .. cb+3: dv[2k] = D[row k][cb, cb+1], dv[2k+1] = D[row k][cb+2, cb+3].
+    const int h = lane >> 4, qq = lane & 15;
+    const int cb = wv * 16 + 4 * h;
+    const double2 ub0 = uB[cb], ub1 = uB[cb + 1], ub2 = uB[cb + 2], ub3 = uB[cb + 3];
+    double2 cp[4];
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-        if (a0 + r >= RA) dv[r] = make_double2(0.0, 0.0);
-    const double2 ub0 = uB[2 * lane], ub1 = uB[2 * lane + 1];
-    double2 cp0 = make_double2(0.0, 0.0), cp1 = make_double2(0.0, 0.0);
-    double tr[16], ti[16];
+    for (int c = 0; c < 4; ++c) cp[c] = make_double2(0.0, 0.0);
+    double tr[8], ti[8];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const double2 ua = uA[a0 + r];
-        cp0.x = fma(dv[r].x, ua.x, cp0.x);
-        cp0.y = fma(dv[r].x, ua.y, cp0.y);
-        cp1.x = fma(dv[r].y, ua.x, cp1.x);
-        cp1.y = fma(dv[r].y, ua.y, cp1.y);
-        tr[r] = fma(dv[r].y, ub1.x, dv[r].x * ub0.x);
-        ti[r] = fma(dv[r].y, ub1.y, dv[r].x * ub0.y);
+    for (int k = 0; k < 8; ++k) {
+        const double2 d01 = dv[2 * k], d23 = dv[2 * k + 1];
+        const double2 ua = uA[qq + 16 * k];
+        tr[k] = fma(d23.y, ub3.x, fma(d23.x, ub2.x, fma(d01.y, ub1.x, d01.x * ub0.x)));
+        ti[k] = fma(d23.y, ub3.y, fma(d23.x, ub2.y, fma(d01.y, ub1.y, d01.x * ub0.y)));
+        cp[0].x = fma(d01.x, ua.x, cp[0].x);
+        cp[0].y = fma(d01.x, ua.y, cp[0].y);
+        cp[1].x = fma(d01.y, ua.x, cp[1].x);
+        cp[1].y = fma(d01.y, ua.y, cp[1].y);
+        cp[2].x = fma(d23.x, ua.x, cp[2].x);
+        cp[2].y = fma(d23.x, ua.y, cp[2].y);
+        cp[3].x = fma(d23.y, ua.x, cp[3].x);
+        cp[3].y = fma(d23.y, ua.y, cp[3].y);
     }
-    // Transpose-reduce the 16 row partials over each 16-lane group: after the
-    // xor-8/4/2/1 exchanges lane L holds row (L & 15) summed over its group;
-    // the four groups are added through LDS below.
-    butterfly<8>(tr, ti, lane);
-    butterfly<4>(tr, ti, lane);
-    butterfly<2>(tr, ti, lane);
-    butterfly<1>(tr, ti, lane);
-    rpart[wv][lane >> 4][lane & 15] = make_double2(tr[0], ti[0]);
-    cpart[wv][2 * lane] = cp0;
-    cpart[wv][2 * lane + 1] = cp1;
+    // Row partials over the wave's 16 columns: reduce over lane bits 5 and 4
+    // (the four column groups h). Afterwards a lane holds rows
+    // qq + 16 (k + 2 bit4 + 4 bit5), k = 0, 1.
+    double sr[4], si[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        sr[k] = swap_reduce<5>(tr[k], tr[k + 4]);
+        si[k] = swap_reduce<5>(ti[k], ti[k + 4]);
+    }
+    const int rcls = 2 * (h & 1) + 4 * (h >> 1);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double zr = swap_reduce<4>(sr[k], sr[k + 2]), zi = swap_reduce<4>(si[k], si[k + 2]);
+        rbuf[wv][qq + 16 * (k + rcls)] = make_double2(zr, zi);
+    }
+    // Column partials over the lane's 8 rows, per row class qq.
+#pragma unroll
+    for (int c = 0; c < 4; ++c) cbuf[cb + c][qq] = cp[c];
     lds_barrier();
 
     const int npar = par ^ 1;
     if (t < VEC_TILE_MAX) {
-        if (t < RB) {  // column partial of column t: sum over the 8 waves' rows
-            double2 s = cpart[0][t];
+        if (t < RB) {  // column partial of column t: sum over the 16 row classes
+            double2 s = cbuf[t][0];
 #pragma unroll
-            for (int k = 1; k < VEC_THREADS / 64; ++k) s = cadd(s, cpart[k][t]);
+            for (int k = 1; k < 16; ++k) s = cadd(s, cbuf[t][k]);
             double2 *cpo = colp_ptr(b, npar) + ((size_t)(l * T + j) * T + i) * VEC_TILE_MAX;
             st_nt(cpo + t, s);
         }
-    } else if (t < 2 * VEC_TILE_MAX) {  // row partial of row a: sum over the 4 lane groups
-        const int a = t - VEC_TILE_MAX, rw = a >> 4, rr = a & 15;
+    } else if (t < 2 * VEC_TILE_MAX) {  // row partial of row a: sum over the 8 waves' columns
+        const int a = t - VEC_TILE_MAX;
         if (a < RA) {
-            double2 s = cadd(cadd(rpart[rw][0][rr], rpart[rw][1][rr]), cadd(rpart[rw][2][rr], rpart[rw][3][rr]));
+            double2 s = rbuf[0][a];
+#pragma unroll
+            for (int k = 1; k < VEC_THREADS / 64; ++k) s = cadd(s, rbuf[k][a]);
             double2 *rp = rowp_ptr(b, npar) + ((size_t)(l * T + i) * T + j) * VEC_TILE_MAX;
             st_nt(rp + a, s);
         }
@@ -346,7 +377,7 @@ __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
                                                                  int64_t round, double dt) {
     const GroupTile gt = tiles[blockIdx.x];
     const GroupInst &gi = insts[gt.inst];
-    const VecBuffers b = gi.b;
+    const VecBuffers &b = gi.b;  // read in place: a local copy would be indexed through scratch
     // RK4 launch schedule: launch 4k+s completes stage s of step k (stage 4 of
     // step k-1 for s == 0) and forms the input of the next stage.
     const int s = (int)(round & 3);
@@ -417,14 +448,16 @@ __global__ void vec_start_kernel(VecBuffers b, int par, const double2 *c0, int t
 }
 
 // Re-layout of the caller's row-major blocks [lmax][n][n] into tiles
-// [lmax][T][T][VEC_TILE_MAX][VEC_TILE_MAX], zero outside each tile's extent.
+// [lmax][T][T][VEC_TILE_MAX * VEC_TILE_MAX] in tile_pos order, zero outside
+// each tile's extent.
 __global__ void vec_layout_kernel(const double *src, double *dst, int lmax, int n, int T) {
     const size_t tile_elems = (size_t)VEC_TILE_MAX * VEC_TILE_MAX;
     const size_t total = (size_t)lmax * T * T * tile_elems;
     for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
          g += (size_t)gridDim.x * blockDim.x) {
         const size_t tile = g / tile_elems, w = g - tile * tile_elems;
-        const int a = (int)(w / VEC_TILE_MAX), bcol = (int)(w % VEC_TILE_MAX);
+        int a, bcol;
+        tile_elem((int64_t)w, &a, &bcol);
         const int l = (int)(tile / (T * T)), rem = (int)(tile % (T * T)), i = rem / T, j = rem % T;
         const int RA = (int)split_len(n, T, i), RB = (int)split_len(n, T, j);
         double v = 0.0;
@@ -448,7 +481,7 @@ __global__ void vec_untile_kernel(const double *tiles, double *dst, int lmax, in
         while (i + 1 < T && split_start(n, T, i + 1) <= r) ++i;
         while (j + 1 < T && split_start(n, T, j + 1) <= c) ++j;
         const int a = r - (int)split_start(n, T, i), bcol = c - (int)split_start(n, T, j);
-        dst[g] = tiles[(((size_t)l * T + i) * T + j) * VEC_TILE_MAX * VEC_TILE_MAX + (size_t)a * VEC_TILE_MAX + bcol];
+        dst[g] = tiles[(((size_t)l * T + i) * T + j) * VEC_TILE_MAX * VEC_TILE_MAX + tile_pos(a, bcol)];
     }
 }
 

@@ -1,10 +1,12 @@
-// Host-only checks of the library's argument validation and work split.
+// Host-only checks of the library's argument validation, work split and
+// dipole tile order.
 // Built with g++ (no HIP) by tests/test_abi_cpu.py; prints one line per
 // failed check and exits non-zero if any failed.
 #include <math.h>
 #include <stdio.h>
 
 #include "tdse_split.h"
+#include "tdse_tile.h"
 #include "tdse_validate.h"
 
 static int fails = 0;
@@ -26,6 +28,26 @@ int main() {
             CHECK(pos == w);
             CHECK(mx - mn <= 1);
         }
+    // Tile order: a bijection of [0,128)^2 onto [0,16384); lane (h, q) of
+    // wave w reads double2 number 64 (16 w + jj) + 16 h + q in load jj and
+    // finds rows q + 16k, columns 16w + 4h + c there.
+    {
+        static int seen[128 * 128];
+        for (int a = 0; a < 128; ++a)
+            for (int b = 0; b < 128; ++b) {
+                const int64_t p = tile_pos(a, b);
+                CHECK(p >= 0 && p < 128 * 128);
+                if (p < 0 || p >= 128 * 128) continue;
+                ++seen[p];
+                int a2 = -1, b2 = -1;
+                tile_elem(p, &a2, &b2);
+                CHECK(a2 == a && b2 == b);
+                const int64_t d2 = p >> 1, lane = d2 & 63, w = d2 >> 10, jj = (d2 >> 6) & 15;
+                CHECK((lane & 15) == (a & 15) && jj / 2 == a / 16);
+                CHECK(w == b / 16 && (lane >> 4) == (b % 16) / 4 && 2 * (jj & 1) + (p & 1) == b % 4);
+            }
+        for (int p = 0; p < 128 * 128; ++p) CHECK(seen[p] == 1);
+    }
     std::string why;
     int dummy = 0;
     CHECK(validate_create(nullptr, &dummy, &dummy, 1, 1, 1, &why) == TDSE_E_INVAL);

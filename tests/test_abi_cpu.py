@@ -97,7 +97,7 @@ def test_adjoint_and_group_argument_errors(lib):
 
 
 def test_host_logic_native(tmp_path):
-    """Argument rules and the Sec. 4.1 work split, compiled host-only with g++."""
+    """Argument rules, the Sec. 4.1 work split and the tile order, compiled host-only with g++."""
     import subprocess
     csrc = os.path.join(ROOT, "paper_1201_6062_amd", "csrc")
     exe = str(tmp_path / "host_logic")

@@ -124,3 +124,40 @@ def test_adjoint_vs_central_fd_batched_perturbations():
     fd = (y[0::2] - y[1::2]) / (2 * hstep)
     ga = np.array([g.flat[i] for i in idx])
     assert np.abs(ga - fd).max() <= 1e-6 * np.abs(fd).max(), (ga, fd)
+
+
+def test_adjoint_full_size_piecewise():
+    """Lmax=15, N=500, 32 pulses of 2048 piecewise-constant samples (32768 RK4
+    steps, dt=0.01, checkpoints every 64 steps): pulses 0 and 31 vs the stored
+    full-length oracle adjoint; 16 sampled dY/dE_k of pulse 0 vs central
+    differences, the 32 perturbed runs forming one batch of 32."""
+    h = wl.hamiltonian(15, 500, 0)
+    pulses = wl.adjoint_pulses(32)
+    spi = wl.ADJ_STEPS_PER_INTERVAL
+    ek = np.stack([wl.piecewise_samples(p) for p in pulses])
+    f = wl.expand_piecewise(ek, spi)
+    c0 = wl.ground_state(15, 500, 32)
+    dt = 0.01
+    plan = make_plan(h, 32)
+    cT, ck = plan.propagate(f, c0, dt, "rk4", ckpt_every=64)
+    g, l0 = plan.adjoint(f, c0, dt, yield_seed_dev(plan, cT), ckpt=ck, ckpt_every=64)
+    del ck
+    gk = wl.collapse_piecewise(g.cpu().numpy(), spi)
+    l0, cT = l0.cpu().numpy(), cT.cpu().numpy()
+    for b in (0, 31):
+        gold = np.load(os.path.join(HERE, "golden", f"adjoint_pulse{b:02d}.npz"), allow_pickle=False)
+        assert np.linalg.norm(cT[b] - gold["cT"]) <= 1e-10 * np.linalg.norm(gold["cT"]), b
+        assert np.abs(gk[b] - gold["grad_k"]).max() <= 1e-10 * np.abs(gold["grad_k"]).max(), b
+        assert np.abs(l0[b] - gold["lam0"]).max() <= 1e-10 * np.abs(gold["lam0"]).max(), b
+    # central differences on pulse 0: the 8 largest |dY/dE_k| and 8 evenly spaced k
+    idx = np.argsort(-np.abs(gk[0]))[:8].tolist() + np.linspace(0, wl.ADJ_INTERVALS - 1, 8).astype(int).tolist()
+    hstep = 1e-6
+    ep = np.repeat(ek[:1], 32, axis=0)
+    for q, k in enumerate(idx):
+        ep[2 * q, k] += hstep
+        ep[2 * q + 1, k] -= hstep
+    yT = plan.propagate(wl.expand_piecewise(ep, spi), c0, dt, "rk4").cpu().numpy()
+    y = oracle.ionization_yield(h.energies, yT)
+    fd = (y[0::2] - y[1::2]) / (2 * hstep)
+    ga = gk[0, idx]
+    assert np.abs(ga - fd).max() <= 1e-6 * np.abs(fd).max(), (ga, fd)
