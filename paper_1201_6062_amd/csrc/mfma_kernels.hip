@@ -41,9 +41,78 @@ struct BatTile {
     static constexpr int THREADS = 256;
     static constexpr int WM = TM / 2, WN = TN / 2;       // 2 x 2 waves
     static constexpr int SM = WM / 16, SN = WN / 16;     // 16 x 16 subtiles per wave
-    static constexpr int A_ELEMS = KC * TM, B_ELEMS = KC * TN;
-    static constexpr int A_PER_T = A_ELEMS / 2 / THREADS, B_PER_T = B_ELEMS / 2 / THREADS;  // double2 each
+    // The K panels go from global memory straight into LDS (global_load_lds):
+    // one instruction moves 64 lanes x 16 B = 1 KB, i.e. 128 / TM rows of the
+    // A panel (128 / TN rows of B). Each such group of rows is followed by
+    // 128 B of padding, so the four 16-lane row groups of a fragment read
+    // fall into two LDS bank sets.
+    static constexpr int A_RPI = 128 / TM, B_RPI = 128 / TN;
+    static constexpr int GROUP = 1024 + 128;
+    static constexpr int A_GROUPS = KC / A_RPI, B_GROUPS = KC / B_RPI;
+    static constexpr int A_PER_W = A_GROUPS / 4, B_PER_W = B_GROUPS / 4;  // instructions per wave
+    static constexpr int A_BYTES = A_GROUPS * GROUP, B_BYTES = B_GROUPS * GROUP;
 };
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// byte offset of element (k, x) of a staged panel with rows of W doubles
+template <int W>
+__device__ __forceinline__ int panel_off(int k, int x) {
+    constexpr int RPI = 128 / W;
+    return (k / RPI) * (1024 + 128) + ((k % RPI) * W + x) * 8;
+}
+
+// One K chunk of a workgroup: start the direct-to-LDS loads of the next
+// chunk into (wa, wb) when wa is non-null -- wave wv moves row groups
+// wv, wv+4, ... of both panels -- then run the chunk's MFMAs from (la, lb)
+// when la is non-null. The restrict qualifiers tell the compiler that the
+// panels being read and the ones being filled do not overlap, so it does
+// not wait for the new loads before reading the current panels.
+template <int TM, int TN, int KC>
+__device__ __forceinline__ void bat_chunk(const char *__restrict__ la, const char *__restrict__ lb,
+                                          char *__restrict__ wa, char *__restrict__ wb,
+                                          const double *__restrict__ pa, const double *__restrict__ pb,
+                                          int Np, int ldu, int lane, int wv,
+                                          d4_t (&acc)[BatTile<TM, TN, KC>::SM][BatTile<TM, TN, KC>::SN]) {
+    using C = BatTile<TM, TN, KC>;
+    if (wa) {
+#pragma unroll
+        for (int q = 0; q < C::A_PER_W; ++q) {
+            const int g = wv + 4 * q, k = g * C::A_RPI + lane / (TM / 2), x = 2 * (lane % (TM / 2));
+            __builtin_amdgcn_global_load_lds((const void *)(pa + (size_t)k * Np + x),
+                                             (lds_void_t *)(wa + g * C::GROUP), 16, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < C::B_PER_W; ++q) {
+            const int g = wv + 4 * q, k = g * C::B_RPI + lane / (TN / 2), x = 2 * (lane % (TN / 2));
+            __builtin_amdgcn_global_load_lds((const void *)(pb + (size_t)k * ldu + x),
+                                             (lds_void_t *)(wb + g * C::GROUP), 16, 0, 0);
+        }
+    }
+    if (!la) return;
+    const int wy = wv >> 1, wx = wv & 1;
+    // fragments of k-step ks+1 are read while the products of ks run
+    double af[2][C::SM], bf[2][C::SN];
+    auto frag = [&](int ks, int slot) {
+        const int kr = ks * 4 + (lane >> 4);
+#pragma unroll
+        for (int i = 0; i < C::SM; ++i)
+            af[slot][i] = *reinterpret_cast<const double *>(la + panel_off<TM>(kr, wy * C::WM + i * 16 + (lane & 15)));
+#pragma unroll
+        for (int j = 0; j < C::SN; ++j)
+            bf[slot][j] = *reinterpret_cast<const double *>(lb + panel_off<TN>(kr, wx * C::WN + j * 16 + (lane & 15)));
+    };
+    frag(0, 0);
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+        if (ks + 1 < KC / 4) frag(ks + 1, (ks + 1) & 1);
+#pragma unroll
+        for (int i = 0; i < C::SM; ++i)
+#pragma unroll
+            for (int j = 0; j < C::SN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks & 1][i], bf[ks & 1][j], acc[i][j], 0, 0, 0);
+    }
+}
 
 // ADJ = false: forward RK4 / Taylor stage (or a single product).
 // ADJ = true: one stage of the discrete adjoint of an RK4 step, run in
@@ -54,7 +123,8 @@ struct BatTile {
 template <int TM, int TN, int KC, bool ADJ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void bat_stage_kernel(BatBuffers b, BatLaunch L) {
     using C = BatTile<TM, TN, KC>;
-    static_assert(C::A_PER_T >= 1 && C::B_PER_T >= 1, "tile too small for 256 threads");
+    static_assert(C::A_PER_W >= 1 && C::B_PER_W >= 1 && C::A_GROUPS % 4 == 0 && C::B_GROUPS % 4 == 0,
+                  "panel groups must split evenly over the 4 waves");
     const int Np = b.np, ldu = b.ldu, lmax = b.lmax;
     const int RT = Np / TM, CT = ldu / TN;
     const int ntiles = (lmax + 1) * RT * CT;
@@ -64,8 +134,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     const int m = tile / (RT * CT), rem = tile - m * RT * CT, rt = rem / CT, ct = rem - rt * CT;
     const int r0 = rt * TM, c0 = ct * TN;
 
-    __shared__ double As[2][KC][TM];
-    __shared__ double Bs[2][KC][TN];
+    __shared__ __attribute__((aligned(16))) char lds_a[2][C::A_BYTES];
+    __shared__ __attribute__((aligned(16))) char lds_b[2][C::B_BYTES];
 
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int wy = wv >> 1, wx = wv & 1;
@@ -79,6 +149,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     const int nchunks = kchunks * ((has_up ? 1 : 0) + (has_dn ? 1 : 0));
     const size_t blk = (size_t)Np * Np;
 
+    // Panel sources of chunk kc.
     auto a_src = [&](int kc) -> const double * {
         const bool up = has_up && kc < kchunks;
         const int k0 = (up ? kc : kc - (has_up ? kchunks : 0)) * KC;
@@ -88,35 +159,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     auto b_src = [&](int kc) -> const double * {
         const bool up = has_up && kc < kchunks;
         const int k0 = (up ? kc : kc - (has_up ? kchunks : 0)) * KC;
-        const int lb = up ? m + 1 : m - 1;
-        return U + ((size_t)lb * Np + k0) * ldu + c0;
-    };
-
-    double2 ra[C::A_PER_T], rb[C::B_PER_T];
-    auto gload = [&](int kc) {
-        const double *pa = a_src(kc), *pb = b_src(kc);
-#pragma unroll
-        for (int q = 0; q < C::A_PER_T; ++q) {
-            const int e = t + C::THREADS * q, k = e / (TM / 2), i2 = e % (TM / 2);
-            ra[q] = *reinterpret_cast<const double2 *>(pa + (size_t)k * Np + 2 * i2);
-        }
-#pragma unroll
-        for (int q = 0; q < C::B_PER_T; ++q) {
-            const int e = t + C::THREADS * q, k = e / (TN / 2), j2 = e % (TN / 2);
-            rb[q] = *reinterpret_cast<const double2 *>(pb + (size_t)k * ldu + 2 * j2);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < C::A_PER_T; ++q) {
-            const int e = t + C::THREADS * q, k = e / (TM / 2), i2 = e % (TM / 2);
-            *reinterpret_cast<double2 *>(&As[buf][k][2 * i2]) = ra[q];
-        }
-#pragma unroll
-        for (int q = 0; q < C::B_PER_T; ++q) {
-            const int e = t + C::THREADS * q, k = e / (TN / 2), j2 = e % (TN / 2);
-            *reinterpret_cast<double2 *>(&Bs[buf][k][2 * j2]) = rb[q];
-        }
+        return U + ((size_t)(up ? m + 1 : m - 1) * Np + k0) * ldu + c0;
     };
 
     d4_t acc[C::SM][C::SN];
@@ -126,30 +169,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
         for (int j = 0; j < C::SN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
     if (nchunks > 0) {
-        gload(0);
-        sstore(0);
+        bat_chunk<TM, TN, KC>(nullptr, nullptr, lds_a[0], lds_b[0], a_src(0), b_src(0), Np, ldu, lane, wv, acc);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         bat_lds_barrier();
         for (int kc = 0; kc < nchunks; ++kc) {
             const int buf = kc & 1;
-            if (kc + 1 < nchunks) gload(kc + 1);
-#pragma unroll
-            for (int ks = 0; ks < KC / 4; ++ks) {
-                const int kr = ks * 4 + (lane >> 4);
-                double af[C::SM], bf[C::SN];
-#pragma unroll
-                for (int i = 0; i < C::SM; ++i) af[i] = As[buf][kr][wy * C::WM + i * 16 + (lane & 15)];
-#pragma unroll
-                for (int j = 0; j < C::SN; ++j) bf[j] = Bs[buf][kr][wx * C::WN + j * 16 + (lane & 15)];
-#pragma unroll
-                for (int i = 0; i < C::SM; ++i)
-#pragma unroll
-                    for (int j = 0; j < C::SN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-            }
-            if (kc + 1 < nchunks) {
-                sstore(buf ^ 1);
-                bat_lds_barrier();
-            }
+            const bool next = kc + 1 < nchunks;
+            bat_chunk<TM, TN, KC>(lds_a[buf], lds_b[buf], next ? lds_a[buf ^ 1] : nullptr,
+                                  next ? lds_b[buf ^ 1] : nullptr, next ? a_src(kc + 1) : nullptr,
+                                  next ? b_src(kc + 1) : nullptr, Np, ldu, lane, wv, acc);
+            // the next chunk's panels have landed and every wave is done with this one
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            bat_lds_barrier();
         }
     }
 
