@@ -80,7 +80,15 @@ static hipError_t enqueue_steps(tdse_plan p, tdse_method m, int order, int64_t n
             L.off = (int32_t)k;
             L.parity = parity;
             L.slots = m == TDSE_RK4 ? 3 : 1;
-            hipError_t e = p->lmax > 0 ? vec_launch_tiles(p->vb, L, s) : vec_launch_combine(p->vb, L, s);
+            hipError_t e;
+            if (p->lmax == 0) {
+                e = vec_launch_combine(p->vb, L, s);
+            } else if (p->split) {
+                e = vec_launch_combine(p->vb, L, s);
+                if (e == hipSuccess) e = vec_launch_products(p->vb, L, s);
+            } else {
+                e = vec_launch_tiles(p->vb, L, s);
+            }
             if (e != hipSuccess) return e;
             parity ^= 1;
         }
@@ -536,6 +544,15 @@ tdse_status create_plan(tdse_plan *out, const double *energies, const double *di
         // a forced tile count selects the tiled kernels even for small problems
         p->small = tc.T == 0 && small_eligible(lmax, n);
     }
+    // Beyond two tile workgroups per CU the product launches stream the dipole
+    // from HBM, and re-reading every segment's partials in each of its T
+    // tiles would add (T + 3) / 64 of the dipole traffic: completion then runs
+    // once per segment in a launch of its own. $TDSE_SPLIT=0/1 overrides.
+    p->split = (int64_t)lmax * p->T * p->T > 512;
+    if (const char *sp = getenv("TDSE_SPLIT")) {
+        if (sp[0] == '0') p->split = false;
+        if (sp[0] == '1') p->split = true;
+    }
     if (p->T > 16) {
         delete p;
         return fail(TDSE_E_UNSUPPORTED, "n > 2048 states per partial wave is not supported");
@@ -733,8 +750,9 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
     }
     std::stable_sort(order_idx.begin(), order_idx.end(), [&](int a, int b) { return nsteps[a] > nsteps[b]; });
     g->tiles.clear();
+    g->segs.clear();
     g->insts.clear();
-    std::vector<int64_t> prefix(1, 0);
+    std::vector<int64_t> prefix(1, 0), seg_prefix(1, 0);
     for (size_t q = 0; q < order_idx.size(); ++q) {
         const tdse_plan p = g->plans[order_idx[q]];
         GroupInst gi{};
@@ -745,7 +763,10 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
         for (int l = 0; l < p->lmax; ++l)
             for (int i = 0; i < p->T; ++i)
                 for (int j = 0; j < p->T; ++j) g->tiles.push_back({(int32_t)q, (int16_t)l, (int8_t)i, (int8_t)j});
+        for (int mm = 0; mm <= p->lmax; ++mm)
+            for (int qq = 0; qq < p->T; ++qq) g->segs.push_back({(int32_t)q, (int16_t)mm, (int16_t)qq});
         prefix.push_back((int64_t)g->tiles.size());
+        seg_prefix.push_back((int64_t)g->segs.size());
     }
     if (order_idx.empty()) return TDSE_OK;
     if (g->tiles.size() > g->tiles_cap) {
@@ -757,6 +778,16 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
             return fail(TDSE_E_NOMEM, "hipMalloc of the group work list failed");
         }
         g->tiles_cap = g->tiles.size();
+    }
+    if (g->segs.size() > g->segs_cap) {
+        if (g->d_segs) (void)hipFree(g->d_segs);
+        g->d_segs = nullptr;
+        g->segs_cap = 0;
+        if (hipMalloc(&g->d_segs, g->segs.size() * sizeof(GroupSeg)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(TDSE_E_NOMEM, "hipMalloc of the group segment list failed");
+        }
+        g->segs_cap = g->segs.size();
     }
     if (g->insts.size() > g->insts_cap) {
         if (g->d_insts) (void)hipFree(g->d_insts);
@@ -770,6 +801,8 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
     }
     TDSE_HIP(hipMemcpyAsync(g->d_tiles, g->tiles.data(), g->tiles.size() * sizeof(GroupTile),
                             hipMemcpyHostToDevice, s));
+    TDSE_HIP(hipMemcpyAsync(g->d_segs, g->segs.data(), g->segs.size() * sizeof(GroupSeg),
+                            hipMemcpyHostToDevice, s));
     TDSE_HIP(hipMemcpyAsync(g->d_insts, g->insts.data(), g->insts.size() * sizeof(GroupInst),
                             hipMemcpyHostToDevice, s));
     for (int k : order_idx) TDSE_HIP(vec_launch_start(g->plans[k]->vb, 0, c0[k], TDSE_RK4, s));
@@ -778,7 +811,8 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
     for (int64_t r = 0; r < rounds; ++r) {
         while (active > 0 && 4 * nsteps[order_idx[active - 1]] <= r) --active;
         const int64_t nt = prefix[active];
-        if (nt > 0) TDSE_HIP(group_launch_round(g->d_tiles, (int)nt, g->d_insts, r, dt, s));
+        if (nt > 0)
+            TDSE_HIP(group_launch_round(g->d_segs, (int)seg_prefix[active], g->d_tiles, (int)nt, g->d_insts, r, dt, s));
     }
     // final completion of every instance (c(T) -> cT)
     for (int k : order_idx) {
@@ -809,6 +843,7 @@ tdse_status tdse_group_destroy(tdse_group g) {
     if (!g) return TDSE_OK;
     (void)hipDeviceSynchronize();
     if (g->d_tiles) (void)hipFree(g->d_tiles);
+    if (g->d_segs) (void)hipFree(g->d_segs);
     if (g->d_insts) (void)hipFree(g->d_insts);
     delete g;
     return TDSE_OK;

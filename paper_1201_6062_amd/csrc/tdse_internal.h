@@ -109,6 +109,11 @@ struct GroupTile {
     int16_t l;              // block of the tile
     int8_t i, j;            // row / column segment
 };
+struct GroupSeg {
+    int32_t inst;           // instance (index into the GroupInst array)
+    int16_t m;              // block of the segment
+    int16_t q;              // segment index within the block
+};
 struct GroupInst {
     VecBuffers b;           // the instance plan's buffers (its own T and segments)
     const double *field;    // [nsteps][3]
@@ -120,11 +125,15 @@ hipError_t small_propagate(const double *en, const double *dip, int lmax, int n,
                            int64_t nsteps, const double *field, const double *c0, double *cT, double *ckpt,
                            int64_t ckpt_every, hipStream_t s);
 
-hipError_t group_launch_round(const GroupTile *tiles, int ntiles, const GroupInst *insts, int64_t round,
-                              double dt, hipStream_t s);
+// One RK4 stage-round of a group: completion over the segment list, then
+// the tile products over the tile list.
+hipError_t group_launch_round(const GroupSeg *segs, int nsegs, const GroupTile *tiles, int ntiles,
+                              const GroupInst *insts, int64_t round, double dt, hipStream_t s);
 
 hipError_t vec_launch_tiles(const VecBuffers &b, const VecLaunch &l, hipStream_t s);
 hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream_t s);
+// Split path: products only, inputs completed by a preceding vec_launch_combine.
+hipError_t vec_launch_products(const VecBuffers &b, const VecLaunch &l, hipStream_t s);
 hipError_t vec_launch_start(const VecBuffers &b, int32_t parity, const double *c0, int32_t method,
                             hipStream_t s);
 hipError_t chunk_begin(CallDesc *d, int64_t base, hipStream_t s);
@@ -196,10 +205,12 @@ struct tdse_group_s {
     // work list and instance table of the last call (host copies stay alive
     // until the next call, so the asynchronous uploads can read them)
     std::vector<tdse::GroupTile> tiles;
+    std::vector<tdse::GroupSeg> segs;
     std::vector<tdse::GroupInst> insts;
     tdse::GroupTile *d_tiles = nullptr;
+    tdse::GroupSeg *d_segs = nullptr;
     tdse::GroupInst *d_insts = nullptr;
-    size_t tiles_cap = 0, insts_cap = 0;
+    size_t tiles_cap = 0, segs_cap = 0, insts_cap = 0;
 };
 
 struct tdse_plan_s {
@@ -212,6 +223,7 @@ struct tdse_plan_s {
     // single-vector path
     int32_t T = 1;
     bool small = false;          // whole propagation in one workgroup
+    bool split = false;          // separate completion and product launches (large problems)
     double *scratch = nullptr;   // one allocation holding states, partials, descriptor
     size_t scratch_bytes = 0;
     tdse::VecBuffers vb{};

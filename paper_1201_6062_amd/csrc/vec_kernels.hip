@@ -194,10 +194,6 @@ __device__ __forceinline__ void store_state(const VecBuffers &b, const VecLaunch
     if (ct.slot) st_global(ct.slot + gi, c);
 }
 
-// One tile workgroup: completes the previous product for segments A = (l, i)
-// and B = (l+1, j) and produces this launch's row and column partials of
-// tile (l, i, j). T is the number of tiles per block dimension (a compile-time
-// constant where TP == T), F the field sample of the completed product.
 // Swap of 32-bit lane data between two registers: permlane32_swap exchanges
 // the upper 32 lanes of x with the lower 32 lanes of y, permlane16_swap the
 // odd 16-lane rows of x with the even rows of y. Adding the two results
@@ -222,6 +218,91 @@ __device__ __forceinline__ double swap_reduce(double x, double y) {
     return a + c;
 }
 
+// LDS of a tile workgroup.
+struct TileLds {
+    double2 uA[VEC_TILE_MAX], uB[VEC_TILE_MAX];    // product inputs: segments (l, i), (l+1, j)
+    double2 zc[2 * VEC_TILE_MAX];                  // column-partial sums for the completing threads
+    double2 rbuf[VEC_THREADS / 64][VEC_TILE_MAX];  // [wave][row]
+    double2 cbuf[VEC_TILE_MAX][17];                // [column][row class], padded
+};
+
+// Tile products of workgroup (l, i, j) from the tile data dv (tile_pos
+// order, this lane's 16 loads) and the inputs in lds.uA / lds.uB: writes the
+// row partials (towards z_l, rows i) and column partials (towards z_{l+1},
+// columns j) to the partial buffers of parity npar.
+__device__ __forceinline__ void tile_products(const VecBuffers &b, TileLds &lds, const double2 (&dv)[16], int T,
+                                              int l, int i, int j, int RA, int RB, int npar) {
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    // ---- tile products. Lane (h, qq) holds rows qq + 16k and columns
+    // cb .. cb+3: dv[2k] = D[row k][cb, cb+1], dv[2k+1] = D[row k][cb+2, cb+3].
+    const int h = lane >> 4, qq = lane & 15;
+    const int cb = wv * 16 + 4 * h;
+    const double2 ub0 = lds.uB[cb], ub1 = lds.uB[cb + 1], ub2 = lds.uB[cb + 2], ub3 = lds.uB[cb + 3];
+    double2 cp[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) cp[c] = make_double2(0.0, 0.0);
+    double tr[8], ti[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double2 d01 = dv[2 * k], d23 = dv[2 * k + 1];
+        const double2 ua = lds.uA[qq + 16 * k];
+        tr[k] = fma(d23.y, ub3.x, fma(d23.x, ub2.x, fma(d01.y, ub1.x, d01.x * ub0.x)));
+        ti[k] = fma(d23.y, ub3.y, fma(d23.x, ub2.y, fma(d01.y, ub1.y, d01.x * ub0.y)));
+        cp[0].x = fma(d01.x, ua.x, cp[0].x);
+        cp[0].y = fma(d01.x, ua.y, cp[0].y);
+        cp[1].x = fma(d01.y, ua.x, cp[1].x);
+        cp[1].y = fma(d01.y, ua.y, cp[1].y);
+        cp[2].x = fma(d23.x, ua.x, cp[2].x);
+        cp[2].y = fma(d23.x, ua.y, cp[2].y);
+        cp[3].x = fma(d23.y, ua.x, cp[3].x);
+        cp[3].y = fma(d23.y, ua.y, cp[3].y);
+    }
+    // Row partials over the wave's 16 columns: reduce over lane bits 5 and 4
+    // (the four column groups h). Afterwards a lane holds rows
+    // qq + 16 (k + 2 bit4 + 4 bit5), k = 0, 1.
+    double sr[4], si[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        sr[k] = swap_reduce<5>(tr[k], tr[k + 4]);
+        si[k] = swap_reduce<5>(ti[k], ti[k + 4]);
+    }
+    const int rcls = 2 * (h & 1) + 4 * (h >> 1);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double zr = swap_reduce<4>(sr[k], sr[k + 2]), zi = swap_reduce<4>(si[k], si[k + 2]);
+        lds.rbuf[wv][qq + 16 * (k + rcls)] = make_double2(zr, zi);
+    }
+    // Column partials over the lane's 8 rows, per row class qq.
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lds.cbuf[cb + c][qq] = cp[c];
+    lds_barrier();
+
+    if (t < VEC_TILE_MAX) {
+        if (t < RB) {  // column partial of column t: sum over the 16 row classes
+            double2 s = lds.cbuf[t][0];
+#pragma unroll
+            for (int k = 1; k < 16; ++k) s = cadd(s, lds.cbuf[t][k]);
+            double2 *cpo = colp_ptr(b, npar) + ((size_t)(l * T + j) * T + i) * VEC_TILE_MAX;
+            st_nt(cpo + t, s);
+        }
+    } else if (t < 2 * VEC_TILE_MAX) {  // row partial of row a: sum over the 8 waves' columns
+        const int a = t - VEC_TILE_MAX;
+        if (a < RA) {
+            double2 s = lds.rbuf[0][a];
+#pragma unroll
+            for (int k = 1; k < VEC_THREADS / 64; ++k) s = cadd(s, lds.rbuf[k][a]);
+            double2 *rp = rowp_ptr(b, npar) + ((size_t)(l * T + i) * T + j) * VEC_TILE_MAX;
+            st_nt(rp + a, s);
+        }
+    }
+}
+
+// One tile workgroup of the fused path: completes the previous product for
+// segments A = (l, i) and B = (l+1, j) and produces this launch's row and
+// column partials of tile (l, i, j). T is the number of tiles per block
+// dimension (a compile-time constant where TP == T), F the field sample of
+// the completed product.
 template <int TP>
 __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &L, int T, int l, int i, int j,
                                           int r0, int RA, int c0, int RB, double F, double dt,
@@ -229,10 +310,7 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
     const int n = b.n;
     const int tile = (l * T + i) * T + j;
 
-    __shared__ double2 uA[VEC_TILE_MAX], uB[VEC_TILE_MAX];
-    __shared__ double2 zc[2 * VEC_TILE_MAX];
-    __shared__ double2 rbuf[VEC_THREADS / 64][VEC_TILE_MAX];  // [wave][row]
-    __shared__ double2 cbuf[VEC_TILE_MAX][17];                // [column][row class q], padded
+    __shared__ TileLds lds;
 
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
@@ -273,84 +351,49 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
     for (int r = EARLY; r < 16; ++r) dv[r] = Dt[r * 64];
 
     // ---- completion of the previous product (overlaps the tile stream).
-    if (half == 1) zc[pe] = zpart;
+    if (half == 1) lds.zc[pe] = zpart;
     lds_barrier();
     if (half == 0) {
         double2 u = make_double2(0.0, 0.0);
         if (e < len) {
             double2 c = c_in, acc = acc_in;
             u = u_in;
-            apply_completion(L.comp, dt, F, E0, cadd(zpart, zc[pe]), c, acc, u);
+            apply_completion(L.comp, dt, F, E0, cadd(zpart, lds.zc[pe]), c, acc, u);
             const bool owner = isB ? (l == b.lmax - 1 && i == 0) : (j == 0);
             if (owner) store_state(b, L, ct, gi, c, acc, u);
         }
-        (isB ? uB : uA)[e] = u;
+        (isB ? lds.uB : lds.uA)[e] = u;
     }
     lds_barrier();
+    tile_products(b, lds, dv, T, l, i, j, RA, RB, par ^ 1);
+}
 
-    // ---- tile products. Lane (h, qq) holds rows qq + 16k and columns
-    // cb .. cb+3: dv[2k] = D[row k][cb, cb+1], dv[2k+1] = D[row k][cb+2, cb+3].
-    const int h = lane >> 4, qq = lane & 15;
-    const int cb = wv * 16 + 4 * h;
-    const double2 ub0 = uB[cb], ub1 = uB[cb + 1], ub2 = uB[cb + 2], ub3 = uB[cb + 3];
-    double2 cp[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) cp[c] = make_double2(0.0, 0.0);
-    double tr[8], ti[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const double2 d01 = dv[2 * k], d23 = dv[2 * k + 1];
-        const double2 ua = uA[qq + 16 * k];
-        tr[k] = fma(d23.y, ub3.x, fma(d23.x, ub2.x, fma(d01.y, ub1.x, d01.x * ub0.x)));
-        ti[k] = fma(d23.y, ub3.y, fma(d23.x, ub2.y, fma(d01.y, ub1.y, d01.x * ub0.y)));
-        cp[0].x = fma(d01.x, ua.x, cp[0].x);
-        cp[0].y = fma(d01.x, ua.y, cp[0].y);
-        cp[1].x = fma(d01.y, ua.x, cp[1].x);
-        cp[1].y = fma(d01.y, ua.y, cp[1].y);
-        cp[2].x = fma(d23.x, ua.x, cp[2].x);
-        cp[2].y = fma(d23.x, ua.y, cp[2].y);
-        cp[3].x = fma(d23.y, ua.x, cp[3].x);
-        cp[3].y = fma(d23.y, ua.y, cp[3].y);
+// One tile workgroup of the split path: the stage inputs were completed by
+// the preceding combine launch (state buffers of parity par ^ 1), so the
+// workgroup only loads its two input segments and its tile.
+__device__ __forceinline__ void products_body(const VecBuffers &b, int par, int T, int l, int i, int j, int r0,
+                                              int RA, int c0, int RB) {
+    __shared__ TileLds lds;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    const int tile = (l * T + i) * T + j;
+    const double2 *Dt = reinterpret_cast<const double2 *>(b.dip) +
+                        (size_t)tile * (VEC_TILE_MAX * VEC_TILE_MAX / 2) + wv * 16 * 64 + lane;
+    // input segments first: waiting for them leaves the tile loads in flight,
+    // and the products consume tile rows in load order as they arrive
+    const bool isB = t >= VEC_TILE_MAX;
+    const int e = t & (VEC_TILE_MAX - 1), len = isB ? RB : RA;
+    double2 u = make_double2(0.0, 0.0);
+    if (t < 2 * VEC_TILE_MAX) {
+        const size_t gi = (size_t)(isB ? l + 1 : l) * b.n + (isB ? c0 : r0) + (e < len ? e : len - 1);
+        u = ld_nt(st_ptr(b, par ^ 1, 2) + gi);
     }
-    // Row partials over the wave's 16 columns: reduce over lane bits 5 and 4
-    // (the four column groups h). Afterwards a lane holds rows
-    // qq + 16 (k + 2 bit4 + 4 bit5), k = 0, 1.
-    double sr[4], si[4];
+    double2 dv[16];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        sr[k] = swap_reduce<5>(tr[k], tr[k + 4]);
-        si[k] = swap_reduce<5>(ti[k], ti[k + 4]);
-    }
-    const int rcls = 2 * (h & 1) + 4 * (h >> 1);
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const double zr = swap_reduce<4>(sr[k], sr[k + 2]), zi = swap_reduce<4>(si[k], si[k + 2]);
-        rbuf[wv][qq + 16 * (k + rcls)] = make_double2(zr, zi);
-    }
-    // Column partials over the lane's 8 rows, per row class qq.
-#pragma unroll
-    for (int c = 0; c < 4; ++c) cbuf[cb + c][qq] = cp[c];
+    for (int r = 0; r < 16; ++r) dv[r] = Dt[r * 64];
+    if (t < 2 * VEC_TILE_MAX) (isB ? lds.uB : lds.uA)[e] = e < len ? u : make_double2(0.0, 0.0);
     lds_barrier();
-
-    const int npar = par ^ 1;
-    if (t < VEC_TILE_MAX) {
-        if (t < RB) {  // column partial of column t: sum over the 16 row classes
-            double2 s = cbuf[t][0];
-#pragma unroll
-            for (int k = 1; k < 16; ++k) s = cadd(s, cbuf[t][k]);
-            double2 *cpo = colp_ptr(b, npar) + ((size_t)(l * T + j) * T + i) * VEC_TILE_MAX;
-            st_nt(cpo + t, s);
-        }
-    } else if (t < 2 * VEC_TILE_MAX) {  // row partial of row a: sum over the 8 waves' columns
-        const int a = t - VEC_TILE_MAX;
-        if (a < RA) {
-            double2 s = rbuf[0][a];
-#pragma unroll
-            for (int k = 1; k < VEC_THREADS / 64; ++k) s = cadd(s, rbuf[k][a]);
-            double2 *rp = rowp_ptr(b, npar) + ((size_t)(l * T + i) * T + j) * VEC_TILE_MAX;
-            st_nt(rp + a, s);
-        }
-    }
+    tile_products(b, lds, dv, T, l, i, j, RA, RB, par ^ 1);
 }
 
 template <int TP>
@@ -370,16 +413,27 @@ __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
     tile_body<TP>(b, L, T, l, i, j, r0, RA, c0, RB, F, dt, ct);
 }
 
-// Uneven group: one launch runs one RK4 stage-round of every active
-// instance. Workgroup w takes entry w of the work list (instance, l, i, j);
-// each instance brings its own buffers, tile count and field samples.
-__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_group_kernel(const GroupTile *tiles, const GroupInst *insts,
-                                                                 int64_t round, double dt) {
-    const GroupTile gt = tiles[blockIdx.x];
-    const GroupInst &gi = insts[gt.inst];
-    const VecBuffers &b = gi.b;  // read in place: a local copy would be indexed through scratch
-    // RK4 launch schedule: launch 4k+s completes stage s of step k (stage 4 of
-    // step k-1 for s == 0) and forms the input of the next stage.
+// Products-only launch of the split path (after a vec_combine launch).
+template <int TP>
+__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_products_kernel(VecBuffers b, VecLaunch L) {
+    const int T = TP <= 8 ? TP : b.T;
+    const int ntiles = b.lmax * T * T;
+    const int w = blockIdx.x;
+    const int xcd = w & 7, per = ntiles >> 3, extra = ntiles & 7;
+    const int tile = xcd * per + (xcd < extra ? xcd : extra) + (w >> 3);
+    const int l = tile / (T * T), rem = tile - l * T * T, i = rem / T, j = rem - i * T;
+    const int r0 = b.seg[i], RA = b.seg[i + 1] - r0;
+    const int c0 = b.seg[j], RB = b.seg[j + 1] - c0;
+    products_body(b, L.parity, T, l, i, j, r0, RA, c0, RB);
+}
+
+// Uneven group: every RK4 stage-round of the active instances is one
+// combine launch over their segments (work list of (instance, m, q)) and one
+// products launch over their tiles (work list of (instance, l, i, j)); each
+// instance brings its own buffers, tile count and field samples.
+// RK4 launch schedule: round 4k+s completes stage s of step k (stage 4 of
+// step k-1 for s == 0) and forms the input of the next stage.
+__device__ __forceinline__ VecLaunch group_round_launch(int64_t round) {
     const int s = (int)(round & 3);
     VecLaunch L{};
     L.parity = (int)(round & 1);
@@ -388,11 +442,35 @@ __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
     else if (s == 1) L.comp = {CK_RK4_MID, 0, 0, 1, 1.0 / 6.0, 0.5};
     else if (s == 2) L.comp = {CK_RK4_MID, 1, 0, 0, 2.0 / 6.0, 0.5};
     else L.comp = {CK_RK4_MID, 1, 0, 0, 2.0 / 6.0, 1.0};
+    return L;
+}
+
+__global__ __launch_bounds__(VEC_TILE_MAX) void vec_group_combine_kernel(const GroupSeg *segs, const GroupInst *insts,
+                                                                          int64_t round, double dt) {
+    const GroupSeg gs = segs[blockIdx.x];
+    const GroupInst &gi = insts[gs.inst];
+    const VecBuffers &b = gi.b;  // read in place: a local copy would be indexed through scratch
+    const VecLaunch L = group_round_launch(round);
+    const int e = threadIdx.x;
+    const int len = (int)split_len(b.n, b.T, gs.q);
+    if (e >= len) return;
     const int64_t step = (round >> 2) + L.comp.step_delta;
     const double F = (step >= 0 && step < gi.nsteps) ? gi.field[step * 3 + L.comp.slot] : 0.0;
+    const size_t g = (size_t)gs.m * b.n + split_start(b.n, b.T, gs.q) + e;
+    const int par = L.parity;
+    const double2 z = cadd(sum_partials<8>(b, b.T, par, true, gs.m, gs.q, e),
+                           sum_partials<8>(b, b.T, par, false, gs.m, gs.q, e));
+    double2 c = ld_nt(st_ptr(b, par, 0) + g), acc = ld_nt(st_ptr(b, par, 1) + g), u = ld_nt(st_ptr(b, par, 2) + g);
+    apply_completion(L.comp, dt, F, b.en[g], z, c, acc, u);
+    store_state(b, L, CkptTarget{nullptr}, g, c, acc, u);
+}
+
+__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_group_products_kernel(const GroupTile *tiles, const GroupInst *insts, int64_t round) {
+    const GroupTile gt = tiles[blockIdx.x];
+    const VecBuffers &b = insts[gt.inst].b;
     const int r0 = (int)split_start(b.n, b.T, gt.i), RA = (int)split_len(b.n, b.T, gt.i);
     const int c0 = (int)split_start(b.n, b.T, gt.j), RB = (int)split_len(b.n, b.T, gt.j);
-    tile_body<8>(b, L, b.T, gt.l, gt.i, gt.j, r0, RA, c0, RB, F, dt, CkptTarget{nullptr});
+    products_body(b, (int)(round & 1), b.T, gt.l, gt.i, gt.j, r0, RA, c0, RB);
 }
 
 // Completion only (no products): the final completion of a propagation,
@@ -558,9 +636,17 @@ hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream
     TDSE_TP_DISPATCH(b.T, vec_combine_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s, b, l);
     return hipGetLastError();
 }
-hipError_t group_launch_round(const GroupTile *tiles, int ntiles, const GroupInst *insts, int64_t round,
-                              double dt, hipStream_t s) {
-    hipLaunchKernelGGL(vec_group_kernel, dim3(ntiles), dim3(VEC_THREADS), 0, s, tiles, insts, round, dt);
+hipError_t vec_launch_products(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {
+    const int ntiles = b.lmax * b.T * b.T;
+    TDSE_TP_DISPATCH(b.T, vec_products_kernel, dim3(ntiles), dim3(VEC_THREADS), 0, s, b, l);
+    return hipGetLastError();
+}
+hipError_t group_launch_round(const GroupSeg *segs, int nsegs, const GroupTile *tiles, int ntiles,
+                              const GroupInst *insts, int64_t round, double dt, hipStream_t s) {
+    hipLaunchKernelGGL(vec_group_combine_kernel, dim3(nsegs), dim3(VEC_TILE_MAX), 0, s, segs, insts, round, dt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(vec_group_products_kernel, dim3(ntiles), dim3(VEC_THREADS), 0, s, tiles, insts, round);
     return hipGetLastError();
 }
 

@@ -34,15 +34,22 @@ def make_plan(h, batch=1):
     return Plan(h.energies, h.dipole if h.lmax > 0 else np.zeros((0, h.n, h.n)), batch=batch)
 
 
-@pytest.fixture(params=["auto", "tiles"])
+@pytest.fixture(params=["auto", "tiles", "split"])
 def path(request):
     """auto: the library's choice (one-workgroup kernel for small problems);
-    tiles: the tiled per-product kernels, forced through TDSE_TILE."""
+    tiles: the fused per-product tile kernels, forced through TDSE_TILE;
+    split: separate completion and product launches, forced through TDSE_SPLIT."""
     return request.param
 
 
 def force_tiles(monkeypatch, n):
     monkeypatch.setenv("TDSE_TILE", f"T={(n + 127) // 128}")
+
+
+def apply_path(path, monkeypatch, n):
+    if path in ("tiles", "split"):
+        force_tiles(monkeypatch, n)
+        monkeypatch.setenv("TDSE_SPLIT", "1" if path == "split" else "0")
 
 
 SHAPES = [(1, 1), (2, 3), (3, 50), (0, 7), (2, 130), (3, 257), (1, 128), (2, 129)]
@@ -71,8 +78,7 @@ def _rk4_case(lmax, n, nsteps, dt, seed=0, e0=0.08, w=0.6):
 @pytest.mark.parametrize("lmax,n,nsteps", [(1, 1, 50), (2, 3, 130), (3, 50, 300), (0, 7, 65),
                                             (2, 130, 100), (3, 257, 70), (2, 129, 64)])
 def test_rk4_parity(torch_dev, lmax, n, nsteps, path, monkeypatch):
-    if path == "tiles":
-        force_tiles(monkeypatch, n)
+    apply_path(path, monkeypatch, n)
     h, f, c0 = _rk4_case(lmax, n, nsteps, 0.01)
     plan = make_plan(h)
     got = plan.propagate(f, c0, 0.01, "rk4").cpu().numpy()
@@ -83,8 +89,7 @@ def test_rk4_parity(torch_dev, lmax, n, nsteps, path, monkeypatch):
 @pytest.mark.parametrize("order", [1, 2, 4, 8, 10])
 @pytest.mark.parametrize("lmax,n,nsteps", [(2, 3, 70), (3, 130, 66), (0, 5, 64)])
 def test_taylor_parity(torch_dev, order, lmax, n, nsteps, path, monkeypatch):
-    if path == "tiles":
-        force_tiles(monkeypatch, n)
+    apply_path(path, monkeypatch, n)
     h = wl.hamiltonian(lmax, n, 3)
     dt = 0.02
     f = wl.taylor_samples(wl.Pulse(0.08, 0.6, 2.0), dt, nsteps)[None]
@@ -97,8 +102,7 @@ def test_taylor_parity(torch_dev, order, lmax, n, nsteps, path, monkeypatch):
 
 def test_single_small_full_length(torch_dev, path, monkeypatch):
     """Lmax=3, N=50, 12567 RK4 steps against the stored full-length oracle result."""
-    if path == "tiles":
-        force_tiles(monkeypatch, 50)
+    apply_path(path, monkeypatch, 50)
     w = wl.single_small()
     gold = np.load(os.path.join(HERE, "golden", "single_small_rk4.npz"), allow_pickle=False)
     assert int(gold["nsteps"]) == w.nsteps
@@ -137,8 +141,7 @@ def test_single_large_full_length(torch_dev, name, method, order):
 
 def test_nsteps_zero_and_alias(torch_dev, path, monkeypatch):
     torch = torch_dev
-    if path == "tiles":
-        force_tiles(monkeypatch, 9)
+    apply_path(path, monkeypatch, 9)
     h, f, c0 = _rk4_case(2, 9, 40, 0.01)
     plan = make_plan(h)
     out = plan.propagate(np.zeros((1, 0, 3)), c0, 0.01, "rk4").cpu().numpy()
@@ -149,9 +152,11 @@ def test_nsteps_zero_and_alias(torch_dev, path, monkeypatch):
     assert rel_l2(buf.cpu().numpy(), ref) <= TOL
 
 
+@pytest.mark.parametrize("split", ["0", "1"])
 @pytest.mark.parametrize("method,order", [("rk4", 0), ("taylor", 6)])
 @pytest.mark.parametrize("lmax,n", [(2, 140), (3, 40)])
-def test_checkpoints(torch_dev, method, order, lmax, n):
+def test_checkpoints(torch_dev, method, order, lmax, n, split, monkeypatch):
+    monkeypatch.setenv("TDSE_SPLIT", split)
     h = wl.hamiltonian(lmax, n, 2)
     dt, nsteps, k = 0.01, 150, 64
     pulse = wl.Pulse(0.1, 0.5, 2.0)
