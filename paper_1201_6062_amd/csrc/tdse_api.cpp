@@ -699,6 +699,17 @@ tdse_status tdse_adjoint(tdse_plan p, tdse_method method, int32_t order, double 
     return bat_adjoint(q, dt, nsteps, field, c0, ckpt, ckpt_every, lambdaT, grad_field, lambda0, s);
 }
 
+// Captured group chunks hold the work-list addresses: drop them before the
+// lists move.
+static void drop_group_graphs(tdse_group g) {
+    if (g->graphs.empty() && g->graph_defs.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : g->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t gd : g->graph_defs) (void)hipGraphDestroy(gd);
+    g->graphs.clear();
+    g->graph_defs.clear();
+}
+
 tdse_status tdse_group_create(tdse_group *out, int32_t count, const tdse_plan *plans, void *stream) {
     clear_error();
     (void)stream;
@@ -770,6 +781,7 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
     }
     if (order_idx.empty()) return TDSE_OK;
     if (g->tiles.size() > g->tiles_cap) {
+        drop_group_graphs(g);
         if (g->d_tiles) (void)hipFree(g->d_tiles);
         g->d_tiles = nullptr;
         g->tiles_cap = 0;
@@ -780,6 +792,7 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
         g->tiles_cap = g->tiles.size();
     }
     if (g->segs.size() > g->segs_cap) {
+        drop_group_graphs(g);
         if (g->d_segs) (void)hipFree(g->d_segs);
         g->d_segs = nullptr;
         g->segs_cap = 0;
@@ -790,6 +803,7 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
         g->segs_cap = g->segs.size();
     }
     if (g->insts.size() > g->insts_cap) {
+        drop_group_graphs(g);
         if (g->d_insts) (void)hipFree(g->d_insts);
         g->d_insts = nullptr;
         g->insts_cap = 0;
@@ -805,14 +819,50 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
                             hipMemcpyHostToDevice, s));
     TDSE_HIP(hipMemcpyAsync(g->d_insts, g->insts.data(), g->insts.size() * sizeof(GroupInst),
                             hipMemcpyHostToDevice, s));
+    if (!g->d_desc && hipMalloc(&g->d_desc, sizeof(GroupDesc)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(TDSE_E_NOMEM, "hipMalloc of the group descriptor failed");
+    }
     for (int k : order_idx) TDSE_HIP(vec_launch_start(g->plans[k]->vb, 0, c0[k], TDSE_RK4, s));
+    // Rounds go in chunks of GROUP_CHUNK_ROUNDS; a chunk's launches cover the
+    // instances active at its first round (the kernels skip instances that
+    // finish inside the chunk). Whole chunks replay a captured graph.
     const int64_t rounds = 4 * nsteps[order_idx[0]];
     size_t active = order_idx.size();
-    for (int64_t r = 0; r < rounds; ++r) {
+    for (int64_t r = 0; r < rounds; r += GROUP_CHUNK_ROUNDS) {
         while (active > 0 && 4 * nsteps[order_idx[active - 1]] <= r) --active;
-        const int64_t nt = prefix[active];
-        if (nt > 0)
-            TDSE_HIP(group_launch_round(g->d_segs, (int)seg_prefix[active], g->d_tiles, (int)nt, g->d_insts, r, dt, s));
+        const int nt = (int)prefix[active], ns = (int)seg_prefix[active];
+        const int len = (int)std::min<int64_t>(GROUP_CHUNK_ROUNDS, rounds - r);
+        TDSE_HIP(group_set_desc(g->d_desc, r, dt, s));
+        hipGraphExec_t ge = nullptr;
+        if (graphs_enabled() && len == GROUP_CHUNK_ROUNDS) {
+            const int64_t key = ((int64_t)nt << 32) | (uint32_t)ns;  // what a capture depends on
+            auto it = g->graphs.find(key);
+            if (it != g->graphs.end()) {
+                ge = it->second;
+            } else {
+                hipStream_t cs;
+                TDSE_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+                hipGraph_t gd = nullptr;
+                hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+                for (int off = 0; e == hipSuccess && off < GROUP_CHUNK_ROUNDS; ++off)
+                    e = group_launch_round(g->d_segs, ns, g->d_tiles, nt, g->d_insts, g->d_desc, off, cs);
+                hipError_t e2 = hipStreamEndCapture(cs, &gd);
+                if (e == hipSuccess) e = e2;
+                if (e == hipSuccess) e = hipGraphInstantiate(&ge, gd, nullptr, nullptr, 0);
+                (void)hipStreamDestroy(cs);
+                if (e != hipSuccess) {
+                    if (gd) (void)hipGraphDestroy(gd);
+                    return hip_fail(e, "graph capture of a group chunk");
+                }
+                g->graphs[key] = ge;
+                g->graph_defs.push_back(gd);
+            }
+            TDSE_HIP(hipGraphLaunch(ge, s));
+        } else {
+            for (int off = 0; off < len; ++off)
+                TDSE_HIP(group_launch_round(g->d_segs, ns, g->d_tiles, nt, g->d_insts, g->d_desc, off, s));
+        }
     }
     // final completion of every instance (c(T) -> cT)
     for (int k : order_idx) {
@@ -843,8 +893,10 @@ tdse_status tdse_group_destroy(tdse_group g) {
     if (!g) return TDSE_OK;
     (void)hipDeviceSynchronize();
     if (g->d_tiles) (void)hipFree(g->d_tiles);
+    drop_group_graphs(g);
     if (g->d_segs) (void)hipFree(g->d_segs);
     if (g->d_insts) (void)hipFree(g->d_insts);
+    if (g->d_desc) (void)hipFree(g->d_desc);
     delete g;
     return TDSE_OK;
 }

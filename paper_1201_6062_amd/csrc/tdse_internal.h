@@ -125,10 +125,17 @@ hipError_t small_propagate(const double *en, const double *dip, int lmax, int n,
                            int64_t nsteps, const double *field, const double *c0, double *cT, double *ckpt,
                            int64_t ckpt_every, hipStream_t s);
 
-// One RK4 stage-round of a group: completion over the segment list, then
-// the tile products over the tile list.
+// Per-call values of a group that its captured graphs read from device memory.
+struct GroupDesc {
+    int64_t base_round;     // first RK4 stage-round of the current chunk
+    double dt;
+};
+constexpr int GROUP_CHUNK_ROUNDS = 64;  // rounds per captured graph (16 steps)
+// One RK4 stage-round (desc->base_round + off) of a group: completion over the
+// segment list, then the tile products over the tile list.
 hipError_t group_launch_round(const GroupSeg *segs, int nsegs, const GroupTile *tiles, int ntiles,
-                              const GroupInst *insts, int64_t round, double dt, hipStream_t s);
+                              const GroupInst *insts, const GroupDesc *desc, int32_t off, hipStream_t s);
+hipError_t group_set_desc(GroupDesc *desc, int64_t base_round, double dt, hipStream_t s);
 
 hipError_t vec_launch_tiles(const VecBuffers &b, const VecLaunch &l, hipStream_t s);
 hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream_t s);
@@ -211,6 +218,11 @@ struct tdse_group_s {
     tdse::GroupSeg *d_segs = nullptr;
     tdse::GroupInst *d_insts = nullptr;
     size_t tiles_cap = 0, segs_cap = 0, insts_cap = 0;
+    tdse::GroupDesc *d_desc = nullptr;
+    // captured chunks of GROUP_CHUNK_ROUNDS rounds, keyed by their grid sizes
+    // (tiles << 32 | segments: the active prefix of the work lists)
+    std::map<int64_t, hipGraphExec_t> graphs;
+    std::vector<hipGraph_t> graph_defs;
 };
 
 struct tdse_plan_s {

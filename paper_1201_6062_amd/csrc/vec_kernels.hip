@@ -445,10 +445,15 @@ __device__ __forceinline__ VecLaunch group_round_launch(int64_t round) {
     return L;
 }
 
+// A group launch belongs to round desc->base_round + off; instances whose
+// last round has passed leave at once (the grid covers the instances active
+// at the start of a chunk of rounds).
 __global__ __launch_bounds__(VEC_TILE_MAX) void vec_group_combine_kernel(const GroupSeg *segs, const GroupInst *insts,
-                                                                          int64_t round, double dt) {
+                                                                          const GroupDesc *desc, int32_t off) {
     const GroupSeg gs = segs[blockIdx.x];
     const GroupInst &gi = insts[gs.inst];
+    const int64_t round = desc->base_round + off;
+    if (round >= 4 * gi.nsteps) return;
     const VecBuffers &b = gi.b;  // read in place: a local copy would be indexed through scratch
     const VecLaunch L = group_round_launch(round);
     const int e = threadIdx.x;
@@ -461,16 +466,24 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_group_combine_kernel(const G
     const double2 z = cadd(sum_partials<8>(b, b.T, par, true, gs.m, gs.q, e),
                            sum_partials<8>(b, b.T, par, false, gs.m, gs.q, e));
     double2 c = ld_nt(st_ptr(b, par, 0) + g), acc = ld_nt(st_ptr(b, par, 1) + g), u = ld_nt(st_ptr(b, par, 2) + g);
-    apply_completion(L.comp, dt, F, b.en[g], z, c, acc, u);
+    apply_completion(L.comp, desc->dt, F, b.en[g], z, c, acc, u);
     store_state(b, L, CkptTarget{nullptr}, g, c, acc, u);
 }
 
-__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_group_products_kernel(const GroupTile *tiles, const GroupInst *insts, int64_t round) {
+__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_group_products_kernel(const GroupTile *tiles, const GroupInst *insts, const GroupDesc *desc, int32_t off) {
     const GroupTile gt = tiles[blockIdx.x];
-    const VecBuffers &b = insts[gt.inst].b;
+    const GroupInst &gi = insts[gt.inst];
+    const int64_t round = desc->base_round + off;
+    if (round >= 4 * gi.nsteps) return;
+    const VecBuffers &b = gi.b;
     const int r0 = (int)split_start(b.n, b.T, gt.i), RA = (int)split_len(b.n, b.T, gt.i);
     const int c0 = (int)split_start(b.n, b.T, gt.j), RB = (int)split_len(b.n, b.T, gt.j);
     products_body(b, (int)(round & 1), b.T, gt.l, gt.i, gt.j, r0, RA, c0, RB);
+}
+
+__global__ void group_desc_kernel(GroupDesc *desc, int64_t base_round, double dt) {
+    desc->base_round = base_round;
+    desc->dt = dt;
 }
 
 // Completion only (no products): the final completion of a propagation,
@@ -642,11 +655,15 @@ hipError_t vec_launch_products(const VecBuffers &b, const VecLaunch &l, hipStrea
     return hipGetLastError();
 }
 hipError_t group_launch_round(const GroupSeg *segs, int nsegs, const GroupTile *tiles, int ntiles,
-                              const GroupInst *insts, int64_t round, double dt, hipStream_t s) {
-    hipLaunchKernelGGL(vec_group_combine_kernel, dim3(nsegs), dim3(VEC_TILE_MAX), 0, s, segs, insts, round, dt);
+                              const GroupInst *insts, const GroupDesc *desc, int32_t off, hipStream_t s) {
+    hipLaunchKernelGGL(vec_group_combine_kernel, dim3(nsegs), dim3(VEC_TILE_MAX), 0, s, segs, insts, desc, off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(vec_group_products_kernel, dim3(ntiles), dim3(VEC_THREADS), 0, s, tiles, insts, round);
+    hipLaunchKernelGGL(vec_group_products_kernel, dim3(ntiles), dim3(VEC_THREADS), 0, s, tiles, insts, desc, off);
+    return hipGetLastError();
+}
+hipError_t group_set_desc(GroupDesc *desc, int64_t base_round, double dt, hipStream_t s) {
+    hipLaunchKernelGGL(group_desc_kernel, dim3(1), dim3(1), 0, s, desc, base_round, dt);
     return hipGetLastError();
 }
 

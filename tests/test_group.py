@@ -67,3 +67,21 @@ def test_group_full_length_sampled_instances():
         gold = np.load(os.path.join(HERE, "golden", f"uneven_inst{i:02d}.npz"), allow_pickle=False)
         assert int(gold["nsteps"]) == specs[i].nsteps
         assert rel_l2(o.cpu().numpy(), gold["cT"]) <= TOL
+
+
+def test_group_repeated_calls_reuse_graphs():
+    """Two calls on one group with different step counts and dt (captured
+    chunks are reused with the new descriptor) and a third after the work
+    list grew (a new group over more instances)."""
+    from paper_1201_6062_amd.api import Group
+    shapes = [(2, 70, 0), (3, 140, 0), (1, 20, 0)]
+    hs = [wl.hamiltonian(l, n, 200 + q) for q, (l, n, _) in enumerate(shapes)]
+    plans = [plan_of(h) for h in hs]
+    grp = Group(plans)
+    for call, (dt, steps) in enumerate([(0.01, (80, 33, 50)), (0.02, (41, 90, 17))]):
+        fs = [wl.rk4_samples(wl.Pulse(0.1, 0.4 + 0.1 * q, 2.0), dt, st) for q, st in enumerate(steps)]
+        cs = [wl.random_state(np.random.default_rng(10 * call + q), h.nstates)[0] for q, h in enumerate(hs)]
+        out = grp.propagate(fs, cs, dt)
+        for h, f, c, o in zip(hs, fs, cs, out):
+            ref = oracle.rk4(h.energies, h.dipole, dt, f[None], c[None], n=h.n)[0]
+            assert rel_l2(o.cpu().numpy(), ref) <= TOL, (call, h.lmax, h.n)
