@@ -51,6 +51,8 @@ def _load():
         lib.oracle_rk4_tangent.restype = i32
         lib.oracle_rk4_adjoint.argtypes = [i32, i32, P, P, d, i64, P, P, P, P]
         lib.oracle_rk4_adjoint.restype = i32
+        lib.oracle_taylor_adjoint.argtypes = [i32, i32, P, P, i32, d, i64, P, P, P, P]
+        lib.oracle_taylor_adjoint.restype = i32
         _lib = lib
     return _lib
 
@@ -160,6 +162,21 @@ def rk4_adjoint(energies, dipole, dt, field, c0, lam_t, n=None):
                                     _p(field), _p(c0), _p(lam), _p(grad))
     if rc != 0:
         raise MemoryError("oracle_rk4_adjoint allocation failed")
+    return lam, grad
+
+
+def taylor_adjoint(energies, dipole, order, dt, field, c0, lam_t, n=None):
+    """Discrete Taylor-p adjoint for one pulse (field [nsteps] or [nsteps, 1]).
+    Returns (lambda_0, grad[nsteps])."""
+    en, dip, lmax, n = _dims_n(energies, dipole, n)
+    field = _f64(np.asarray(field).reshape(-1))
+    c0 = _f64(np.asarray(c0).reshape(-1))
+    lam = np.array(lam_t, dtype=np.float64, copy=True).reshape(-1)
+    grad = np.zeros_like(field)
+    rc = _load().oracle_taylor_adjoint(lmax, n, _p(en), _p(dip), int(order), float(dt), field.shape[0],
+                                       _p(field), _p(c0), _p(lam), _p(grad))
+    if rc != 0:
+        raise MemoryError("oracle_taylor_adjoint allocation failed")
     return lam, grad
 
 

@@ -28,7 +28,9 @@
  * eigendecomposition of the per-step polynomial propagator, RK4 convergence
  * order against a high-accuracy ODE solve, Taylor-4 = RK4 identity, norm
  * contraction, linearity, and for the adjoint the dot-product identity,
- * tangent-linear agreement and central finite differences.
+ * tangent-linear agreement and central finite differences; for the Taylor
+ * adjoint the dot-product identity, finite differences and its agreement
+ * with the RK4 adjoint where Taylor-4 and RK4 coincide.
  */
 #include <math.h>
 #include <stdint.h>
@@ -276,5 +278,72 @@ int oracle_rk4_adjoint(int lmax, int n, const double *en, const double *dip, dou
     }
     for (int i = 0; i < 4; ++i) { free(u[i]); free(k[i]); }
     free(cs); free(tmp); free(kb); free(ub); free(cb); free(z);
+    return 0;
+}
+
+/*
+ * Discrete adjoint of the Taylor map above (same convention as the RK4
+ * adjoint: dL = Re(lambda^H dc); on entry lam = lambda_T, on return
+ * lam = lambda_0 and grad[k] = dL/dfield[k]). One step is
+ *   c' = T_0 + T_1 + ... + T_p,  T_0 = c,  T_m = a_m H(F) T_{m-1},
+ * with a_m = -i dt / m. Every T_m reaches c' directly and through T_{m+1}, so
+ * with lambda the co-state of c' the co-states of the terms are
+ *   Tbar_p = lambda,  Tbar_{m-1} = lambda + conj(a_m) H Tbar_m  (m = p..1),
+ * using H^T = H (real symmetric), and the co-state of c is Tbar_0. The field
+ * enters every term through dT_m / dF = a_m D T_{m-1}, so
+ *   g(F) = sum_m Re(Tbar_m^H a_m D T_{m-1}) = sum_m (dt / m) Im((D Tbar_m)^H T_{m-1}).
+ * Forward states c_k are stored for every step; the terms of a step are
+ * recomputed from c_k.
+ */
+int oracle_taylor_adjoint(int lmax, int n, const double *en, const double *dip, int order, double dt,
+                          int64_t nsteps, const double *field, const double *c0, double *lam, double *grad)
+{
+    size_t ns = (size_t)(lmax + 1) * n;
+    double *cs = malloc(16 * ns * (size_t)(nsteps + 1));
+    double *terms = malloc(16 * ns * (size_t)(order + 1));
+    double *tb = malloc(16 * ns), *h = malloc(16 * ns), *z = malloc(16 * ns);
+    if (!cs || !terms || !tb || !h || !z) return -1;
+
+    memcpy(cs, c0, 16 * ns);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        double *cn = cs + 2 * ns * (size_t)(s + 1);
+        memcpy(cn, cs + 2 * ns * (size_t)s, 16 * ns);
+        oracle_taylor(lmax, n, en, dip, order, dt, 1, field + s, cn);
+    }
+    for (int64_t s = 0; s < nsteps; ++s) grad[s] = 0.0;
+
+    for (int64_t s = nsteps - 1; s >= 0; --s) {
+        const double F = field[s];
+        /* recompute T_0 .. T_{p-1} of step s */
+        memcpy(terms, cs + 2 * ns * (size_t)s, 16 * ns);
+        for (int m = 1; m < order; ++m) {
+            const double *tp = terms + 2 * ns * (size_t)(m - 1);
+            double *tm = terms + 2 * ns * (size_t)m;
+            oracle_hmul(lmax, n, en, dip, F, tp, h);
+            double sc = dt / (double)m;
+            for (size_t j = 0; j < ns; ++j) {
+                RE(tm, j) = sc * IM(h, j);
+                IM(tm, j) = -sc * RE(h, j);
+            }
+        }
+        memcpy(tb, lam, 16 * ns);                    /* Tbar_p = lambda */
+        for (int m = order; m >= 1; --m) {
+            const double *tprev = terms + 2 * ns * (size_t)(m - 1);
+            const double sc = dt / (double)m;
+            /* g += (dt/m) Im((D Tbar_m)^H T_{m-1}) */
+            oracle_dmul(lmax, n, dip, tb, z);
+            double g = 0.0;
+            for (size_t j = 0; j < ns; ++j) g += RE(z, j) * IM(tprev, j) - IM(z, j) * RE(tprev, j);
+            grad[s] += sc * g;
+            /* Tbar_{m-1} = lambda + (i dt/m) H Tbar_m ; i (x + iy) = -y + ix */
+            oracle_hmul(lmax, n, en, dip, F, tb, h);
+            for (size_t j = 0; j < ns; ++j) {
+                RE(tb, j) = RE(lam, j) - sc * IM(h, j);
+                IM(tb, j) = IM(lam, j) + sc * RE(h, j);
+            }
+        }
+        memcpy(lam, tb, 16 * ns);                    /* lambda_s = Tbar_0 */
+    }
+    free(cs); free(terms); free(tb); free(h); free(z);
     return 0;
 }

@@ -399,6 +399,94 @@ def test_adjoint_lambda0_matches_fd(oracle_mod):
 
 # ------------------------------------------------------- generator and paper facts
 
+# ---- Taylor-p adjoint (next to the RK4 adjoint: same convention dL = Re(lambda^H dc))
+
+def _tay_case(seed=0, lmax=2, n=13, nst=30, dt=0.05):
+    h = wl.hamiltonian(lmax, n, seed)
+    rng = np.random.default_rng(seed + 200)
+    f = wl.taylor_samples(wl.Pulse(0.7, 0.8, 1.0), dt, nst)[:, 0] + 0.05 * rng.standard_normal(nst)
+    c0 = wl.ground_state(lmax, n)[0]
+    return h, f, c0, dt
+
+
+@pytest.mark.parametrize("order", [1, 4, 7])
+def test_taylor_adjoint_dot_product_identity(oracle_mod, order):
+    h, f, c0, dt = _tay_case(order)
+    rng = np.random.default_rng(21 + order)
+    lam_t = rng.standard_normal(c0.size)
+    dc0 = rng.standard_normal(c0.size)
+    lam0, _ = oracle_mod.taylor_adjoint(h.energies, h.dipole, order, dt, f, c0, lam_t)
+    dct = oracle_mod.taylor(h.energies, h.dipole, order, dt, f[None], dc0[None])[0]
+    lhs = np.real(np.vdot(cplx(lam0), cplx(dc0)))
+    rhs = np.real(np.vdot(cplx(lam_t), cplx(dct)))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1e-300) + 1e-15
+
+
+@pytest.mark.parametrize("order", [2, 5, 8])
+def test_taylor_adjoint_matches_central_fd(oracle_mod, order):
+    h, f, c0, dt = _tay_case(10 + order)
+
+    def y_of(ff):
+        cT = oracle_mod.taylor(h.energies, h.dipole, order, dt, ff[None], c0[None])
+        return oracle_mod.ionization_yield(h.energies, cT)[0]
+
+    cT = oracle_mod.taylor(h.energies, h.dipole, order, dt, f[None], c0[None])[0]
+    lam_t = oracle_mod.yield_seed(h.energies, cT)[0]
+    _, grad = oracle_mod.taylor_adjoint(h.energies, h.dipole, order, dt, f, c0, lam_t)
+    assert np.abs(grad).max() > 1e-4
+    scale = np.abs(grad).max()
+    hstep = 1e-5
+    for i in list(np.argsort(-np.abs(grad))[:6]) + [0, f.size - 1]:
+        fp, fm = f.copy(), f.copy()
+        fp[i] += hstep
+        fm[i] -= hstep
+        fd = (y_of(fp) - y_of(fm)) / (2 * hstep)
+        assert abs(fd - grad[i]) <= 1e-6 * scale, (i, fd, grad[i])
+
+
+def test_taylor4_adjoint_equals_rk4_adjoint_when_samples_equal(oracle_mod):
+    """With the three RK4 stage samples of a step equal, RK4 and Taylor-4 are
+    the same map (pinned above), so their adjoints agree: lambda_0 equal and
+    the Taylor gradient of a step equal to the sum of its three RK4 slots."""
+    h = wl.hamiltonian(2, 12, 4)
+    rng = np.random.default_rng(31)
+    dt, nst = 0.04, 35
+    fk = stepwise_fields(nst, dt, seed=3) + 0.3
+    c0 = wl.random_state(rng, h.nstates)[0]
+    lam_t = rng.standard_normal(c0.size)
+    l_rk, g_rk = oracle_mod.rk4_adjoint(h.energies, h.dipole, dt, np.repeat(fk[:, None], 3, 1), c0, lam_t)
+    l_ty, g_ty = oracle_mod.taylor_adjoint(h.energies, h.dipole, 4, dt, fk, c0, lam_t)
+    np.testing.assert_allclose(l_ty, l_rk, rtol=0, atol=1e-13 * np.abs(l_rk).max())
+    np.testing.assert_allclose(g_ty, g_rk.sum(axis=1), rtol=0, atol=1e-12 * np.abs(g_rk).max())
+
+
+def test_midpoint_taylor_second_order_in_field(oracle_mod):
+    """Freezing H at the step's left end (appendix B) makes Taylor-p first
+    order in dt once the field varies in time; sampling the field at the
+    step's midpoint makes it second order (the exponential midpoint rule)."""
+    from scipy.integrate import solve_ivp
+
+    h = wl.hamiltonian(1, 4, 5)
+    c0 = wl.ground_state(1, 4)
+    pulse = wl.Pulse(0.9, 0.7, 1.0)
+    t_final = pulse.duration
+    h0, h1 = np.diag(h.energies), dense_h(h.energies, h.dipole, 1.0) - np.diag(h.energies)
+    sol = solve_ivp(lambda t, y: -1j * (h0 + float(pulse(t)) * h1) @ y, (0, t_final),
+                    cplx(c0[0]).astype(complex), method="DOP853", rtol=1e-13, atol=1e-15)
+    ref = sol.y[:, -1]
+
+    def err(nst, where):
+        dt = t_final / nst
+        f = wl.taylor_samples(pulse, dt, nst, where)
+        cT = oracle_mod.taylor(h.energies, h.dipole, 10, dt, f[None], c0)
+        return np.abs(cplx(cT[0]) - ref).max()
+
+    left = [err(m, "left") for m in (200, 400, 800)]
+    mid = [err(m, "mid") for m in (200, 400, 800)]
+    assert 1.6 < left[0] / left[1] < 2.5 and 1.6 < left[1] / left[2] < 2.5, left
+    assert 3.2 < mid[0] / mid[1] < 5.0 and 3.2 < mid[1] / mid[2] < 5.0, mid
+
+
 def _golden():
     rows = []
     with open(os.path.join(HERE, "golden", "paper_values.txt")) as fh:
