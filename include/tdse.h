@@ -125,11 +125,14 @@ tdse_status tdse_propagate(tdse_plan plan, tdse_method method, int32_t taylor_or
                            double *ckpt, int32_t ckpt_every, void *stream);
 
 /*
- * Discrete adjoint of tdse_propagate (RK4 only; TDSE_E_UNSUPPORTED for
- * Taylor). For a real loss L(c(T)) with lambdaT = dL/dRe c(T) + i dL/dIm c(T)
- * ([batch][2*nstates] device), writes grad_field[batch][nsteps][3] =
- * dL/dfield (device, overwritten) and, if lambda0 != NULL, lambda0 =
- * dL/dRe c0 + i dL/dIm c0 ([batch][2*nstates] device).
+ * Discrete adjoint of tdse_propagate, for RK4 and for the Taylor series of
+ * order taylor_order (appendix B steps run backwards: the co-states of the
+ * RK4 stage derivatives, or of the Taylor terms Tbar_{m-1} = lambda +
+ * (i dt/m) H Tbar_m). For a real loss L(c(T)) with lambdaT = dL/dRe c(T) +
+ * i dL/dIm c(T) ([batch][2*nstates] device), writes grad_field[batch][nsteps][S]
+ * = dL/dfield (S = 3 for RK4, 1 for Taylor; device, overwritten) and, if
+ * lambda0 != NULL, lambda0 = dL/dRe c0 + i dL/dIm c0 ([batch][2*nstates]
+ * device).
  * ckpt: the checkpoints written by tdse_propagate with the same field, c0,
  * dt and ckpt_every (device), or NULL: then the library recomputes them into
  * plan-owned memory first. Forward states between checkpoints are recomputed

@@ -6,11 +6,11 @@ The compute path is the HIP library libtdse.so (C ABI in include/tdse.h);
 inputs. Import of the binding is lazy so the input generator can be used
 without loading the GPU runtime.
 """
-__all__ = ["Plan", "Group", "Propagate", "ionization_yield", "tune", "TdseError", "workloads"]
+__all__ = ["Plan", "Group", "Propagate", "piecewise_field", "ionization_yield", "tune", "TdseError", "workloads"]
 
 
 def __getattr__(name):
-    if name in ("Plan", "Group", "Propagate", "ionization_yield", "tune", "TdseError", "METHODS"):
+    if name in ("Plan", "Group", "Propagate", "piecewise_field", "ionization_yield", "tune", "TdseError", "METHODS"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

@@ -180,12 +180,14 @@ def ionization_yield(cT: torch.Tensor, energies) -> torch.Tensor:
 
 
 class Propagate(torch.autograd.Function):
-    """c(T) = RK4 map of (field, c0); backward runs the library's discrete adjoint."""
+    """c(T) = RK4 or Taylor-p map of (field, c0); backward runs the library's
+    discrete adjoint from the forward pass's checkpoints."""
 
     @staticmethod
-    def forward(ctx, field, c0, plan: Plan, dt: float, ckpt_every: int = 64):
-        cT, ck = plan.propagate(field, c0, dt, "rk4", ckpt_every=ckpt_every)
-        ctx.plan, ctx.dt, ctx.ckpt_every = plan, dt, ckpt_every
+    def forward(ctx, field, c0, plan: Plan, dt: float, ckpt_every: int = 64, method: str = "rk4",
+                order: int = 8):
+        cT, ck = plan.propagate(field, c0, dt, method, order=order, ckpt_every=ckpt_every)
+        ctx.plan, ctx.dt, ctx.ckpt_every, ctx.method, ctx.order = plan, dt, ckpt_every, method, order
         ctx.save_for_backward(field, c0, ck)
         return cT
 
@@ -193,9 +195,18 @@ class Propagate(torch.autograd.Function):
     def backward(ctx, grad_cT):
         field, c0, ck = ctx.saved_tensors
         plan = ctx.plan
-        g, l0 = plan.adjoint(field, c0, ctx.dt, grad_cT.contiguous(), ckpt=ck,
-                             ckpt_every=ctx.ckpt_every)
-        return g.reshape(field.shape), l0.reshape(c0.shape), None, None, None
+        g, l0 = plan.adjoint(field, c0, ctx.dt, grad_cT.contiguous(), ckpt=ck, ckpt_every=ctx.ckpt_every,
+                             method=ctx.method, order=ctx.order)
+        return g.reshape(field.shape), l0.reshape(c0.shape), None, None, None, None, None
 
 
-__all__ = ["Plan", "Group", "Propagate", "ionization_yield", "tune", "TdseError", "METHODS"]
+def piecewise_field(ek: torch.Tensor, steps_per: int, method: str = "rk4") -> torch.Tensor:
+    """Per-step samples [B, K * steps_per, S] of piecewise-constant fields
+    ek [B, K]: every stage sample of every step in interval k equals ek[:, k].
+    Differentiable: the backward sums the per-step, per-slot gradients over
+    each interval."""
+    rep = torch.repeat_interleave(ek, steps_per, dim=-1)
+    return rep.unsqueeze(-1).expand(*rep.shape, slots_of(method)).contiguous()
+
+
+__all__ = ["Plan", "Group", "Propagate", "piecewise_field", "ionization_yield", "tune", "TdseError", "METHODS"]

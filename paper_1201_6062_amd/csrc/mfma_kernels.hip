@@ -16,6 +16,7 @@
 // comes from lane 16k + i, B[k][j] from lane 16k + j, and output register r
 // of lane L holds row L/16 + 4r of column L % 16.
 #include "tdse_internal.h"
+#include "tdse_validate.h"
 
 namespace tdse {
 
@@ -432,32 +433,39 @@ hipError_t bat_pack_strided(const BatBuffers &b, const double *src, size_t pulse
     return hipGetLastError();
 }
 
-// gpart layout for one segment: [step][stage j-1][row tiles][batch];
-// stage 1 -> slot 0, stages 2 and 3 -> slot 1, stage 4 -> slot 2.
+// gpart layout for one segment: [step][product j][row tiles][batch]. RK4:
+// stage 1 -> slot 0, stages 2 and 3 -> slot 1, stage 4 -> slot 2; Taylor:
+// all terms of a step -> its one sample.
 __global__ void bat_reduce_grad_kernel(const double *gpart, int rowtiles, int batch, int64_t k0, int64_t len,
-                                       int64_t nsteps, double *grad) {
+                                       int64_t nsteps, int nprod, int rk4, double *grad) {
     const int64_t total = (int64_t)batch * len;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
         const int pulse = (int)(g / len);
         const int64_t kl = g % len;
-        double sj[4];
-        for (int j = 0; j < 4; ++j) {
-            const double *p = gpart + ((size_t)(kl * 4 + j) * rowtiles) * batch + pulse;
+        double sj[TAYLOR_MAX_ORDER];
+        for (int j = 0; j < nprod; ++j) {
+            const double *p = gpart + ((size_t)(kl * nprod + j) * rowtiles) * batch + pulse;
             double acc = 0.0;
             for (int rt = 0; rt < rowtiles; ++rt) acc += p[(size_t)rt * batch];
             sj[j] = acc;
         }
-        double *out = grad + ((size_t)pulse * nsteps + (k0 + kl)) * 3;
-        out[0] = sj[0];
-        out[1] = sj[2] + sj[1];
-        out[2] = sj[3];
+        if (rk4) {
+            double *out = grad + ((size_t)pulse * nsteps + (k0 + kl)) * 3;
+            out[0] = sj[0];
+            out[1] = sj[2] + sj[1];
+            out[2] = sj[3];
+        } else {
+            double t = 0.0;
+            for (int j = nprod - 1; j >= 0; --j) t += sj[j];
+            grad[(size_t)pulse * nsteps + (k0 + kl)] = t;
+        }
     }
 }
 
 hipError_t bat_reduce_grad(const double *gpart, int rowtiles, int batch, int64_t k0, int64_t len,
-                           int64_t nsteps, double *grad, hipStream_t s) {
+                           int64_t nsteps, int nprod, int rk4, double *grad, hipStream_t s) {
     hipLaunchKernelGGL(bat_reduce_grad_kernel, dim3(64), dim3(256), 0, s, gpart, rowtiles, batch, k0, len, nsteps,
-                       grad);
+                       nprod, rk4, grad);
     return hipGetLastError();
 }
 

@@ -350,17 +350,18 @@ static tdse_status bat_hmul(tdse_plan p, const double *fields, const double *u, 
 }
 
 // ---------------------------------------------------------------------------
-// Discrete adjoint of the batched RK4 map (reverse sweep over checkpointed
-// segments; the forward states inside a segment are recomputed from its
-// checkpoint and the four stage inputs of every step are kept).
+// Discrete adjoint of the batched RK4 / Taylor map (reverse sweep over
+// checkpointed segments; the forward states inside a segment are recomputed
+// from its checkpoint and the inputs of every product of a step are kept:
+// the four stage inputs of RK4, the terms T_0 .. T_{p-1} of Taylor-p).
 
-static tdse_status adj_workspace(tdse_plan p, int32_t K, bool need_ckpt, int64_t nsteps, double **fwd,
+static tdse_status adj_workspace(tdse_plan p, int32_t K, int nprod, bool need_ckpt, int64_t nsteps, double **fwd,
                                  double **ustore, double **gpart, double **ickpt) {
     const BatBuffers &b = p->bb;
     const size_t usz = (size_t)(b.lmax + 1) * b.np * b.ldu;
     const int rowtiles = (b.lmax + 1) * (b.np / b.tm);
     const size_t ns = (size_t)(b.lmax + 1) * b.n;
-    const size_t n_fwd = 4 * usz, n_us = (size_t)K * 4 * usz, n_gp = (size_t)K * 4 * rowtiles * b.batch;
+    const size_t n_fwd = 4 * usz, n_us = (size_t)K * nprod * usz, n_gp = (size_t)K * nprod * rowtiles * b.batch;
     const size_t n_ck = need_ckpt ? (size_t)b.batch * (size_t)(nsteps / K + 1) * 2 * ns + (size_t)b.batch * 2 * ns : 0;
     const size_t bytes = (n_fwd + n_us + n_gp + n_ck) * sizeof(double);
     if (bytes > p->adj_bytes) {
@@ -380,21 +381,23 @@ static tdse_status adj_workspace(tdse_plan p, int32_t K, bool need_ckpt, int64_t
     return TDSE_OK;
 }
 
-static tdse_status bat_adjoint(tdse_plan p, double dt, int64_t nsteps, const double *field, const double *c0,
-                               const double *ckpt, int32_t K, const double *lambdaT, double *grad,
-                               double *lambda0, hipStream_t s) {
+static tdse_status bat_adjoint(tdse_plan p, tdse_method method, int order, double dt, int64_t nsteps,
+                               const double *field, const double *c0, const double *ckpt, int32_t K,
+                               const double *lambdaT, double *grad, double *lambda0, hipStream_t s) {
     const BatBuffers &pb = p->bb;
     const size_t ns = (size_t)(pb.lmax + 1) * pb.n;
     const size_t usz = (size_t)(pb.lmax + 1) * pb.np * pb.ldu;
     const int rowtiles = (pb.lmax + 1) * (pb.np / pb.tm);
     const int64_t rows = nsteps / K + 1;
+    const bool rk4 = method == TDSE_RK4;
+    const int nprod = rk4 ? 4 : order, slots = rk4 ? 3 : 1;
     double *fwd, *ustore, *gpart, *ickpt;
-    tdse_status st = adj_workspace(p, K, ckpt == nullptr, nsteps, &fwd, &ustore, &gpart, &ickpt);
+    tdse_status st = adj_workspace(p, K, nprod, ckpt == nullptr, nsteps, &fwd, &ustore, &gpart, &ickpt);
     if (st != TDSE_OK) return st;
     if (!ckpt) {
         // forward pass writing checkpoints into the workspace (c(T) goes to its tail)
         double *cT = ickpt + (size_t)pb.batch * rows * 2 * ns;
-        st = bat_propagate(p, TDSE_RK4, 4, dt, nsteps, field, c0, cT, ickpt, K, s);
+        st = bat_propagate(p, method, order, dt, nsteps, field, c0, cT, ickpt, K, s);
         if (st != TDSE_OK) return st;
         ckpt = ickpt;
     }
@@ -405,32 +408,55 @@ static tdse_status bat_adjoint(tdse_plan p, double dt, int64_t nsteps, const dou
     fb.u[1] = fwd + usz;
     fb.c = fwd + 2 * usz;
     fb.acc = fwd + 3 * usz;
-    // adjoint state: c = lambda, acc = co-state sum, u = kbar
+    // adjoint state: c = lambda, acc = co-state sum, u = product input (RK4:
+    // kbar of the stage; Taylor: (dt/m) Tbar_m)
     BatBuffers ab = pb;
     ab.field = field;
-    TDSE_HIP(bat_pack_strided(ab, lambdaT, 2 * ns, dt / 6.0, s));
+    TDSE_HIP(bat_pack_strided(ab, lambdaT, 2 * ns, rk4 ? dt / 6.0 : dt / order, s));
     int apar = 0;
     std::vector<BatLaunch> fsched;
-    bat_schedule(TDSE_RK4, 4, fsched);
+    bat_schedule(method, order, fsched);
     const int64_t nseg = (nsteps + K - 1) / K;
     for (int64_t sg = nseg - 1; sg >= 0; --sg) {
         const int64_t k0 = sg * K, len = nsteps - k0 < K ? nsteps - k0 : K;
         TDSE_HIP(bat_pack_strided(fb, ckpt + (size_t)sg * 2 * ns, (size_t)rows * 2 * ns, 1.0, s));
         int fpar = 0;
         for (int64_t k = k0; k < k0 + len; ++k) {
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < nprod; ++j) {
                 BatLaunch L = fsched[j];
                 L.parity = fpar;
                 L.dt = dt;
                 L.step = k;
                 L.nsteps = nsteps;
-                L.slots = 3;
-                L.ustore = ustore + ((size_t)(k - k0) * 4 + j) * usz;
+                L.slots = slots;
+                L.ustore = ustore + ((size_t)(k - k0) * nprod + j) * usz;
                 TDSE_HIP(bat_launch_stage(fb, L, s));
                 fpar ^= 1;
             }
         }
-        for (int64_t k = k0 + len - 1; k >= k0; --k) {
+        for (int64_t k = k0 + len - 1; k >= k0 && !rk4; --k) {
+            // Taylor term m = p..1: input (dt/m) Tbar_m gives ubar = (i dt/m) H Tbar_m,
+            // Tbar_{m-1} = lambda + ubar; the next input is (dt/(m-1)) Tbar_{m-1},
+            // and after m = 1 the new lambda Tbar_0 scaled by dt/p.
+            for (int m = order; m >= 1; --m) {
+                BatLaunch L{};
+                L.kind = m > 1 ? CK_ADJ_MID : CK_ADJ_LAST;
+                L.slot = 0;
+                L.first = 1;
+                L.parity = apar;
+                L.dt = dt;
+                L.step = k;
+                L.nsteps = nsteps;
+                L.slots = 1;
+                L.ustore = ustore + ((size_t)(k - k0) * nprod + (m - 1)) * usz;
+                L.gpart = gpart + ((size_t)(k - k0) * nprod + (m - 1)) * rowtiles * pb.batch;
+                L.p_lam = m > 1 ? dt / (m - 1) : dt / order;
+                L.p_ub = m > 1 ? dt / (m - 1) : 0.0;
+                TDSE_HIP(bat_launch_adjoint(ab, L, s));
+                apar ^= 1;
+            }
+        }
+        for (int64_t k = k0 + len - 1; k >= k0 && rk4; --k) {
             for (int j = 4; j >= 1; --j) {
                 BatLaunch L{};
                 L.kind = j > 1 ? CK_ADJ_MID : CK_ADJ_LAST;
@@ -452,7 +478,7 @@ static tdse_status bat_adjoint(tdse_plan p, double dt, int64_t nsteps, const dou
                 apar ^= 1;
             }
         }
-        TDSE_HIP(bat_reduce_grad(gpart, rowtiles, pb.batch, k0, len, nsteps, grad, s));
+        TDSE_HIP(bat_reduce_grad(gpart, rowtiles, pb.batch, k0, len, nsteps, nprod, rk4 ? 1 : 0, grad, s));
     }
     if (lambda0) TDSE_HIP(bat_unpack(ab, lambda0, s));
     return TDSE_OK;
@@ -680,7 +706,6 @@ tdse_status tdse_adjoint(tdse_plan p, tdse_method method, int32_t order, double 
     tdse_status st = validate_propagate(p != nullptr, (int)method, method == TDSE_TAYLOR ? order : 4, dt, nsteps,
                                         true, ckpt_every, &why);
     if (st != TDSE_OK) return fail(st, why);
-    if (method != TDSE_RK4) return fail(TDSE_E_UNSUPPORTED, "the adjoint is implemented for RK4 only");
     if (nsteps > 0 && (st = check_dev(field, "field"))) return st;
     if ((st = check_dev(c0, "c0")) || (st = check_dev(lambdaT, "lambdaT"))) return st;
     if (nsteps > 0 && (st = check_dev(grad_field, "grad_field"))) return st;
@@ -696,7 +721,7 @@ tdse_status tdse_adjoint(tdse_plan p, tdse_method method, int32_t order, double 
         }
         q = p->adj_plan;
     }
-    return bat_adjoint(q, dt, nsteps, field, c0, ckpt, ckpt_every, lambdaT, grad_field, lambda0, s);
+    return bat_adjoint(q, method, order, dt, nsteps, field, c0, ckpt, ckpt_every, lambdaT, grad_field, lambda0, s);
 }
 
 // Captured group chunks hold the work-list addresses: drop them before the

@@ -184,7 +184,7 @@ hipError_t bat_pack_strided(const BatBuffers &b, const double *src, size_t pulse
 hipError_t bat_launch_adjoint(const BatBuffers &b, const BatLaunch &l, hipStream_t s);
 // grad[b][k][slot] for the steps k0 .. k0+len-1 from the partials of one segment
 hipError_t bat_reduce_grad(const double *gpart, int rowtiles, int batch, int64_t k0, int64_t len,
-                           int64_t nsteps, double *grad, hipStream_t s);
+                           int64_t nsteps, int nprod, int rk4, double *grad, hipStream_t s);
 hipError_t bat_unpack(const BatBuffers &b, double *out, hipStream_t s);
 hipError_t bat_ckpt0(const BatBuffers &b, const double *c0, double *ckpt, int rows, hipStream_t s);
 hipError_t bat_launch_stage(const BatBuffers &b, const BatLaunch &l, hipStream_t s);

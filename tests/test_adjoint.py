@@ -161,3 +161,90 @@ def test_adjoint_full_size_piecewise():
     fd = (y[0::2] - y[1::2]) / (2 * hstep)
     ga = gk[0, idx]
     assert np.abs(ga - fd).max() <= 1e-6 * np.abs(fd).max(), (ga, fd)
+
+
+# ---- Taylor-p adjoint
+
+def taylor_case(lmax=2, n=13, batch=3, nsteps=30, dt=0.04, seed=0, where="left"):
+    h = wl.hamiltonian(lmax, n, seed)
+    rng = np.random.default_rng(seed + 7)
+    ps = [wl.Pulse(0.5 + 0.2 * b, 0.8 + 0.1 * b, 1.0) for b in range(batch)]
+    f = np.stack([wl.taylor_samples(p, dt, nsteps, where) for p in ps]) + 0.05 * rng.standard_normal((batch, nsteps, 1))
+    c0 = wl.ground_state(lmax, n, batch)
+    return h, np.ascontiguousarray(f), c0, dt
+
+
+def oracle_taylor_grads(h, f, c0, dt, order):
+    gs, l0s = [], []
+    for b in range(f.shape[0]):
+        cT = oracle.taylor(h.energies, h.dipole, order, dt, f[b:b + 1], c0[b:b + 1])[0]
+        lam = oracle.yield_seed(h.energies, cT)[0]
+        l0, g = oracle.taylor_adjoint(h.energies, h.dipole, order, dt, f[b], c0[b], lam)
+        gs.append(g)
+        l0s.append(l0)
+    return np.stack(gs), np.stack(l0s)
+
+
+@pytest.mark.parametrize("batch,lmax,n,nsteps,order,k", [(3, 2, 13, 30, 4, 8), (2, 1, 11, 21, 1, 5),
+                                                        (1, 3, 20, 25, 8, 64), (4, 2, 70, 12, 6, 4)])
+def test_taylor_adjoint_matches_oracle(batch, lmax, n, nsteps, order, k):
+    h, f, c0, dt = taylor_case(lmax, n, batch, nsteps)
+    plan = make_plan(h, batch)
+    cT, ck = plan.propagate(f, c0, dt, "taylor", order=order, ckpt_every=k)
+    g, l0 = plan.adjoint(f, c0, dt, yield_seed_dev(plan, cT), ckpt=ck, ckpt_every=k, method="taylor", order=order)
+    g, l0 = g.cpu().numpy()[..., 0], l0.cpu().numpy()
+    g_ref, l0_ref = oracle_taylor_grads(h, f, c0, dt, order)
+    assert np.abs(g_ref).max() > 1e-6
+    assert np.abs(g - g_ref).max() <= 1e-10 * np.abs(g_ref).max()
+    assert np.abs(l0 - l0_ref).max() <= 1e-10 * np.abs(l0_ref).max()
+
+
+def test_taylor_adjoint_midpoint_samples_without_checkpoints():
+    """Midpoint field samples are just other samples to the library; no
+    checkpoints given: the library recomputes them."""
+    h, f, c0, dt = taylor_case(2, 40, 2, 33, where="mid", seed=5)
+    plan = make_plan(h, 2)
+    cT = plan.propagate(f, c0, dt, "taylor", order=8)
+    g, l0 = plan.adjoint(f, c0, dt, yield_seed_dev(plan, cT), ckpt=None, ckpt_every=10, method="taylor", order=8)
+    g_ref, l0_ref = oracle_taylor_grads(h, f, c0, dt, 8)
+    assert np.abs(g.cpu().numpy()[..., 0] - g_ref).max() <= 1e-10 * np.abs(g_ref).max()
+    assert np.abs(l0.cpu().numpy() - l0_ref).max() <= 1e-10 * np.abs(l0_ref).max()
+
+
+def test_taylor_adjoint_vs_central_fd():
+    h, f, c0, dt = taylor_case(3, 40, 1, 40, seed=9)
+    order = 8
+    plan1 = make_plan(h, 1)
+    cT, ck = plan1.propagate(f, c0, dt, "taylor", order=order, ckpt_every=16)
+    g, _ = plan1.adjoint(f, c0, dt, yield_seed_dev(plan1, cT), ckpt=ck, ckpt_every=16, method="taylor", order=order)
+    g = g.cpu().numpy()[0, :, 0]
+    idx = np.argsort(-np.abs(g))[:8].tolist() + np.linspace(0, g.size - 1, 8).astype(int).tolist()
+    hstep = 1e-6
+    fp = np.repeat(f, 32, axis=0)
+    for q, i in enumerate(idx):
+        fp[2 * q, i, 0] += hstep
+        fp[2 * q + 1, i, 0] -= hstep
+    cT32 = make_plan(h, 32).propagate(fp, np.repeat(c0, 32, axis=0), dt, "taylor", order=order).cpu().numpy()
+    y = oracle.ionization_yield(h.energies, cT32)
+    fd = (y[0::2] - y[1::2]) / (2 * hstep)
+    assert np.abs(g[idx] - fd).max() <= 1e-6 * np.abs(fd).max(), (g[idx], fd)
+
+
+def test_autograd_taylor_piecewise():
+    """d(yield)/d(piecewise field values) through piecewise_field and
+    Propagate (Taylor-6): the per-step adjoint gradients summed over each
+    interval, vs the oracle's adjoint collapsed the same way."""
+    from paper_1201_6062_amd.api import Propagate, ionization_yield, piecewise_field
+    h = wl.hamiltonian(2, 13, 3)
+    spi, nint, dt, order, batch = 4, 10, 0.05, 6, 2
+    rng = np.random.default_rng(12)
+    ek_np = rng.uniform(-0.6, 0.6, (batch, nint))
+    plan = make_plan(h, batch)
+    ek = torch.as_tensor(ek_np, device="cuda").requires_grad_(True)
+    c0 = torch.as_tensor(wl.ground_state(2, 13, batch), device="cuda")
+    cT = Propagate.apply(piecewise_field(ek, spi, "taylor"), c0, plan, dt, 8, "taylor", order)
+    ionization_yield(cT, h.energies).sum().backward()
+    f = wl.expand_piecewise(ek_np, spi, slots=1)
+    g_ref, _ = oracle_taylor_grads(h, f, wl.ground_state(2, 13, batch), dt, order)
+    gk_ref = wl.collapse_piecewise(g_ref[..., None], spi)
+    assert np.abs(ek.grad.cpu().numpy() - gk_ref).max() <= 1e-10 * np.abs(gk_ref).max()
