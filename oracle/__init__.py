@@ -53,6 +53,8 @@ def _load():
         lib.oracle_rk4_adjoint.restype = i32
         lib.oracle_taylor_adjoint.argtypes = [i32, i32, P, P, i32, d, i64, P, P, P, P]
         lib.oracle_taylor_adjoint.restype = i32
+        lib.oracle_set_gauge.argtypes = [i32]
+        lib.oracle_set_gauge.restype = None
         _lib = lib
     return _lib
 
@@ -66,6 +68,23 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+GAUGES = {"length": 0, "velocity": 1}
+
+
+class _gauge:
+    """Select the coupling gauge of the C oracle for one call (length by default)."""
+
+    def __init__(self, gauge):
+        self.code = GAUGES[gauge]
+
+    def __enter__(self):
+        _load().oracle_set_gauge(self.code)
+
+    def __exit__(self, *exc):
+        _load().oracle_set_gauge(0)
+        return False
+
+
 def _dims_n(energies, dipole, n=None):
     en = _f64(energies)
     dip = _f64(dipole)
@@ -76,108 +95,115 @@ def _dims_n(energies, dipole, n=None):
     return en, dip, lmax, n
 
 
-def dmul(energies, dipole, u, n=None):
+def dmul(energies, dipole, u, n=None, gauge="length"):
     """z = D u for one interleaved complex vector u."""
-    en, dip, lmax, n = _dims_n(energies, dipole, n)
-    u = _f64(u)
-    z = np.empty_like(u)
-    _load().oracle_dmul(lmax, n, _p(dip), _p(u), _p(z))
-    return z
+    with _gauge(gauge):
+        en, dip, lmax, n = _dims_n(energies, dipole, n)
+        u = _f64(u)
+        z = np.empty_like(u)
+        _load().oracle_dmul(lmax, n, _p(dip), _p(u), _p(z))
+        return z
 
 
-def hmul(energies, dipole, field, u, n=None):
+def hmul(energies, dipole, field, u, n=None, gauge="length"):
     """y = H(field) u = E o u + field * D u."""
-    en, dip, lmax, n = _dims_n(energies, dipole, n)
-    u = _f64(u)
-    y = np.empty_like(u)
-    _load().oracle_hmul(lmax, n, _p(en), _p(dip), float(field), _p(u), _p(y))
-    return y
+    with _gauge(gauge):
+        en, dip, lmax, n = _dims_n(energies, dipole, n)
+        u = _f64(u)
+        y = np.empty_like(u)
+        _load().oracle_hmul(lmax, n, _p(en), _p(dip), float(field), _p(u), _p(y))
+        return y
 
 
-def rk4(energies, dipole, dt, field, c0, n=None):
+def rk4(energies, dipole, dt, field, c0, n=None, gauge="length"):
     """RK4 over field[B, nsteps, 3] from c0[B, 2n]; returns c(T) [B, 2n]."""
-    en, dip, lmax, n = _dims_n(energies, dipole, n)
-    field = _f64(field)
-    c = np.array(c0, dtype=np.float64, copy=True, order="C")
-    if field.ndim == 2:
-        field = field[None]
-    if c.ndim == 1:
-        c = c[None]
-    assert field.shape[-1] == 3 and field.shape[0] == c.shape[0]
-    lib = _load()
-    for b in range(c.shape[0]):
-        fb = _f64(field[b])
-        cb = np.ascontiguousarray(c[b])
-        rc = lib.oracle_rk4(lmax, n, _p(en), _p(dip), float(dt), fb.shape[0], _p(fb), _p(cb))
-        if rc != 0:
-            raise MemoryError("oracle_rk4 allocation failed")
-        c[b] = cb
-    return c
+    with _gauge(gauge):
+        en, dip, lmax, n = _dims_n(energies, dipole, n)
+        field = _f64(field)
+        c = np.array(c0, dtype=np.float64, copy=True, order="C")
+        if field.ndim == 2:
+            field = field[None]
+        if c.ndim == 1:
+            c = c[None]
+        assert field.shape[-1] == 3 and field.shape[0] == c.shape[0]
+        lib = _load()
+        for b in range(c.shape[0]):
+            fb = _f64(field[b])
+            cb = np.ascontiguousarray(c[b])
+            rc = lib.oracle_rk4(lmax, n, _p(en), _p(dip), float(dt), fb.shape[0], _p(fb), _p(cb))
+            if rc != 0:
+                raise MemoryError("oracle_rk4 allocation failed")
+            c[b] = cb
+        return c
 
 
-def taylor(energies, dipole, order, dt, field, c0, n=None):
+def taylor(energies, dipole, order, dt, field, c0, n=None, gauge="length"):
     """Taylor-order propagation over field[B, nsteps, 1] (or [B, nsteps])."""
-    en, dip, lmax, n = _dims_n(energies, dipole, n)
-    field = _f64(field)
-    c = np.array(c0, dtype=np.float64, copy=True, order="C")
-    if c.ndim == 1:
-        c = c[None]
-    if field.ndim == 1:
-        field = field[None]
-    if field.ndim == 3:
-        field = field[..., 0]
-    lib = _load()
-    for b in range(c.shape[0]):
-        fb = _f64(field[b])
-        cb = np.ascontiguousarray(c[b])
-        rc = lib.oracle_taylor(lmax, n, _p(en), _p(dip), int(order), float(dt), fb.shape[0],
-                               _p(fb), _p(cb))
-        if rc != 0:
-            raise MemoryError("oracle_taylor allocation failed")
-        c[b] = cb
-    return c
+    with _gauge(gauge):
+        en, dip, lmax, n = _dims_n(energies, dipole, n)
+        field = _f64(field)
+        c = np.array(c0, dtype=np.float64, copy=True, order="C")
+        if c.ndim == 1:
+            c = c[None]
+        if field.ndim == 1:
+            field = field[None]
+        if field.ndim == 3:
+            field = field[..., 0]
+        lib = _load()
+        for b in range(c.shape[0]):
+            fb = _f64(field[b])
+            cb = np.ascontiguousarray(c[b])
+            rc = lib.oracle_taylor(lmax, n, _p(en), _p(dip), int(order), float(dt), fb.shape[0],
+                                   _p(fb), _p(cb))
+            if rc != 0:
+                raise MemoryError("oracle_taylor allocation failed")
+            c[b] = cb
+        return c
 
 
-def rk4_tangent(energies, dipole, dt, field, dfield, c0, dc0=None, n=None):
+def rk4_tangent(energies, dipole, dt, field, dfield, c0, dc0=None, n=None, gauge="length"):
     """Returns (c(T), dc(T)) for one pulse: field, dfield [nsteps, 3]."""
-    en, dip, lmax, n = _dims_n(energies, dipole, n)
-    field, dfield = _f64(field), _f64(dfield)
-    c = np.array(c0, dtype=np.float64, copy=True).reshape(-1)
-    dc = np.zeros_like(c) if dc0 is None else np.array(dc0, dtype=np.float64, copy=True).reshape(-1)
-    rc = _load().oracle_rk4_tangent(lmax, n, _p(en), _p(dip), float(dt), field.shape[0],
-                                    _p(field), _p(dfield), _p(c), _p(dc))
-    if rc != 0:
-        raise MemoryError("oracle_rk4_tangent allocation failed")
-    return c, dc
+    with _gauge(gauge):
+        en, dip, lmax, n = _dims_n(energies, dipole, n)
+        field, dfield = _f64(field), _f64(dfield)
+        c = np.array(c0, dtype=np.float64, copy=True).reshape(-1)
+        dc = np.zeros_like(c) if dc0 is None else np.array(dc0, dtype=np.float64, copy=True).reshape(-1)
+        rc = _load().oracle_rk4_tangent(lmax, n, _p(en), _p(dip), float(dt), field.shape[0],
+                                        _p(field), _p(dfield), _p(c), _p(dc))
+        if rc != 0:
+            raise MemoryError("oracle_rk4_tangent allocation failed")
+        return c, dc
 
 
-def rk4_adjoint(energies, dipole, dt, field, c0, lam_t, n=None):
+def rk4_adjoint(energies, dipole, dt, field, c0, lam_t, n=None, gauge="length"):
     """Discrete RK4 adjoint for one pulse. Returns (lambda_0, grad[nsteps, 3])."""
-    en, dip, lmax, n = _dims_n(energies, dipole, n)
-    field = _f64(field)
-    c0 = _f64(np.asarray(c0).reshape(-1))
-    lam = np.array(lam_t, dtype=np.float64, copy=True).reshape(-1)
-    grad = np.zeros_like(field)
-    rc = _load().oracle_rk4_adjoint(lmax, n, _p(en), _p(dip), float(dt), field.shape[0],
-                                    _p(field), _p(c0), _p(lam), _p(grad))
-    if rc != 0:
-        raise MemoryError("oracle_rk4_adjoint allocation failed")
-    return lam, grad
+    with _gauge(gauge):
+        en, dip, lmax, n = _dims_n(energies, dipole, n)
+        field = _f64(field)
+        c0 = _f64(np.asarray(c0).reshape(-1))
+        lam = np.array(lam_t, dtype=np.float64, copy=True).reshape(-1)
+        grad = np.zeros_like(field)
+        rc = _load().oracle_rk4_adjoint(lmax, n, _p(en), _p(dip), float(dt), field.shape[0],
+                                        _p(field), _p(c0), _p(lam), _p(grad))
+        if rc != 0:
+            raise MemoryError("oracle_rk4_adjoint allocation failed")
+        return lam, grad
 
 
-def taylor_adjoint(energies, dipole, order, dt, field, c0, lam_t, n=None):
+def taylor_adjoint(energies, dipole, order, dt, field, c0, lam_t, n=None, gauge="length"):
     """Discrete Taylor-p adjoint for one pulse (field [nsteps] or [nsteps, 1]).
     Returns (lambda_0, grad[nsteps])."""
-    en, dip, lmax, n = _dims_n(energies, dipole, n)
-    field = _f64(np.asarray(field).reshape(-1))
-    c0 = _f64(np.asarray(c0).reshape(-1))
-    lam = np.array(lam_t, dtype=np.float64, copy=True).reshape(-1)
-    grad = np.zeros_like(field)
-    rc = _load().oracle_taylor_adjoint(lmax, n, _p(en), _p(dip), int(order), float(dt), field.shape[0],
-                                       _p(field), _p(c0), _p(lam), _p(grad))
-    if rc != 0:
-        raise MemoryError("oracle_taylor_adjoint allocation failed")
-    return lam, grad
+    with _gauge(gauge):
+        en, dip, lmax, n = _dims_n(energies, dipole, n)
+        field = _f64(np.asarray(field).reshape(-1))
+        c0 = _f64(np.asarray(c0).reshape(-1))
+        lam = np.array(lam_t, dtype=np.float64, copy=True).reshape(-1)
+        grad = np.zeros_like(field)
+        rc = _load().oracle_taylor_adjoint(lmax, n, _p(en), _p(dip), int(order), float(dt), field.shape[0],
+                                           _p(field), _p(c0), _p(lam), _p(grad))
+        if rc != 0:
+            raise MemoryError("oracle_taylor_adjoint allocation failed")
+        return lam, grad
 
 
 def positive_mask(energies):

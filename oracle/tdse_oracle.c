@@ -18,6 +18,9 @@
  * The derivative is the block matrix-vector product of Sec. 4:
  *   (H u)_l = E_l u_l + F (D_l u_{l+1} + D_{l-1}^T u_{l-1}).
  *
+ * The velocity gauge of Sec. 5 replaces F D by A(t) P with the momentum
+ * coupling P = -i Q (oracle_set_gauge); every function below then uses it.
+ *
  * Complex vectors are interleaved (re, im) doubles. All arithmetic is double,
  * in natural ascending index order, with no blocking or reordering. Build
  * without FMA contraction (-ffp-contract=off) so every product is rounded
@@ -40,6 +43,16 @@
 #define RE(v, j) (v)[2 * (size_t)(j)]
 #define IM(v, j) (v)[2 * (size_t)(j) + 1]
 
+/*
+ * Gauge of the coupling blocks (Sec. 5). Length gauge (0): the blocks are the
+ * real dipole D_l and the coupling is real symmetric, H = E + F D. Velocity
+ * gauge (1): the blocks hold the real matrix Q_l of the momentum coupling
+ * P = -i Q (P_{l,l+1} = -i Q_l, P_{l+1,l} = +i Q_l^T, so P is Hermitian and
+ * imaginary) and F is the vector potential A(t): H = E + A P.
+ */
+static int g_gauge = 0;
+void oracle_set_gauge(int gauge) { g_gauge = gauge; }
+
 /* z = D u (the field-coupling part of H, without the field factor). */
 void oracle_dmul(int lmax, int n, const double *dip, const double *u, double *z)
 {
@@ -47,33 +60,39 @@ void oracle_dmul(int lmax, int n, const double *dip, const double *u, double *z)
     for (size_t j = 0; j < ns; ++j) { RE(z, j) = 0.0; IM(z, j) = 0.0; }
     for (int l = 0; l <= lmax; ++l) {
         for (int a = 0; a < n; ++a) {
-            double sr = 0.0, si = 0.0;
-            /* D_l u_{l+1}: row a of block l. */
+            double ur = 0.0, ui = 0.0, dr = 0.0, di = 0.0;
+            /* block l+1 -> l: row a of block l times u_{l+1} */
             if (l < lmax) {
                 const double *row = dip + ((size_t)l * n + a) * n;
                 for (int b = 0; b < n; ++b) {
                     size_t jb = (size_t)(l + 1) * n + b;
-                    sr += row[b] * RE(u, jb);
-                    si += row[b] * IM(u, jb);
+                    ur += row[b] * RE(u, jb);
+                    ui += row[b] * IM(u, jb);
                 }
             }
-            /* D_{l-1}^T u_{l-1}: column a of block l-1. */
+            /* block l-1 -> l: column a of block l-1 (its transpose) times u_{l-1} */
             if (l > 0) {
                 const double *blk = dip + (size_t)(l - 1) * n * n;
                 for (int b = 0; b < n; ++b) {
                     size_t jb = (size_t)(l - 1) * n + b;
-                    sr += blk[(size_t)b * n + a] * RE(u, jb);
-                    si += blk[(size_t)b * n + a] * IM(u, jb);
+                    dr += blk[(size_t)b * n + a] * RE(u, jb);
+                    di += blk[(size_t)b * n + a] * IM(u, jb);
                 }
             }
             size_t ja = (size_t)l * n + a;
-            RE(z, ja) = sr;
-            IM(z, ja) = si;
+            if (g_gauge == 0) {
+                RE(z, ja) = ur + dr;
+                IM(z, ja) = ui + di;
+            } else {
+                /* -i Q_l u_{l+1} + i Q_{l-1}^T u_{l-1} = -i (up - down); -i (x + iy) = y - ix */
+                RE(z, ja) = ui - di;
+                IM(z, ja) = -(ur - dr);
+            }
         }
     }
 }
 
-/* y = H(F) u = E o u + F (D u). */
+/* y = H(F) u = E o u + F (D u)  (velocity gauge: E o u + A (P u)). */
 void oracle_hmul(int lmax, int n, const double *en, const double *dip, double f,
                  const double *u, double *y)
 {

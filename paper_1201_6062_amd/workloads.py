@@ -122,6 +122,57 @@ def random_pulses(rng: np.random.Generator, count: int, ncyc: float = 10.0):
 # The five workloads.
 
 
+# ---- velocity gauge (Sec. 5): the coupling is -p.A(t)/c with A = -int E dt
+
+# 5-point Gauss-Legendre nodes and weights on [-1, 1]
+_GL5_X = np.array([-0.9061798459386640, -0.5384693101056831, 0.0, 0.5384693101056831, 0.9061798459386640])
+_GL5_W = np.array([0.2369268850561891, 0.4786286704993665, 0.5688888888888889, 0.4786286704993665,
+                   0.2369268850561891])
+
+
+def _gl5(pulse, a, b):
+    """int_a^b E(t) dt by 5-point Gauss-Legendre quadrature (elementwise over a, b)."""
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    mid, half = 0.5 * (a + b), 0.5 * (b - a)
+    t = mid[..., None] + half[..., None] * _GL5_X
+    return half * (pulse(t) * _GL5_W).sum(axis=-1)
+
+
+def vector_potential_exact(pulse, t):
+    """A(t) = -int_0^t E, closed form for the sin^2 cos pulse (constant after the pulse)."""
+    t = np.clip(np.asarray(t, dtype=np.float64), 0.0, pulse.duration)
+    w, big = pulse.omega, 2.0 * math.pi / pulse.duration
+    val = (np.sin(w * t) / w - np.sin((w + big) * t) / (2.0 * (w + big))
+           - np.sin((w - big) * t) / (2.0 * (w - big)))
+    return -0.5 * pulse.e0 * val
+
+
+def vector_potential_samples(pulse, dt: float, nsteps: int, method: str = "rk4", where: str = "left"):
+    """A(t) at the stage times of each step, accumulated step by step with
+    5-point Gauss-Legendre quadrature of E (the paper's velocity-gauge
+    procedure). RK4: [nsteps, 3] at t_k, t_k + dt/2, t_k + dt; Taylor:
+    [nsteps, 1] at the step's left end or midpoint."""
+    k = np.arange(nsteps, dtype=np.float64)
+    t0 = k * dt
+    a_start = -np.concatenate([[0.0], np.cumsum(_gl5(pulse, t0, t0 + dt))])[:nsteps]
+    if method == "rk4":
+        a_mid = a_start - _gl5(pulse, t0, t0 + 0.5 * dt)
+        a_end = a_start - _gl5(pulse, t0, t0 + dt)
+        return np.ascontiguousarray(np.stack([a_start, a_mid, a_end], axis=1))
+    if where == "mid":
+        return np.ascontiguousarray((a_start - _gl5(pulse, t0, t0 + 0.5 * dt))[:, None])
+    return np.ascontiguousarray(a_start[:, None])
+
+
+def velocity_coupling(energies: np.ndarray, dipole: np.ndarray) -> np.ndarray:
+    """Blocks Q_l of the momentum coupling P = -i Q that matches the dipole:
+    P = i [H0, D] in this basis, i.e. P_{l,l+1}[a, b] = i (E_l[a] - E_{l+1}[b]) D_l[a, b],
+    so Q_l[a, b] = (E_{l+1}[b] - E_l[a]) D_l[a, b] (real; P is Hermitian)."""
+    lmax, n = dipole.shape[0], dipole.shape[1]
+    e = np.asarray(energies).reshape(lmax + 1, n)
+    return np.ascontiguousarray((e[1:, None, :] - e[:-1, :, None]) * dipole)
+
+
 @dataclass
 class Hamiltonian:
     lmax: int

@@ -487,6 +487,111 @@ def test_midpoint_taylor_second_order_in_field(oracle_mod):
     assert 3.2 < mid[0] / mid[1] < 5.0 and 3.2 < mid[1] / mid[2] < 5.0, mid
 
 
+# ---- velocity gauge (Sec. 5): H = E + A(t) P, P = -i Q Hermitian
+
+def dense_h_velocity(en, q, a):
+    """Full complex matrix: P_{l,l+1} = -i Q_l, P_{l+1,l} = +i Q_l^T."""
+    lmax, n = q.shape[0], en.size // (q.shape[0] + 1)
+    h = np.diag(en).astype(np.complex128)
+    for l in range(lmax):
+        r, c = slice(l * n, (l + 1) * n), slice((l + 1) * n, (l + 2) * n)
+        h[r, c] += -1j * a * q[l]
+        h[c, r] += 1j * a * q[l].T
+    return h
+
+
+@pytest.mark.parametrize("lmax,n", [(1, 1), (2, 3), (3, 5)])
+def test_velocity_hmul_matches_dense_assembly(oracle_mod, lmax, n):
+    rng = np.random.default_rng(40 + n)
+    en, q = random_system(rng, lmax, n)      # non-symmetric blocks: a wrong transpose shows
+    u = rng.standard_normal(2 * en.size)
+    for a in (0.0, 0.37, -1.3):
+        y = oracle_mod.hmul(en, q, a, u, n=n, gauge="velocity")
+        ref = dense_h_velocity(en, q, a) @ cplx(u)
+        np.testing.assert_allclose(cplx(y), ref, rtol=0, atol=1e-13 * max(1.0, np.abs(ref).max()))
+        assert np.allclose(dense_h_velocity(en, q, a), dense_h_velocity(en, q, a).conj().T)
+
+
+def test_velocity_coupling_is_the_commutator():
+    """P = -i Q built from the dipole equals i [H0, D] in the basis."""
+    h = wl.hamiltonian(2, 6, 3)
+    q = wl.velocity_coupling(h.energies, h.dipole)
+    p_dense = dense_h_velocity(np.zeros_like(h.energies), q, 1.0)
+    d_dense = dense_h(np.zeros_like(h.energies), h.dipole, 1.0)
+    h0 = np.diag(h.energies)
+    np.testing.assert_allclose(p_dense, 1j * (h0 @ d_dense - d_dense @ h0), rtol=0, atol=1e-14)
+
+
+def test_velocity_rk4_dense_step_product(oracle_mod):
+    h = wl.hamiltonian(2, 3, 5)
+    q = wl.velocity_coupling(h.energies, h.dipole)
+    rng = np.random.default_rng(6)
+    c0 = wl.random_state(rng, h.nstates)
+    dt, nst = 0.05, 60
+    ak = stepwise_fields(nst, dt, seed=1)
+    cT = oracle_mod.rk4(h.energies, q, dt, np.repeat(ak[:, None], 3, axis=1)[None], c0, gauge="velocity")
+    v = cplx(c0[0])
+    for k in range(nst):
+        lam, w = np.linalg.eigh(dense_h_velocity(h.energies, q, ak[k]))
+        v = (w * poly_exp(-1j * lam * dt, 4)[None, :]) @ (w.conj().T @ v)
+    np.testing.assert_allclose(cplx(cT[0]), v, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("method", ["rk4", "taylor"])
+def test_velocity_adjoint_dot_product_and_fd(oracle_mod, method):
+    h = wl.hamiltonian(2, 13, 8)
+    q = wl.velocity_coupling(h.energies, h.dipole)
+    dt, nst, order = 0.05, 30, 6
+    pulse = wl.Pulse(0.9, 0.8, 1.0)
+    f = wl.vector_potential_samples(pulse, dt, nst, method)
+    if method == "taylor":
+        f = f[:, 0]
+    c0 = wl.ground_state(2, 13)[0]
+    rng = np.random.default_rng(9)
+
+    def fwd(ff, c):
+        if method == "rk4":
+            return oracle_mod.rk4(h.energies, q, dt, ff[None], c[None], gauge="velocity")[0]
+        return oracle_mod.taylor(h.energies, q, order, dt, ff[None], c[None], gauge="velocity")[0]
+
+    def adj(lam):
+        if method == "rk4":
+            return oracle_mod.rk4_adjoint(h.energies, q, dt, f, c0, lam, gauge="velocity")
+        return oracle_mod.taylor_adjoint(h.energies, q, order, dt, f, c0, lam, gauge="velocity")
+
+    lam_t = rng.standard_normal(c0.size)
+    dc0 = rng.standard_normal(c0.size)
+    lam0, _ = adj(lam_t)
+    lhs, rhs = np.dot(lam0, dc0), np.dot(lam_t, fwd(f, dc0))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    cT = fwd(f, c0)
+    _, grad = adj(oracle_mod.yield_seed(h.energies, cT)[0])
+    scale = np.abs(grad).max()
+    assert scale > 1e-5
+    hstep = 1e-5
+    for i in np.argsort(-np.abs(grad).ravel())[:6]:
+        fp, fm = f.copy(), f.copy()
+        fp.flat[i] += hstep
+        fm.flat[i] -= hstep
+        fd = (oracle_mod.ionization_yield(h.energies, fwd(fp, c0))[0]
+              - oracle_mod.ionization_yield(h.energies, fwd(fm, c0))[0]) / (2 * hstep)
+        assert abs(fd - grad.flat[i]) <= 1e-6 * scale, (i, fd, grad.flat[i])
+
+
+def test_vector_potential_quadrature_matches_closed_form():
+    """Step-wise 5-point Gauss-Legendre accumulation of A = -int E vs the
+    closed-form integral of the sin^2 cos pulse, at every stage time."""
+    p = wl.Pulse(0.05, 0.5, 10.0)
+    dt = 0.01
+    nst = wl.nsteps_for(p.duration, dt)
+    a = wl.vector_potential_samples(p, dt, nst, "rk4")
+    t = np.arange(nst) * dt
+    exact = np.stack([wl.vector_potential_exact(p, t + s * dt) for s in (0.0, 0.5, 1.0)], axis=1)
+    assert np.abs(a - exact).max() <= 1e-12 * np.abs(exact).max()
+    mid = wl.vector_potential_samples(p, dt, nst, "taylor", "mid")[:, 0]
+    assert np.abs(mid - wl.vector_potential_exact(p, t + 0.5 * dt)).max() <= 1e-12 * np.abs(exact).max()
+
+
 def _golden():
     rows = []
     with open(os.path.join(HERE, "golden", "paper_values.txt")) as fh:
