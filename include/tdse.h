@@ -73,6 +73,11 @@ typedef enum {
     TDSE_TAYLOR = 1          /* truncated Taylor series of order p, p products per step */
 } tdse_method;
 
+typedef enum {
+    TDSE_LENGTH = 0,         /* coupling F(t) D, D real symmetric (the dipole blocks) */
+    TDSE_VELOCITY = 1        /* coupling A(t) P, P = -i Q Hermitian (momentum blocks Q) */
+} tdse_gauge;
+
 /* Version of this ABI (TDSE_ABI_VERSION of the built library). */
 int tdse_abi_version(void);
 
@@ -93,6 +98,20 @@ const char *tdse_last_error(void);
  */
 tdse_status tdse_create(tdse_plan *out, const double *energies, const double *dipole,
                         int32_t lmax, int32_t n, int32_t batch, void *stream);
+
+/*
+ * As tdse_create, with the gauge of the coupling (Sec. 5: the paper's runs
+ * use the velocity gauge, -p.A(t)/c). TDSE_LENGTH: coupling holds the dipole
+ * blocks D_l and the field samples are E(t); identical to tdse_create.
+ * TDSE_VELOCITY: coupling holds the real blocks Q_l of the momentum coupling
+ * P = -i Q, i.e. P_{l,l+1} = -i Q_l and P_{l+1,l} = +i Q_l^T (P Hermitian,
+ * imaginary), and the field samples are the vector potential A(t); the
+ * derivative is -i (E o u + A (P u)). Everything else (propagation, adjoint,
+ * groups) is the same for both gauges. Errors: as tdse_create, and
+ * TDSE_E_INVAL for an unknown gauge.
+ */
+tdse_status tdse_create_gauge(tdse_plan *out, const double *energies, const double *coupling,
+                              tdse_gauge gauge, int32_t lmax, int32_t n, int32_t batch, void *stream);
 
 /* Release a plan and everything it owns. Synchronises the device. NULL is a no-op. */
 tdse_status tdse_destroy(tdse_plan plan);

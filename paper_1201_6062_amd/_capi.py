@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libtdse.so")
 
 TDSE_OK, TDSE_E_INVAL, TDSE_E_NOMEM, TDSE_E_HIP, TDSE_E_UNSUPPORTED, TDSE_E_UNSTABLE = range(6)
 TDSE_RK4, TDSE_TAYLOR = 0, 1
+TDSE_LENGTH, TDSE_VELOCITY = 0, 1
 STATUS_NAMES = {0: "TDSE_OK", 1: "TDSE_E_INVAL", 2: "TDSE_E_NOMEM", 3: "TDSE_E_HIP",
                 4: "TDSE_E_UNSUPPORTED", 5: "TDSE_E_UNSTABLE"}
 
@@ -26,6 +27,7 @@ SIGNATURES = {
     "tdse_abi_version": (ctypes.c_int, []),
     "tdse_last_error": (ctypes.c_char_p, []),
     "tdse_create": (_st, [ctypes.POINTER(_vp), _vp, _vp, _i32, _i32, _i32, _vp]),
+    "tdse_create_gauge": (_st, [ctypes.POINTER(_vp), _vp, _vp, _st, _i32, _i32, _i32, _vp]),
     "tdse_destroy": (_st, [_vp]),
     "tdse_plan_shape": (_st, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "tdse_hmul": (_st, [_vp, _vp, _vp, _vp, _vp]),

@@ -12,9 +12,10 @@ import numpy as np
 import torch
 
 from . import _capi
-from ._capi import TDSE_RK4, TDSE_TAYLOR, TdseError, check
+from ._capi import TDSE_LENGTH, TDSE_RK4, TDSE_TAYLOR, TDSE_VELOCITY, TdseError, check
 
 METHODS = {"rk4": TDSE_RK4, "taylor": TDSE_TAYLOR}
+GAUGES = {"length": TDSE_LENGTH, "velocity": TDSE_VELOCITY}
 
 
 def _stream(device=None):
@@ -38,9 +39,13 @@ def slots_of(method: str) -> int:
 
 
 class Plan:
-    """One Hamiltonian (energies [(L+1)N], upper dipole blocks [L, N, N]) and a batch width."""
+    """One Hamiltonian (energies [(L+1)N], upper coupling blocks [L, N, N]) and a batch width.
 
-    def __init__(self, energies, dipole, batch: int = 1, device="cuda"):
+    gauge="length": the blocks are the dipole D_l and field samples are E(t);
+    gauge="velocity": the blocks are Q_l of the momentum coupling P = -i Q and
+    field samples are the vector potential A(t)."""
+
+    def __init__(self, energies, dipole, batch: int = 1, device="cuda", gauge: str = "length"):
         self._lib = _capi.load()
         self.device = torch.device(device)
         en = _dev_f64(energies, self.device).reshape(-1)
@@ -53,8 +58,9 @@ class Plan:
         self.energies = en
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            check(self._lib.tdse_create(ctypes.byref(h), _ptr(en), _ptr(dip) if self.lmax else None,
-                                        self.lmax, self.n, self.batch, _stream(self.device)))
+            check(self._lib.tdse_create_gauge(ctypes.byref(h), _ptr(en), _ptr(dip) if self.lmax else None,
+                                              GAUGES[gauge], self.lmax, self.n, self.batch, _stream(self.device)))
+        self.gauge = gauge
         self._h = h
 
     @property

@@ -207,7 +207,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
                 const int row = r0 + wy * C::WM + i * 16 + (lane >> 4) + 4 * r;
                 const size_t gi = ((size_t)m * Np + row) * ldu + col;
                 const double E0 = b.en[(size_t)m * Np + row];
-                const double z = acc[i][j][r], zp = bat_xor1(z);
+                // coupling product of this column (z) and of its real/imaginary
+                // partner (zp); velocity gauge: -i times the contraction
+                const double zc = acc[i][j][r], zcp = bat_xor1(zc);
+                const double z = b.gauge ? (is_im ? -zcp : zcp) : zc;
+                const double zp = b.gauge ? (is_im ? zc : -zc) : zcp;
                 const double uo = U[gi], up = bat_xor1(uo);
                 if constexpr (ADJ) {
                     // ubar = i (E0 kbar + F w): re = -(E0 kbar_im + F w_im), im = E0 kbar_re + F w_re
@@ -336,8 +340,10 @@ __global__ void bat_ckpt0_kernel(BatBuffers b, const double *c0, double *ckpt, i
     }
 }
 
-// Row-major D and D^T with rows and columns zero-padded to Np.
-__global__ void bat_layout_kernel(const double *src, double *d, double *dT, int lmax, int n, int Np) {
+// Row-major D and D^T with rows and columns zero-padded to Np. d feeds the
+// column (transposed) use of a block; in the velocity gauge it holds -Q so
+// that one contraction gives Q_m U_{m+1} - Q_{m-1}^T U_{m-1}.
+__global__ void bat_layout_kernel(const double *src, double *d, double *dT, int lmax, int n, int Np, double dsign) {
     const size_t total = (size_t)lmax * Np * Np;
     for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (size_t)gridDim.x * blockDim.x) {
         const int c = (int)(g % Np);
@@ -345,7 +351,7 @@ __global__ void bat_layout_kernel(const double *src, double *d, double *dT, int 
         const int r = (int)(rg % Np), l = (int)(rg / Np);
         double v = 0.0, vt = 0.0;
         if (r < n && c < n) {
-            v = src[((size_t)l * n + r) * n + c];
+            v = dsign * src[((size_t)l * n + r) * n + c];
             vt = src[((size_t)l * n + c) * n + r];
         }
         d[g] = v;
@@ -363,7 +369,8 @@ __global__ void bat_energy_kernel(const double *src, double *dst, int lmax, int 
 
 hipError_t bat_layout(const double *src_dip, const double *src_en, BatBuffers &b, hipStream_t s) {
     if (b.lmax > 0)
-        hipLaunchKernelGGL(bat_layout_kernel, dim3(2048), dim3(256), 0, s, src_dip, b.d, b.dT, b.lmax, b.n, b.np);
+        hipLaunchKernelGGL(bat_layout_kernel, dim3(2048), dim3(256), 0, s, src_dip, b.d, b.dT, b.lmax, b.n, b.np,
+                           b.gauge == TDSE_VELOCITY ? -1.0 : 1.0);
     hipLaunchKernelGGL(bat_energy_kernel, dim3(64), dim3(256), 0, s, src_en, b.en, b.lmax, b.n, b.np);
     return hipGetLastError();
 }

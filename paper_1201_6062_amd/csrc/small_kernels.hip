@@ -39,7 +39,7 @@ struct SmallArgs {
     double *ckpt;          // [nsteps/K + 1][2 ns] or null
     int64_t nsteps, ckpt_every;
     double dt;
-    int32_t lmax, n, method, order;
+    int32_t lmax, n, method, order, gauge;
 };
 
 // EPL: compiled bound on the dipole elements per lane, ceil(2n / 4) <= EPL.
@@ -69,7 +69,8 @@ __global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
             if (e < n) {  // row a of D_m
                 if (m < lmax) v = A.dip[(size_t)m * tile + tile_pos(a, e)];
             } else {      // column a of D_{m-1}
-                if (m > 0) v = A.dip[(size_t)(m - 1) * tile + tile_pos(e - n, a)];
+                // velocity gauge: the column use enters with a minus sign, -i (r - s)
+                if (m > 0) v = (A.gauge ? -1.0 : 1.0) * A.dip[(size_t)(m - 1) * tile + tile_pos(e - n, a)];
             }
         }
         d[k] = v;
@@ -122,6 +123,11 @@ __global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
             zi += small_dpp(zi, 1);
             zr += small_dpp(zr, 2);
             zi += small_dpp(zi, 2);
+            if (A.gauge) {  // z = -i (r - s): (x + iy) -> (y - ix)
+                const double t = zr;
+                zr = zi;
+                zi = -t;
+            }
             if (live && g == 0) {
                 const double2 u = ubuf[par][es];
                 int slot = 0;
@@ -168,10 +174,10 @@ __global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
 
 bool small_eligible(int lmax, int n) { return n <= 64 && (lmax + 1) * n <= 256; }
 
-hipError_t small_propagate(const double *en, const double *dip, int lmax, int n, int method, int order, double dt,
+hipError_t small_propagate(const double *en, const double *dip, int gauge, int lmax, int n, int method, int order, double dt,
                            int64_t nsteps, const double *field, const double *c0, double *cT, double *ckpt,
                            int64_t ckpt_every, hipStream_t s) {
-    SmallArgs A{en, dip, field, c0, cT, ckpt, nsteps, ckpt_every > 0 ? ckpt_every : 1, dt, lmax, n, method, order};
+    SmallArgs A{en, dip, field, c0, cT, ckpt, nsteps, ckpt_every > 0 ? ckpt_every : 1, dt, lmax, n, method, order, gauge};
     const int threads = (((lmax + 1) * n * 4 + 63) / 64) * 64;
     const int epl = (2 * n + 3) / 4;
     if (epl <= 16) hipLaunchKernelGGL(small_propagate_kernel<16>, dim3(1), dim3(threads), 0, s, A);

@@ -135,7 +135,7 @@ static tdse_status vec_propagate(tdse_plan p, tdse_method m, int order, double d
                                  const double *field, const double *c0, double *cT, double *ckpt,
                                  int32_t K, hipStream_t s) {
     if (p->small) {
-        TDSE_HIP(small_propagate(p->en, p->dip, p->lmax, p->n, (int)m, order, dt, nsteps, field, c0, cT, ckpt,
+        TDSE_HIP(small_propagate(p->en, p->dip, p->gauge, p->lmax, p->n, (int)m, order, dt, nsteps, field, c0, cT, ckpt,
                                  ckpt ? K : 1, s));
         return TDSE_OK;
     }
@@ -212,6 +212,7 @@ static tdse_status vec_alloc(tdse_plan p) {
     p->vb.n = p->n;
     p->vb.ld = p->ld;
     p->vb.T = p->T;
+    p->vb.gauge = p->gauge;
     for (int q = 0; q <= 16; ++q) p->vb.seg[q] = (int32_t)split_start(p->n, p->T, q < p->T ? q : p->T);
     return TDSE_OK;
 }
@@ -247,6 +248,7 @@ static void bat_pick_tile(int lmax, int n, int batch, const TileChoice *force, i
 static tdse_status bat_create(tdse_plan p, const double *energies, const double *dipole,
                               hipStream_t s, const TileChoice *force) {
     BatBuffers &b = p->bb;
+    b.gauge = p->gauge;
     b.lmax = p->lmax;
     b.n = p->n;
     b.batch = p->batch;
@@ -492,6 +494,7 @@ static tdse_status create_batched_twin(tdse_plan p, hipStream_t s) {
     q->lmax = p->lmax;
     q->n = p->n;
     q->batch = 1;
+    q->gauge = p->gauge;
     q->device = p->device;
     double *rowmajor = nullptr;
     if (p->lmax > 0) {
@@ -530,22 +533,30 @@ const char *tdse_last_error(void) { return g_last_error.c_str(); }
 
 tdse_status tdse_create(tdse_plan *out, const double *energies, const double *dipole,
                         int32_t lmax, int32_t n, int32_t batch, void *stream) {
+    return tdse_create_gauge(out, energies, dipole, TDSE_LENGTH, lmax, n, batch, stream);
+}
+
+tdse_status tdse_create_gauge(tdse_plan *out, const double *energies, const double *coupling, tdse_gauge gauge,
+                              int32_t lmax, int32_t n, int32_t batch, void *stream) {
     clear_error();
     std::string why;
-    tdse_status st = validate_create(out, energies, dipole, lmax, n, batch, &why);
+    tdse_status st = validate_create(out, energies, coupling, lmax, n, batch, &why);
     if (st != TDSE_OK) return fail(st, why);
-    return create_plan(out, energies, dipole, lmax, n, batch, reinterpret_cast<hipStream_t>(stream), nullptr);
+    if (gauge != TDSE_LENGTH && gauge != TDSE_VELOCITY) return fail(TDSE_E_INVAL, "unknown gauge");
+    return create_plan(out, energies, coupling, (int32_t)gauge, lmax, n, batch,
+                       reinterpret_cast<hipStream_t>(stream), nullptr);
 }
 
 }  // extern "C"
 
 namespace tdse {
 
-tdse_status create_plan(tdse_plan *out, const double *energies, const double *dipole, int32_t lmax,
+tdse_status create_plan(tdse_plan *out, const double *energies, const double *dipole, int32_t gauge, int32_t lmax,
                         int32_t n, int32_t batch, hipStream_t s, const TileChoice *force) {
     tdse_status st;
     tdse_plan p = new (std::nothrow) tdse_plan_s();
     if (!p) return fail(TDSE_E_NOMEM, "host allocation failed");
+    p->gauge = gauge;
     p->lmax = lmax;
     p->n = n;
     p->batch = batch;

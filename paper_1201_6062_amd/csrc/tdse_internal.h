@@ -91,6 +91,7 @@ struct VecBuffers {
     double2 *colp[2];      // [parity][lmax][T(out seg j)][T(contrib i)][VEC_TILE_MAX]
     CallDesc *desc;
     int32_t lmax, n, ld, T;
+    int32_t gauge;         // TDSE_LENGTH or TDSE_VELOCITY (how the two block uses combine)
     int32_t seg[17];       // segment starts (Sec. 4.1 split of n over T), seg[T] = n
 };
 
@@ -121,7 +122,7 @@ struct GroupInst {
 };
 // Single-workgroup propagation of small problems ((lmax+1) n <= 256, n <= 64).
 bool small_eligible(int lmax, int n);
-hipError_t small_propagate(const double *en, const double *dip, int lmax, int n, int method, int order, double dt,
+hipError_t small_propagate(const double *en, const double *dip, int gauge, int lmax, int n, int method, int order, double dt,
                            int64_t nsteps, const double *field, const double *c0, double *cT, double *ckpt,
                            int64_t ckpt_every, hipStream_t s);
 
@@ -158,6 +159,7 @@ struct BatBuffers {
     double *c, *acc;       // [(lmax+1)][np][ldu]
     const double *field;   // caller [batch][nsteps][S]
     int32_t lmax, n, np, ldu, batch, tm, tn, kc;
+    int32_t gauge;         // TDSE_LENGTH or TDSE_VELOCITY (d holds -Q_l in the velocity gauge)
 };
 
 struct BatLaunch {
@@ -201,7 +203,7 @@ struct TileChoice {
 // arguments unchanged when there is no entry for (lmax, n, batch).
 void tune_lookup(int lmax, int n, int batch, TileChoice *tc);
 // Plan creation with an optional forced tile choice (used by the tuner).
-tdse_status create_plan(tdse_plan *out, const double *energies, const double *dipole, int32_t lmax,
+tdse_status create_plan(tdse_plan *out, const double *energies, const double *dipole, int32_t gauge, int32_t lmax,
                         int32_t n, int32_t batch, hipStream_t s, const TileChoice *force);
 
 }  // namespace tdse
@@ -227,6 +229,7 @@ struct tdse_group_s {
 
 struct tdse_plan_s {
     int32_t lmax = 0, n = 0, batch = 1;
+    int32_t gauge = 0;           // tdse_gauge of the coupling blocks
     int device = 0;
     // device copies of the Hamiltonian
     double *en = nullptr;

@@ -131,7 +131,7 @@ static tdse_status time_choice(int lmax, int n, int batch, const TileChoice &tc,
                                const double *ddip, const double *dfield, double *dc0, double *dcT,
                                int64_t nsteps, hipStream_t s, double *us_per_step) {
     tdse_plan p = nullptr;
-    tdse_status st = create_plan(&p, den, ddip, lmax, n, batch, s, &tc);
+    tdse_status st = create_plan(&p, den, ddip, TDSE_LENGTH, lmax, n, batch, s, &tc);
     if (st != TDSE_OK) return st;
     hipEvent_t e0, e1;
     TDSE_HIP(hipEventCreate(&e0));

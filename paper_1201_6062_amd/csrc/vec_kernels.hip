@@ -25,6 +25,15 @@ namespace tdse {
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 
+// Coupling product of a state entry from its row-use part r (the block above,
+// D_l u_{l+1}) and column-use part s (the block below, D_{l-1}^T u_{l-1}):
+// length gauge r + s; velocity gauge, with the blocks holding Q of
+// P = -i Q: -i (r - s).
+__device__ __forceinline__ double2 couple(int gauge, double2 r, double2 s) {
+    if (gauge) return make_double2(r.y - s.y, -(r.x - s.x));
+    return make_double2(r.x + s.x, r.y + s.y);
+}
+
 // Streaming (non-temporal) access for partials and state, so that they do not
 // displace dipole lines from the caches.
 typedef double dv2_t __attribute__((ext_vector_type(2)));
@@ -358,7 +367,7 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
         if (e < len) {
             double2 c = c_in, acc = acc_in;
             u = u_in;
-            apply_completion(L.comp, dt, F, E0, cadd(zpart, lds.zc[pe]), c, acc, u);
+            apply_completion(L.comp, dt, F, E0, couple(b.gauge, zpart, lds.zc[pe]), c, acc, u);
             const bool owner = isB ? (l == b.lmax - 1 && i == 0) : (j == 0);
             if (owner) store_state(b, L, ct, gi, c, acc, u);
         }
@@ -463,8 +472,8 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_group_combine_kernel(const G
     const double F = (step >= 0 && step < gi.nsteps) ? gi.field[step * 3 + L.comp.slot] : 0.0;
     const size_t g = (size_t)gs.m * b.n + split_start(b.n, b.T, gs.q) + e;
     const int par = L.parity;
-    const double2 z = cadd(sum_partials<8>(b, b.T, par, true, gs.m, gs.q, e),
-                           sum_partials<8>(b, b.T, par, false, gs.m, gs.q, e));
+    const double2 z = couple(b.gauge, sum_partials<8>(b, b.T, par, true, gs.m, gs.q, e),
+                             sum_partials<8>(b, b.T, par, false, gs.m, gs.q, e));
     double2 c = ld_nt(st_ptr(b, par, 0) + g), acc = ld_nt(st_ptr(b, par, 1) + g), u = ld_nt(st_ptr(b, par, 2) + g);
     apply_completion(L.comp, desc->dt, F, b.en[g], z, c, acc, u);
     store_state(b, L, CkptTarget{nullptr}, g, c, acc, u);
@@ -503,7 +512,7 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_combine_kernel(VecBuffers b,
     const size_t gi = (size_t)m * b.n + s0 + e;
     double2 z = make_double2(0.0, 0.0);
     if (b.lmax > 0)
-        z = cadd(sum_partials<TP>(b, T, par, true, m, q, e), sum_partials<TP>(b, T, par, false, m, q, e));
+        z = couple(b.gauge, sum_partials<TP>(b, T, par, true, m, q, e), sum_partials<TP>(b, T, par, false, m, q, e));
     double2 c = ld_nt(st_ptr(b, par, 0) + gi), acc = ld_nt(st_ptr(b, par, 1) + gi), u = ld_nt(st_ptr(b, par, 2) + gi);
     const double E0 = b.en[gi];
     if (L.comp.kind == CK_HMUL) {
