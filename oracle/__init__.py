@@ -223,3 +223,68 @@ def yield_seed(energies, c):
     """lambda_T = dY/dRe c + i dY/dIm c = 2 [E > 0] c."""
     m = np.repeat(positive_mask(energies), 2).astype(np.float64)
     return 2.0 * np.atleast_2d(c) * m[None, :]
+
+
+# ---- short-iterative Lanczos propagator (Krylov; named in Sec. 5.2 as the
+# propagator to build on an optimised product)
+
+LANCZOS_BREAKDOWN = 1e-13
+
+
+def _as_complex(v):
+    v = np.asarray(v, dtype=np.float64)
+    return v[0::2] + 1j * v[1::2]
+
+
+def _as_interleaved(z):
+    out = np.empty(2 * z.size)
+    out[0::2] = z.real
+    out[1::2] = z.imag
+    return out
+
+
+def lanczos(energies, dipole, m, dt, field, c0, n=None, gauge="length"):
+    """Krylov propagation: with H frozen over step k at the sample field[b, k],
+    build the Lanczos basis v_1 = c / |c|, v_{j+1} beta_j = H v_j - alpha_j v_j
+    - beta_{j-1} v_{j-1} (alpha_j = <v_j, H v_j>, beta_j = |...|; plain
+    three-term recurrence, no reorthogonalisation) for j = 1..m, and set
+    c' = |c| V exp(-i dt T) e_1 with T the m x m tridiagonal of the alphas and
+    betas, exponentiated through its eigendecomposition. The basis ends early
+    (breakdown) once beta_j <= 1e-13 (|alpha_j| + beta_{j-1}).
+    field [B, nsteps] or [B, nsteps, 1]; c0 [B, 2n]; returns c(T) [B, 2n]."""
+    en, dip, lmax, n = _dims_n(energies, dipole, n)
+    c = np.array(c0, dtype=np.float64, copy=True)
+    if c.ndim == 1:
+        c = c[None]
+    f = np.asarray(field, dtype=np.float64)
+    if f.ndim == 3:
+        f = f[..., 0]
+    if f.ndim == 1:
+        f = f[None]
+    for b in range(c.shape[0]):
+        for k in range(f.shape[1]):
+            z = _as_complex(c[b])
+            beta0 = np.linalg.norm(z)
+            if beta0 == 0.0:
+                continue
+            vs, alphas, betas = [z / beta0], [], []
+            for j in range(m):
+                w = _as_complex(hmul(en, dip, f[b, k], _as_interleaved(vs[j]), n=n, gauge=gauge))
+                a = float(np.real(np.vdot(vs[j], w)))
+                w = w - a * vs[j]
+                if j > 0:
+                    w = w - betas[j - 1] * vs[j - 1]
+                alphas.append(a)
+                if j == m - 1:
+                    break
+                bj = float(np.linalg.norm(w))
+                if bj <= LANCZOS_BREAKDOWN * (abs(a) + (betas[j - 1] if j > 0 else 0.0)):
+                    break
+                betas.append(bj)
+                vs.append(w / bj)
+            kdim = len(alphas)
+            t = np.diag(alphas) + np.diag(betas[:kdim - 1], 1) + np.diag(betas[:kdim - 1], -1)
+            lam, q = np.linalg.eigh(t)
+            y = q @ (np.exp(-1j * dt * lam) * q[0, :])
+            c[b] = _as_interleaved(beta0 * sum(y[j] * vs[j] for j in range(kdim)))
+    return c

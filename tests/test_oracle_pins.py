@@ -641,3 +641,61 @@ def test_workload_step_counts():
     g = wl.expand_piecewise(f[None], 16)
     assert g.shape == (1, 32768, 3)
     assert np.allclose(wl.collapse_piecewise(np.ones_like(g), 16), 48.0)
+
+
+# ---- short-iterative Lanczos (Krylov) propagator
+
+def _expm_steps(h, fk, dt, c0, gauge="length", q=None):
+    v = cplx(c0)
+    for f in fk:
+        hk = dense_h_velocity(h.energies, q, f) if gauge == "velocity" else dense_h(h.energies, h.dipole, f)
+        lam, w = np.linalg.eigh(hk)
+        v = (w * np.exp(-1j * lam * dt)[None, :]) @ (w.conj().T @ v)
+    return v
+
+
+@pytest.mark.parametrize("gauge", ["length", "velocity"])
+def test_lanczos_full_krylov_space_is_exact(oracle_mod, gauge):
+    """m = dimension of the space: the Krylov step is exp(-i dt H_k) exactly."""
+    h = wl.hamiltonian(1, 3, 2)
+    q = wl.velocity_coupling(h.energies, h.dipole)
+    rng = np.random.default_rng(3)
+    c0 = wl.random_state(rng, h.nstates)[0]
+    dt, fk = 0.3, stepwise_fields(12, 0.3) + 0.2
+    blocks = q if gauge == "velocity" else h.dipole
+    got = oracle_mod.lanczos(h.energies, blocks, h.nstates, dt, fk[None], c0, gauge=gauge)[0]
+    ref = _expm_steps(h, fk, dt, c0, gauge, q)
+    np.testing.assert_allclose(cplx(got), ref, rtol=0, atol=1e-12)
+
+
+def test_lanczos_eigenstate_breakdown_gives_exact_phase(oracle_mod):
+    """Field-free and c an eigenstate: the basis breaks down after one vector
+    and the step is the exact phase exp(-i E dt)."""
+    h = wl.hamiltonian(2, 12, 1)
+    c0 = np.zeros(2 * h.nstates)
+    c0[2 * 13] = 1.0                     # state 13: block 1, a bound level
+    dt, nst = 0.7, 25
+    got = oracle_mod.lanczos(h.energies, h.dipole, 10, dt, np.zeros((1, nst)), c0)[0]
+    e = h.energies[13]
+    assert abs(cplx(got)[13] - np.exp(-1j * e * dt * nst)) <= 1e-13
+    assert np.abs(np.delete(cplx(got), 13)).max() == 0.0
+
+
+def test_lanczos_converges_rapidly_with_krylov_dimension(oracle_mod):
+    h = wl.hamiltonian(2, 20, 4)
+    rng = np.random.default_rng(5)
+    c0 = wl.random_state(rng, h.nstates)[0]
+    dt, fk = 0.2, stepwise_fields(10, 0.2) + 0.3
+    ref = _expm_steps(h, fk, dt, c0)
+    errs = [np.abs(cplx(oracle_mod.lanczos(h.energies, h.dipole, m, dt, fk[None], c0)[0]) - ref).max()
+            for m in (4, 8, 12)]
+    assert errs[1] < 1e-3 * errs[0] and errs[2] < 1e-3 * errs[1] and errs[2] < 1e-11, errs
+
+
+def test_lanczos_preserves_the_norm(oracle_mod):
+    h = wl.hamiltonian(3, 15, 6)
+    rng = np.random.default_rng(7)
+    c0 = wl.random_state(rng, h.nstates)[0]
+    fk = stepwise_fields(60, 0.1) + 0.1
+    got = oracle_mod.lanczos(h.energies, h.dipole, 8, 0.1, fk[None], c0)[0]
+    assert abs(np.linalg.norm(got) - 1.0) <= 1e-12
