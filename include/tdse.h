@@ -70,7 +70,8 @@ typedef enum {
 
 typedef enum {
     TDSE_RK4 = 0,            /* classic 4th-order Runge-Kutta, 4 products per step */
-    TDSE_TAYLOR = 1          /* truncated Taylor series of order p, p products per step */
+    TDSE_TAYLOR = 1,         /* truncated Taylor series of order p, p products per step */
+    TDSE_LANCZOS = 2         /* short-iterative Lanczos, Krylov dimension m (taylor_order), m products per step */
 } tdse_method;
 
 typedef enum {
@@ -129,15 +130,22 @@ tdse_status tdse_hmul(tdse_plan plan, const double *fields, const double *u, dou
                       void *stream);
 
 /*
- * Propagate c0 over nsteps steps of size dt with RK4 (taylor_order ignored)
- * or the Taylor series of order taylor_order (1 <= order <= 32), writing c(T)
- * to cT. field: [batch][nsteps][S] device; c0, cT: [batch][2*nstates]
- * device; cT may alias c0. nsteps == 0 copies c0 to cT.
+ * Propagate c0 over nsteps steps of size dt with RK4 (taylor_order ignored),
+ * the Taylor series of order taylor_order (1 <= order <= 32), or the
+ * short-iterative Lanczos propagator with Krylov dimension taylor_order
+ * (1 <= m <= 64; the Krylov method named in Sec. 5.2: per step with H frozen
+ * at the sample, c' = |c| V exp(-i dt T) e_1 over the Lanczos basis V of H
+ * from c and its tridiagonal T; no reorthogonalisation; a vanishing beta_j
+ * ends the basis early), writing c(T) to cT. field: [batch][nsteps][S]
+ * device (S = 1 for Taylor and Lanczos); c0, cT: [batch][2*nstates] device;
+ * cT may alias c0. nsteps == 0 copies c0 to cT.
  * ckpt: NULL, or device [batch][nsteps/ckpt_every + 1][2*nstates] receiving
  * c(k*ckpt_every*dt) for k = 0..nsteps/ckpt_every (ckpt_every >= 1).
  * The result is the discrete RK4 / Taylor map applied to the given samples.
  * Errors: TDSE_E_INVAL (null/misaligned/host pointers, dt <= 0 or not finite,
  * nsteps < 0, order out of range, ckpt_every < 1 with ckpt != NULL).
+ * The Lanczos workspace ((m+1) state vectors per pulse) is allocated on
+ * first use and kept by the plan (TDSE_E_NOMEM if it cannot be).
  */
 tdse_status tdse_propagate(tdse_plan plan, tdse_method method, int32_t taylor_order, double dt,
                            int64_t nsteps, const double *field, const double *c0, double *cT,

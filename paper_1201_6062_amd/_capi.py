@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtdse.so")
 
 TDSE_OK, TDSE_E_INVAL, TDSE_E_NOMEM, TDSE_E_HIP, TDSE_E_UNSUPPORTED, TDSE_E_UNSTABLE = range(6)
-TDSE_RK4, TDSE_TAYLOR = 0, 1
+TDSE_RK4, TDSE_TAYLOR, TDSE_LANCZOS = 0, 1, 2
 TDSE_LENGTH, TDSE_VELOCITY = 0, 1
 STATUS_NAMES = {0: "TDSE_OK", 1: "TDSE_E_INVAL", 2: "TDSE_E_NOMEM", 3: "TDSE_E_HIP",
                 4: "TDSE_E_UNSUPPORTED", 5: "TDSE_E_UNSTABLE"}

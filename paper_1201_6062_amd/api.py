@@ -12,9 +12,9 @@ import numpy as np
 import torch
 
 from . import _capi
-from ._capi import TDSE_LENGTH, TDSE_RK4, TDSE_TAYLOR, TDSE_VELOCITY, TdseError, check
+from ._capi import TDSE_LANCZOS, TDSE_LENGTH, TDSE_RK4, TDSE_TAYLOR, TDSE_VELOCITY, TdseError, check
 
-METHODS = {"rk4": TDSE_RK4, "taylor": TDSE_TAYLOR}
+METHODS = {"rk4": TDSE_RK4, "taylor": TDSE_TAYLOR, "lanczos": TDSE_LANCZOS}
 GAUGES = {"length": TDSE_LENGTH, "velocity": TDSE_VELOCITY}
 
 

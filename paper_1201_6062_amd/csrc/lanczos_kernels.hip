@@ -1,0 +1,175 @@
+// Short-iterative Lanczos (Krylov) propagation, the propagator the paper's
+// optimisation notes (Sec. 5.2) name to build on a fast product. Per step,
+// with H frozen at the step's field sample:
+//   v_1 = c / |c|,  v_{j+1} beta_j = H v_j - alpha_j v_j - beta_{j-1} v_{j-1},
+//   alpha_j = Re <v_j, H v_j>,  c' = |c| V exp(-i dt T) e_1,
+// T the tridiagonal of the alphas and betas. The products H v_j are the
+// plan's own product kernels; these kernels do the per-pulse reductions,
+// the recurrence, the small exponential and the recombination. Vectors are in
+// the caller layout [pulse][2 n] (interleaved complex); every reduction runs
+// in one workgroup per pulse, in a fixed order.
+#include "tdse_internal.h"
+
+namespace tdse {
+
+constexpr int LZ_THREADS = 1024;
+
+// Sum of v over the workgroup (fixed tree order). red: LZ_THREADS doubles of LDS.
+__device__ __forceinline__ double lz_block_sum(double v, double *red) {
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int h = LZ_THREADS / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    const double s = red[0];
+    __syncthreads();
+    return s;
+}
+
+// beta0 = |c|, v_1 = c / beta0 (zero when c == 0). One workgroup per pulse.
+__global__ __launch_bounds__(LZ_THREADS) void lz_begin_kernel(const double *c, double *v1, double *beta0,
+                                                              int64_t len) {
+    __shared__ double red[LZ_THREADS];
+    const int b = blockIdx.x;
+    const double *cb = c + (size_t)b * len;
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < len; e += LZ_THREADS) s = fma(cb[e], cb[e], s);
+    const double nrm = sqrt(lz_block_sum(s, red));
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    double *vb = v1 + (size_t)b * len;
+    for (int64_t e = threadIdx.x; e < len; e += LZ_THREADS) vb[e] = cb[e] * inv;
+    if (threadIdx.x == 0) beta0[b] = nrm;
+}
+
+// One Lanczos recurrence step j (0-based) for every pulse: w = H v_j on
+// entry; alpha_j = Re <v_j, w>; w -= alpha_j v_j + beta_{j-1} v_{j-1};
+// unless last: beta_j = |w| and v_{j+1} = w / beta_j. A breakdown (beta_j <=
+// 1e-13 (|alpha_j| + beta_{j-1})) sets beta_j = 0 and v_{j+1} = 0, so the
+// remaining steps add nothing.
+__global__ __launch_bounds__(LZ_THREADS) void lz_orth_kernel(const double *vj, const double *vjm1, double *w,
+                                                             double *vnext, double *alpha, double *beta, int j,
+                                                             int m, int last, int64_t len) {
+    __shared__ double red[LZ_THREADS];
+    const int b = blockIdx.x;
+    const size_t off = (size_t)b * len;
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < len; e += LZ_THREADS) s = fma(vj[off + e], w[off + e], s);
+    const double a = lz_block_sum(s, red);
+    const double bprev = j > 0 ? beta[(size_t)b * m + j - 1] : 0.0;
+    double s2 = 0.0;
+    for (int64_t e = threadIdx.x; e < len; e += LZ_THREADS) {
+        double x = w[off + e] - a * vj[off + e];
+        if (j > 0) x -= bprev * vjm1[off + e];
+        w[off + e] = x;
+        s2 = fma(x, x, s2);
+    }
+    if (threadIdx.x == 0) alpha[(size_t)b * m + j] = a;
+    if (last) return;
+    double bj = sqrt(lz_block_sum(s2, red));
+    if (bj <= 1e-13 * (fabs(a) + bprev)) bj = 0.0;
+    const double inv = bj > 0.0 ? 1.0 / bj : 0.0;
+    for (int64_t e = threadIdx.x; e < len; e += LZ_THREADS) vnext[off + e] = w[off + e] * inv;
+    if (threadIdx.x == 0) beta[(size_t)b * m + j] = bj;
+}
+
+// y = beta0 exp(-i dt T) e_1 for every pulse, one wave per pulse (lane j holds
+// component j, m <= 64). The exponential is the Taylor series of 16 terms
+// over s sub-steps, s chosen so that dt |T| / s <= 1/2 (|T| bounded by its
+// largest Gershgorin row sum): truncation below 1e-17 per sub-step.
+__global__ __launch_bounds__(64) void lz_expm_kernel(const double *alpha, const double *beta, const double *beta0,
+                                                     double dt, int m, double2 *y) {
+    const int b = blockIdx.x, j = threadIdx.x;
+    const bool in = j < m;
+    const double a = in ? alpha[(size_t)b * m + j] : 0.0;
+    const double bu = (in && j + 1 < m) ? beta[(size_t)b * m + j] : 0.0;       // T[j][j+1]
+    const double bl = (in && j > 0) ? beta[(size_t)b * m + j - 1] : 0.0;       // T[j][j-1]
+    double g = fabs(a) + bu + bl;
+    for (int o = 32; o > 0; o >>= 1) g = fmax(g, __shfl_xor(g, o));
+    const int sub = (int)fmax(1.0, ceil(2.0 * dt * g));
+    const double h = dt / sub;
+    double yr = (j == 0) ? 1.0 : 0.0, yi = 0.0;
+    for (int st = 0; st < sub; ++st) {
+        double tr = yr, ti = yi, sr = yr, si = yi;
+        for (int k = 1; k <= 16; ++k) {
+            // (T t)_j = a t_j + bl t_{j-1} + bu t_{j+1}
+            const double pr = __shfl_up(tr, 1), pi = __shfl_up(ti, 1);
+            const double nr = __shfl_down(tr, 1), ni = __shfl_down(ti, 1);
+            const double qr = fma(bu, nr, fma(bl, j > 0 ? pr : 0.0, a * tr));
+            const double qi = fma(bu, ni, fma(bl, j > 0 ? pi : 0.0, a * ti));
+            // t <- (-i h / k) (T t): (-i c)(x + iy) = c y - i c x
+            const double c = h / k;
+            tr = in ? c * qi : 0.0;
+            ti = in ? -c * qr : 0.0;
+            sr += tr;
+            si += ti;
+        }
+        yr = sr;
+        yi = si;
+    }
+    if (in) {
+        const double nb = beta0[b];
+        y[(size_t)b * m + j] = make_double2(nb * yr, nb * yi);
+    }
+}
+
+// c = sum_j y_j v_j (complex y_j, complex vectors), and the checkpoint row if
+// one is due. Grid-stride over the complex entries of all pulses.
+__global__ void lz_combine_kernel(const double *V, size_t vstride, const double2 *y, int m, int batch,
+                                  int64_t ncplx, double *c, double *ckpt, int64_t ckpt_rows, int64_t ckpt_row) {
+    const int64_t total = (int64_t)batch * ncplx;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(g / ncplx);
+        const int64_t e = g - (int64_t)b * ncplx;
+        double sr = 0.0, si = 0.0;
+        for (int j = 0; j < m; ++j) {
+            const double2 yj = y[(size_t)b * m + j];
+            const double2 v = reinterpret_cast<const double2 *>(V + (size_t)j * vstride)[g];
+            sr = fma(yj.x, v.x, fma(-yj.y, v.y, sr));
+            si = fma(yj.x, v.y, fma(yj.y, v.x, si));
+        }
+        reinterpret_cast<double2 *>(c)[g] = make_double2(sr, si);
+        if (ckpt)
+            reinterpret_cast<double2 *>(ckpt)[((size_t)b * ckpt_rows + ckpt_row) * ncplx + e] = make_double2(sr, si);
+    }
+}
+
+__global__ void lz_ckpt0_kernel(const double *c0, double *ckpt, int batch, int64_t len, int64_t rows) {
+    const int64_t total = (int64_t)batch * len;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = g / len, e = g - b * len;
+        ckpt[(size_t)b * rows * len + e] = c0[g];
+    }
+}
+
+hipError_t lz_begin(const double *c, double *v1, double *beta0, int batch, int64_t len, hipStream_t s) {
+    hipLaunchKernelGGL(lz_begin_kernel, dim3(batch), dim3(LZ_THREADS), 0, s, c, v1, beta0, len);
+    return hipGetLastError();
+}
+hipError_t lz_orth(const double *vj, const double *vjm1, double *w, double *vnext, double *alpha, double *beta,
+                   int j, int m, int last, int batch, int64_t len, hipStream_t s) {
+    hipLaunchKernelGGL(lz_orth_kernel, dim3(batch), dim3(LZ_THREADS), 0, s, vj, vjm1, w, vnext, alpha, beta, j, m,
+                       last, len);
+    return hipGetLastError();
+}
+hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0, double dt, int m, int batch,
+                   double *y, hipStream_t s) {
+    hipLaunchKernelGGL(lz_expm_kernel, dim3(batch), dim3(64), 0, s, alpha, beta, beta0, dt, m,
+                       reinterpret_cast<double2 *>(y));
+    return hipGetLastError();
+}
+hipError_t lz_combine(const double *V, size_t vstride, const double *y, int m, int batch, int64_t ncplx, double *c,
+                      double *ckpt, int64_t ckpt_rows, int64_t ckpt_row, hipStream_t s) {
+    hipLaunchKernelGGL(lz_combine_kernel, dim3(1024), dim3(256), 0, s, V, vstride,
+                       reinterpret_cast<const double2 *>(y), m, batch, ncplx, c, ckpt, ckpt_rows, ckpt_row);
+    return hipGetLastError();
+}
+hipError_t lz_ckpt0(const double *c0, double *ckpt, int batch, int64_t len, int64_t rows, hipStream_t s) {
+    hipLaunchKernelGGL(lz_ckpt0_kernel, dim3(256), dim3(256), 0, s, c0, ckpt, batch, len, rows);
+    return hipGetLastError();
+}
+
+}  // namespace tdse

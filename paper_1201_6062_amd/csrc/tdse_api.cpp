@@ -352,6 +352,98 @@ static tdse_status bat_hmul(tdse_plan p, const double *fields, const double *u, 
 }
 
 // ---------------------------------------------------------------------------
+// Short-iterative Lanczos propagation (any plan): the products H v_j run on
+// the plan's own kernels, the recurrence and the small exponential in
+// lanczos_kernels.hip.
+
+// y = H(field[., k]) u for the plan's pulses (caller layout). Single-vector
+// plans read the sample from the chunk staged at `base` by chunk_begin.
+static hipError_t lz_product(tdse_plan p, const double *field, int64_t nsteps, int64_t k, int64_t base,
+                             const double *u, double *y, hipStream_t s) {
+    hipError_t e;
+    if (p->batch > 1) {
+        BatBuffers b = p->bb;
+        b.field = field;
+        if ((e = bat_pack(b, u, 0, s)) != hipSuccess) return e;
+        BatLaunch L{};
+        L.kind = CK_HMUL;
+        L.parity = 0;
+        L.dt = 1.0;
+        L.step = k;
+        L.nsteps = nsteps;
+        L.slots = 1;
+        L.out = y;
+        return bat_launch_stage(b, L, s);
+    }
+    if ((e = vec_launch_start(p->vb, 0, u, TDSE_RK4, s)) != hipSuccess) return e;
+    VecLaunch L{};
+    L.comp = {CK_RK4_END, 0, -1, 0, 1.0 / 6.0, 0.0};  // no-op completion: forms the input u
+    L.parity = 0;
+    L.slots = 1;
+    e = p->lmax > 0 ? vec_launch_tiles(p->vb, L, s) : vec_launch_combine(p->vb, L, s);
+    if (e != hipSuccess) return e;
+    VecLaunch H{};
+    H.comp = {CK_HMUL, 0, 0, 0, 0.0, 0.0};
+    H.parity = 1;
+    H.slots = 1;
+    H.off = (int32_t)(k - base);
+    H.out = y;
+    return vec_launch_combine(p->vb, H, s);
+}
+
+static tdse_status lz_propagate(tdse_plan p, int m, double dt, int64_t nsteps, const double *field,
+                                const double *c0, double *cT, double *ckpt, int32_t K, hipStream_t s) {
+    const int B = p->batch;
+    const int64_t ncplx = (int64_t)(p->lmax + 1) * p->n, len = 2 * ncplx;
+    const size_t vstride = (size_t)B * len;
+    const size_t need = ((size_t)(m + 1) * vstride + (size_t)B * (4 * m + 1)) * sizeof(double);
+    if (need > p->lz_bytes) {
+        if (p->lz_mem) (void)hipFree(p->lz_mem);
+        p->lz_mem = nullptr;
+        p->lz_bytes = 0;
+        if (hipMalloc(&p->lz_mem, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(TDSE_E_NOMEM, "hipMalloc of the Lanczos workspace failed");
+        }
+        p->lz_bytes = need;
+    }
+    double *V = p->lz_mem;                       // v_1 .. v_m, then w
+    double *W = V + (size_t)m * vstride;
+    double *alpha = W + vstride, *beta = alpha + (size_t)B * m, *beta0 = beta + (size_t)B * m;
+    double *y = beta0 + B;                       // [B][m] complex
+    if (cT != c0) TDSE_HIP(hipMemcpyAsync(cT, c0, vstride * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const int64_t rows = ckpt ? nsteps / K + 1 : 0;
+    if (ckpt) TDSE_HIP(lz_ckpt0(c0, ckpt, B, len, rows, s));
+    if (B == 1) {
+        CallDesc d{};
+        d.nsteps = nsteps;
+        d.field = field;
+        d.ckpt_every = 1;
+        d.dt = dt;
+        d.slots = 1;
+        TDSE_HIP(set_desc(p->vb.desc, d, s));
+    }
+    int64_t base = 0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (B == 1 && k % CHUNK_STEPS == 0) {
+            base = k;
+            TDSE_HIP(chunk_begin(p->vb.desc, base, s));
+        }
+        TDSE_HIP(lz_begin(cT, V, beta0, B, len, s));
+        for (int j = 0; j < m; ++j) {
+            const double *vj = V + (size_t)j * vstride;
+            TDSE_HIP(lz_product(p, field, nsteps, k, base, vj, W, s));
+            TDSE_HIP(lz_orth(vj, j > 0 ? vj - vstride : nullptr, W, j + 1 < m ? V + (size_t)(j + 1) * vstride : nullptr,
+                             alpha, beta, j, m, j + 1 == m, B, len, s));
+        }
+        TDSE_HIP(lz_expm(alpha, beta, beta0, dt, m, B, y, s));
+        const bool row = ckpt && (k + 1) % K == 0;
+        TDSE_HIP(lz_combine(V, vstride, y, m, B, ncplx, cT, row ? ckpt : nullptr, rows, row ? (k + 1) / K : 0, s));
+    }
+    return TDSE_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Discrete adjoint of the batched RK4 / Taylor map (reverse sweep over
 // checkpointed segments; the forward states inside a segment are recomputed
 // from its checkpoint and the inputs of every product of a step are kept:
@@ -639,6 +731,7 @@ tdse_status tdse_destroy(tdse_plan p) {
     for (hipGraph_t g : p->graph_defs) (void)hipGraphDestroy(g);
     if (p->scratch) (void)hipFree(p->scratch);
     if (p->bat_mem) (void)hipFree(p->bat_mem);
+    if (p->lz_mem) (void)hipFree(p->lz_mem);
     if (p->adj_mem) (void)hipFree(p->adj_mem);
     if (p->adj_plan) tdse_destroy(p->adj_plan);
     if (p->dip) (void)hipFree(p->dip);
@@ -701,6 +794,7 @@ tdse_status tdse_propagate(tdse_plan p, tdse_method method, int32_t order, doubl
     if ((st = check_dev(c0, "c0")) || (st = check_dev(cT, "cT"))) return st;
     if (ckpt && (st = check_dev(ckpt, "ckpt"))) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (method == TDSE_LANCZOS) return lz_propagate(p, order, dt, nsteps, field, c0, cT, ckpt, ckpt_every, s);
     if (p->batch > 1)
         return bat_propagate(p, method, method == TDSE_RK4 ? 4 : order, dt, nsteps, field, c0, cT, ckpt,
                              ckpt_every, s);
@@ -717,6 +811,7 @@ tdse_status tdse_adjoint(tdse_plan p, tdse_method method, int32_t order, double 
     tdse_status st = validate_propagate(p != nullptr, (int)method, method == TDSE_TAYLOR ? order : 4, dt, nsteps,
                                         true, ckpt_every, &why);
     if (st != TDSE_OK) return fail(st, why);
+    if (method == TDSE_LANCZOS) return fail(TDSE_E_UNSUPPORTED, "no adjoint for the Lanczos propagator");
     if (nsteps > 0 && (st = check_dev(field, "field"))) return st;
     if ((st = check_dev(c0, "c0")) || (st = check_dev(lambdaT, "lambdaT"))) return st;
     if (nsteps > 0 && (st = check_dev(grad_field, "grad_field"))) return st;

@@ -192,6 +192,17 @@ hipError_t bat_ckpt0(const BatBuffers &b, const double *c0, double *ckpt, int ro
 hipError_t bat_launch_stage(const BatBuffers &b, const BatLaunch &l, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// Short-iterative Lanczos (caller-layout vectors [batch][len], len = 2 nstates).
+hipError_t lz_begin(const double *c, double *v1, double *beta0, int batch, int64_t len, hipStream_t s);
+hipError_t lz_orth(const double *vj, const double *vjm1, double *w, double *vnext, double *alpha, double *beta,
+                   int j, int m, int last, int batch, int64_t len, hipStream_t s);
+hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0, double dt, int m, int batch,
+                   double *y, hipStream_t s);
+hipError_t lz_combine(const double *V, size_t vstride, const double *y, int m, int batch, int64_t ncplx, double *c,
+                      double *ckpt, int64_t ckpt_rows, int64_t ckpt_row, hipStream_t s);
+hipError_t lz_ckpt0(const double *c0, double *ckpt, int batch, int64_t len, int64_t rows, hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Tile choices (autotuner cache).
 struct TileChoice {
     int32_t T;        // single-vector path: tiles per block dimension (0 = default)
@@ -249,6 +260,9 @@ struct tdse_plan_s {
     // segment store of stage inputs, gradient partials, internal checkpoints
     double *adj_mem = nullptr;
     size_t adj_bytes = 0;
+    // Lanczos workspace (allocated on first use): basis, product, coefficients
+    double *lz_mem = nullptr;
+    size_t lz_bytes = 0;
     tdse_plan adj_plan = nullptr;   // batched twin of a batch-1 plan, for the adjoint
     // captured chunk graphs keyed by (method, order, chunk steps, parity)
     std::map<std::string, hipGraphExec_t> graphs;

@@ -12,6 +12,7 @@
 namespace tdse {
 
 constexpr int32_t TAYLOR_MAX_ORDER = 32;
+constexpr int32_t LANCZOS_MAX_DIM = 64;
 constexpr int64_t MAX_STATES = (int64_t)1 << 40;
 
 inline tdse_status validate_create(const void *out, const void *energies, const void *dipole,
@@ -33,9 +34,16 @@ inline tdse_status validate_propagate(bool have_plan, int method, int32_t order,
                                       int64_t nsteps, bool have_ckpt, int32_t ckpt_every,
                                       std::string *why) {
     if (!have_plan) { *why = "plan is NULL"; return TDSE_E_INVAL; }
-    if (method != TDSE_RK4 && method != TDSE_TAYLOR) { *why = "unknown method"; return TDSE_E_INVAL; }
+    if (method != TDSE_RK4 && method != TDSE_TAYLOR && method != TDSE_LANCZOS) {
+        *why = "unknown method";
+        return TDSE_E_INVAL;
+    }
     if (method == TDSE_TAYLOR && (order < 1 || order > TAYLOR_MAX_ORDER)) {
         *why = "taylor_order must be in [1, 32]";
+        return TDSE_E_INVAL;
+    }
+    if (method == TDSE_LANCZOS && (order < 1 || order > LANCZOS_MAX_DIM)) {
+        *why = "the Krylov dimension (taylor_order) must be in [1, 64]";
         return TDSE_E_INVAL;
     }
     if (!(dt > 0.0) || !isfinite(dt)) { *why = "dt must be finite and > 0"; return TDSE_E_INVAL; }
