@@ -180,6 +180,77 @@ def small_measure(torch, force_tiles: bool = False):
             "us_per_step": t / w.nsteps * 1e6}
 
 
+def taylor8_measure(torch):
+    """Lmax=15, N=500 with Taylor-8, dt=0.02 (12567 steps, 100536 products): the
+    second propagator the single-instance workload is run with."""
+    from paper_1201_6062_amd import workloads as wl
+    from paper_1201_6062_amd.api import Plan
+    w = wl.single_large("taylor", 8)
+    plan = Plan(w.ham.energies, w.ham.dipole)
+    ev, _, cT = time_propagation(plan, w, "taylor", 8, 2, 1, torch)
+    plan.close()
+    t = ev / 2
+    err = None
+    gold = os.path.join(ROOT, "tests", "golden", "single_large_taylor8.npz")
+    if os.path.exists(gold):
+        g = np.load(gold, allow_pickle=False)["cT"]
+        err = float(np.linalg.norm(cT[0] - g) / np.linalg.norm(g))
+    bpp = algorithmic_bytes_per_product(15, 500)
+    per = t / (8 * w.nsteps)
+    return {"workload": "Lmax=15 N=500, Taylor-8 dt=0.02, 12567 steps", "s_per_propagation": t,
+            "state_steps_per_s": w.ham.nstates * w.nsteps / t, "us_per_product": per * 1e6,
+            "GBps": bpp / per / 1e9, "frac_of_hbm_peak": bpp / per / 1e9 / HBM_PEAK_GBS,
+            "max_rel_err_vs_oracle": err}
+
+
+def lanczos_measure(torch, m: int = 12, dt: float = 0.05, steps: int = 200):
+    """Lmax=15, N=500 short-iterative Lanczos (Krylov dimension m, midpoint samples)."""
+    from paper_1201_6062_amd import workloads as wl
+    from paper_1201_6062_amd.api import Plan
+    h = wl.hamiltonian(15, 500, 0)
+    plan = Plan(h.energies, h.dipole)
+    f = torch.as_tensor(wl.taylor_samples(wl.Pulse(0.05, 0.5, 20.0), dt, steps, "mid")[None], device="cuda")
+    c0 = torch.as_tensor(wl.ground_state(15, 500), device="cuda")
+    plan.propagate(f[:, :4], c0, dt, "lanczos", order=m)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plan.propagate(f, c0, dt, "lanczos", order=m)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3
+    plan.close()
+    return {"workload": f"Lmax=15 N=500, Lanczos m={m}, dt={dt}, first {steps} steps of the 20-cycle pulse",
+            "state_steps_per_s": h.nstates * steps / s, "us_per_step": s / steps * 1e6,
+            "us_per_product": s / (steps * m) * 1e6}
+
+
+def lmax_sweep(torch, n: int = 500, steps: int = 512):
+    """Per-product time of the fused tile kernel against the dipole size at
+    N=500: flat while the dipole fits the XCDs' L2 (launch-latency floor),
+    then a step where it stops fitting."""
+    from paper_1201_6062_amd import workloads as wl
+    from paper_1201_6062_amd.api import Plan
+    out = []
+    for lmax in (7, 11, 13, 15, 16, 17, 19, 23):
+        en = wl.energies(lmax, n)
+        dip = np.random.default_rng(lmax).standard_normal((lmax, n, n)) * 0.01
+        plan = Plan(en, dip)
+
+        class W:
+            pass
+        w = W()
+        w.field = wl.rk4_samples(wl.Pulse(0.05, 0.5, 20.0), 0.005, steps)[None]
+        w.c0, w.dt = wl.ground_state(lmax, n), 0.005
+        ev, _, _ = time_propagation(plan, w, "rk4", 0, 3, 1, torch)
+        plan.close()
+        us = ev / 3 / (4 * steps) * 1e6
+        mb = 8 * lmax * n * n / 1e6
+        out.append({"lmax": lmax, "dipole_MB": mb, "MB_per_xcd": mb / 8, "us_per_product": us,
+                    "GBps": algorithmic_bytes_per_product(lmax, n) / us / 1e3})
+    return {"workload": "fused tile kernel, N=500, RK4, 512 steps per size", "points": out}
+
+
 def group_measure(torch, steps: int = 400):
     """64 uneven instances (Lmax 7..31, N 200..1000), first `steps` RK4 steps of each."""
     from paper_1201_6062_amd import workloads as wl
@@ -229,7 +300,8 @@ def main():
     ap.add_argument("--no-diag", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the small-problem and group measurements")
-    ap.add_argument("--only", choices=["single", "diag", "batched", "small", "small_tiles", "group"], default=None,
+    ap.add_argument("--only", choices=["single", "diag", "batched", "small", "small_tiles", "group", "taylor8",
+                                       "lanczos", "lsweep"], default=None,
                     help="profiling runs: measure one workload and print its record alone")
     ap.add_argument("--tile", default=None, help="batched tile TMxTN (tuning experiments)")
     ap.add_argument("--method", choices=["rk4", "taylor"], default="rk4")
@@ -254,7 +326,10 @@ def main():
             "batched": lambda: batched_measure(torch, steps=a.truncate or 100, tile=a.tile),
             "small": lambda: small_measure(torch),
             "small_tiles": lambda: small_measure(torch, force_tiles=True),
-            "group": lambda: group_measure(torch, steps=a.truncate or 400)}
+            "group": lambda: group_measure(torch, steps=a.truncate or 400),
+            "taylor8": lambda: taylor8_measure(torch),
+            "lanczos": lambda: lanczos_measure(torch),
+            "lsweep": lambda: lmax_sweep(torch)}
     if a.only in only:
         print(json.dumps(only[a.only]()))
         return
@@ -317,6 +392,8 @@ def main():
         out["single_small"] = small_measure(torch)
         out["single_small_tiles"] = small_measure(torch, force_tiles=True)
         out["uneven_group"] = group_measure(torch)
+        out["single_taylor8"] = taylor8_measure(torch)
+        out["lanczos"] = lanczos_measure(torch)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
