@@ -213,7 +213,6 @@ static tdse_status vec_alloc(tdse_plan p) {
     p->vb.ld = p->ld;
     p->vb.T = p->T;
     p->vb.gauge = p->gauge;
-    for (int q = 0; q <= 16; ++q) p->vb.seg[q] = (int32_t)split_start(p->n, p->T, q < p->T ? q : p->T);
     return TDSE_OK;
 }
 

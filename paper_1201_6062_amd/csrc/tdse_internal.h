@@ -92,7 +92,6 @@ struct VecBuffers {
     CallDesc *desc;
     int32_t lmax, n, ld, T;
     int32_t gauge;         // TDSE_LENGTH or TDSE_VELOCITY (how the two block uses combine)
-    int32_t seg[17];       // segment starts (Sec. 4.1 split of n over T), seg[T] = n
 };
 
 struct VecLaunch {

@@ -33,6 +33,11 @@ __device__ __forceinline__ double2 couple(int gauge, double2 r, double2 s) {
     if (gauge) return make_double2(r.y - s.y, -(r.x - s.x));
     return make_double2(r.x + s.x, r.y + s.y);
 }
+template <int G>
+__device__ __forceinline__ double2 couple_g(double2 r, double2 s) {
+    if constexpr (G != 0) return make_double2(r.y - s.y, -(r.x - s.x));
+    else return make_double2(r.x + s.x, r.y + s.y);
+}
 
 // Streaming (non-temporal) access for partials and state, so that they do not
 // displace dipole lines from the caches.
@@ -312,7 +317,7 @@ __device__ __forceinline__ void tile_products(const VecBuffers &b, TileLds &lds,
 // column partials of tile (l, i, j). T is the number of tiles per block
 // dimension (a compile-time constant where TP == T), F the field sample of
 // the completed product.
-template <int TP>
+template <int TP, int G>
 __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &L, int T, int l, int i, int j,
                                           int r0, int RA, int c0, int RB, double F, double dt,
                                           const CkptTarget &ct) {
@@ -367,7 +372,7 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
         if (e < len) {
             double2 c = c_in, acc = acc_in;
             u = u_in;
-            apply_completion(L.comp, dt, F, E0, couple(b.gauge, zpart, lds.zc[pe]), c, acc, u);
+            apply_completion(L.comp, dt, F, E0, couple_g<G>(zpart, lds.zc[pe]), c, acc, u);
             const bool owner = isB ? (l == b.lmax - 1 && i == 0) : (j == 0);
             if (owner) store_state(b, L, ct, gi, c, acc, u);
         }
@@ -405,7 +410,16 @@ __device__ __forceinline__ void products_body(const VecBuffers &b, int par, int 
     tile_products(b, lds, dv, T, l, i, j, RA, RB, par ^ 1);
 }
 
-template <int TP>
+// Start and length of segment q of n split over T (Sec. 4.1), without a
+// dependent load: T is a compile-time constant where TP == T.
+__device__ __forceinline__ void segment_of(int n, int T, int q, int *start, int *len) {
+    const int div = n / T, rem = n - div * T;
+    *start = q * div + (q < rem ? q : rem);
+    *len = div + (q < rem ? 1 : 0);
+}
+
+// G: compile-time gauge (0 length, 1 velocity) of the fused kernel.
+template <int TP, int G>
 __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_tiles_kernel(VecBuffers b, VecLaunch L) {
     // TP == T for T <= 8, so the tile decode divides by compile-time constants.
     const int T = TP <= 8 ? TP : b.T;
@@ -417,9 +431,10 @@ __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
     const CallDesc *d = b.desc;
     const double F = field_of(d, L), dt = d->dt;
     const CkptTarget ct = ckpt_target(b, L, d);
-    const int r0 = b.seg[i], RA = b.seg[i + 1] - r0;
-    const int c0 = b.seg[j], RB = b.seg[j + 1] - c0;
-    tile_body<TP>(b, L, T, l, i, j, r0, RA, c0, RB, F, dt, ct);
+    int r0, RA, c0, RB;
+    segment_of(b.n, T, i, &r0, &RA);
+    segment_of(b.n, T, j, &c0, &RB);
+    tile_body<TP, G>(b, L, T, l, i, j, r0, RA, c0, RB, F, dt, ct);
 }
 
 // Products-only launch of the split path (after a vec_combine launch).
@@ -431,8 +446,9 @@ __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
     const int xcd = w & 7, per = ntiles >> 3, extra = ntiles & 7;
     const int tile = xcd * per + (xcd < extra ? xcd : extra) + (w >> 3);
     const int l = tile / (T * T), rem = tile - l * T * T, i = rem / T, j = rem - i * T;
-    const int r0 = b.seg[i], RA = b.seg[i + 1] - r0;
-    const int c0 = b.seg[j], RB = b.seg[j + 1] - c0;
+    int r0, RA, c0, RB;
+    segment_of(b.n, T, i, &r0, &RA);
+    segment_of(b.n, T, j, &c0, &RB);
     products_body(b, L.parity, T, l, i, j, r0, RA, c0, RB);
 }
 
@@ -649,9 +665,26 @@ hipError_t chunk_begin(CallDesc *d, int64_t base, hipStream_t s) {
         }                                                                       \
     } while (0)
 
+template <int G>
+static void (*tiles_kernel_for(int T))(VecBuffers, VecLaunch) {
+    switch (T) {
+    case 1: return vec_tiles_kernel<1, G>;
+    case 2: return vec_tiles_kernel<2, G>;
+    case 3: return vec_tiles_kernel<3, G>;
+    case 4: return vec_tiles_kernel<4, G>;
+    case 5: return vec_tiles_kernel<5, G>;
+    case 6: return vec_tiles_kernel<6, G>;
+    case 7: return vec_tiles_kernel<7, G>;
+    case 8: return vec_tiles_kernel<8, G>;
+    default: return T <= 16 ? vec_tiles_kernel<16, G> : nullptr;
+    }
+}
+
 hipError_t vec_launch_tiles(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {
     const int ntiles = b.lmax * b.T * b.T;
-    TDSE_TP_DISPATCH(b.T, vec_tiles_kernel, dim3(ntiles), dim3(VEC_THREADS), 0, s, b, l);
+    void (*k)(VecBuffers, VecLaunch) = b.gauge ? tiles_kernel_for<1>(b.T) : tiles_kernel_for<0>(b.T);
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3(ntiles), dim3(VEC_THREADS), 0, s, b, l);
     return hipGetLastError();
 }
 hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {
