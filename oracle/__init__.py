@@ -53,6 +53,8 @@ def _load():
         lib.oracle_rk4_adjoint.restype = i32
         lib.oracle_taylor_adjoint.argtypes = [i32, i32, P, P, i32, d, i64, P, P, P, P]
         lib.oracle_taylor_adjoint.restype = i32
+        lib.oracle_rkf45.argtypes = [i32, i32, P, P, d, i64, P, P, P]
+        lib.oracle_rkf45.restype = i32
         lib.oracle_set_gauge.argtypes = [i32]
         lib.oracle_set_gauge.restype = None
         _lib = lib
@@ -204,6 +206,32 @@ def taylor_adjoint(energies, dipole, order, dt, field, c0, lam_t, n=None, gauge=
         if rc != 0:
             raise MemoryError("oracle_taylor_adjoint allocation failed")
         return lam, grad
+
+
+def rkf45(energies, dipole, dt, field, c0, n=None, gauge="length"):
+    """Runge-Kutta-Fehlberg 4(5) over field[B, nsteps, 6]; returns (c(T) [B, 2n],
+    err [B, nsteps]) with c advanced by the fourth-order weights."""
+    with _gauge(gauge):
+        en, dip, lmax, n = _dims_n(energies, dipole, n)
+        field = _f64(field)
+        if field.ndim == 2:
+            field = field[None]
+        c = np.array(c0, dtype=np.float64, copy=True, order="C")
+        if c.ndim == 1:
+            c = c[None]
+        assert field.shape[-1] == 6 and field.shape[0] == c.shape[0]
+        err = np.zeros(field.shape[:2])
+        lib = _load()
+        for b in range(c.shape[0]):
+            fb = _f64(field[b])
+            cb = np.ascontiguousarray(c[b])
+            eb = np.zeros(fb.shape[0])
+            rc = lib.oracle_rkf45(lmax, n, _p(en), _p(dip), float(dt), fb.shape[0], _p(fb), _p(cb), _p(eb))
+            if rc != 0:
+                raise MemoryError("oracle_rkf45 allocation failed")
+            c[b] = cb
+            err[b] = eb
+        return c, err
 
 
 def positive_mask(energies):

@@ -366,3 +366,54 @@ int oracle_taylor_adjoint(int lmax, int n, const double *en, const double *dip, 
     free(cs); free(terms); free(tb); free(h); free(z);
     return 0;
 }
+
+/*
+ * Runge-Kutta-Fehlberg 4(5) (the embedded pair of appendix B's RK family):
+ * six stages at t_k + c_i dt with c = (0, 1/4, 3/8, 12/13, 1, 1/2) and
+ * Fehlberg's coefficients a_ij; c advances with the fourth-order weights b4
+ * and err[k] = |dt sum_i (b5_i - b4_i) k_i|_2 estimates the local error of
+ * step k (b5: the fifth-order weights). field[k*6 + i] is the field at stage
+ * i of step k.
+ */
+int oracle_rkf45(int lmax, int n, const double *en, const double *dip, double dt, int64_t nsteps,
+                 const double *field, double *c, double *err)
+{
+    static const double A[6][5] = {
+        {0, 0, 0, 0, 0},
+        {1.0 / 4.0, 0, 0, 0, 0},
+        {3.0 / 32.0, 9.0 / 32.0, 0, 0, 0},
+        {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0, 0},
+        {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0},
+        {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}};
+    static const double B4[6] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0, -1.0 / 5.0, 0.0};
+    static const double B5[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0, 2.0 / 55.0};
+    size_t ns = (size_t)(lmax + 1) * n;
+    double *k[6];
+    for (int i = 0; i < 6; ++i) k[i] = malloc(16 * ns);
+    double *u = malloc(16 * ns), *tmp = malloc(16 * ns);
+    if (!u || !tmp) return -1;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        for (int i = 0; i < 6; ++i) {
+            for (size_t j = 0; j < 2 * ns; ++j) {
+                double acc = 0.0;
+                for (int q = 0; q < i; ++q) acc += A[i][q] * k[q][j];
+                u[j] = c[j] + dt * acc;
+            }
+            deriv(lmax, n, en, dip, field[6 * s + i], u, k[i], tmp);
+        }
+        double e2 = 0.0;
+        for (size_t j = 0; j < 2 * ns; ++j) {
+            double acc4 = 0.0, de = 0.0;
+            for (int i = 0; i < 6; ++i) {
+                acc4 += B4[i] * k[i][j];
+                de += (B5[i] - B4[i]) * k[i][j];
+            }
+            c[j] = c[j] + dt * acc4;
+            e2 += (dt * de) * (dt * de);
+        }
+        if (err) err[s] = sqrt(e2);
+    }
+    for (int i = 0; i < 6; ++i) free(k[i]);
+    free(u); free(tmp);
+    return 0;
+}

@@ -92,12 +92,20 @@ def nsteps_for(t_final: float, dt: float) -> int:
 
 
 RK4_SLOTS = (0.0, 0.5, 1.0)
+RKF45_SLOTS = (0.0, 0.25, 0.375, 12.0 / 13.0, 1.0, 0.5)   # Fehlberg stage times / dt
 
 
 def rk4_samples(pulse, dt: float, nsteps: int) -> np.ndarray:
     """RK4 stage samples per step: E(t_k), E(t_k + dt/2), E(t_k + dt); shape [nsteps, 3]."""
     k = np.arange(nsteps, dtype=np.float64)[:, None]
     t = (k + np.array(RK4_SLOTS)[None, :]) * dt
+    return np.ascontiguousarray(pulse(t))
+
+
+def rkf45_samples(pulse, dt: float, nsteps: int) -> np.ndarray:
+    """Runge-Kutta-Fehlberg stage samples per step, E(t_k + c_i dt); shape [nsteps, 6]."""
+    k = np.arange(nsteps, dtype=np.float64)[:, None]
+    t = (k + np.array(RKF45_SLOTS)[None, :]) * dt
     return np.ascontiguousarray(pulse(t))
 
 

@@ -699,3 +699,59 @@ def test_lanczos_preserves_the_norm(oracle_mod):
     fk = stepwise_fields(60, 0.1) + 0.1
     got = oracle_mod.lanczos(h.energies, h.dipole, 8, 0.1, fk[None], c0)[0]
     assert abs(np.linalg.norm(got) - 1.0) <= 1e-12
+
+
+# ---- Runge-Kutta-Fehlberg 4(5)
+
+def _dop853_reference(h, c0, pulse, t_final, gauge="length", q=None):
+    from scipy.integrate import solve_ivp
+    h0 = np.diag(h.energies)
+    h1 = (dense_h_velocity(h.energies, q, 1.0) - h0) if gauge == "velocity" else dense_h(h.energies, h.dipole, 1.0) - h0
+    sol = solve_ivp(lambda t, y: -1j * (h0 + float(pulse(t)) * h1) @ y, (0, t_final), cplx(c0).astype(complex),
+                    method="DOP853", rtol=1e-13, atol=1e-15)
+    return sol.y[:, -1]
+
+
+def test_rkf45_fourth_order_solution(oracle_mod):
+    """The propagated (fourth-order) solution converges at order 4 against a
+    tight DOP853 solve; stage samples in the wrong slots (planted by reversing
+    them) lose the order."""
+    h = wl.hamiltonian(1, 3, 2)
+    c0 = wl.ground_state(1, 3)[0]
+    pulse = wl.Pulse(0.8, 0.9, 2.0)
+    ref = _dop853_reference(h, c0, pulse, pulse.duration)
+
+    def err(nst, rev=False):
+        dt = pulse.duration / nst
+        f = wl.rkf45_samples(pulse, dt, nst)
+        if rev:
+            f = f[:, ::-1].copy()
+        cT, _ = oracle_mod.rkf45(h.energies, h.dipole, dt, f[None], c0[None])
+        return np.abs(cplx(cT[0]) - ref).max()
+
+    e = [err(m) for m in (60, 120, 240)]
+    assert 12.0 < e[0] / e[1] < 20.0 and 12.0 < e[1] / e[2] < 20.0, e
+    bad = [err(m, True) for m in (60, 120, 240)]
+    assert bad[1] / bad[2] < 5.0, bad
+
+
+def test_rkf45_error_estimate_tracks_the_local_error(oracle_mod):
+    """Over one step the estimate |dt sum (b5 - b4) k| scales as dt^5 and
+    matches the true local error of the fourth-order step (the fifth-order
+    solution being much closer to the exact one)."""
+    h = wl.hamiltonian(1, 4, 3)
+    rng = np.random.default_rng(2)
+    c0 = wl.random_state(rng, h.nstates)[0]
+    pulse = wl.Pulse(1.2, 0.8, 1.0)
+    t0 = 0.37 * pulse.duration
+    shifted = lambda t: pulse(np.asarray(t) + t0)  # noqa: E731
+    est, true = [], []
+    for dt in (0.1, 0.05, 0.025):
+        f = np.asarray(shifted(np.array(wl.RKF45_SLOTS) * dt))[None, None, :]
+        cT, e = oracle_mod.rkf45(h.energies, h.dipole, dt, f, c0[None])
+        ref = _dop853_reference(h, c0, shifted, dt)
+        est.append(e[0, 0])
+        true.append(np.linalg.norm(cplx(cT[0]) - ref))
+    assert 24.0 < est[0] / est[1] < 40.0 and 24.0 < est[1] / est[2] < 40.0, est
+    dev = [abs(1.0 - a / b) for a, b in zip(est, true)]
+    assert dev[0] > dev[1] > dev[2] and dev[2] < 0.1, (est, true)
