@@ -71,7 +71,8 @@ typedef enum {
 typedef enum {
     TDSE_RK4 = 0,            /* classic 4th-order Runge-Kutta, 4 products per step */
     TDSE_TAYLOR = 1,         /* truncated Taylor series of order p, p products per step */
-    TDSE_LANCZOS = 2         /* short-iterative Lanczos, Krylov dimension m (taylor_order), m products per step */
+    TDSE_LANCZOS = 2,        /* short-iterative Lanczos, Krylov dimension m (taylor_order), m products per step */
+    TDSE_RKF45 = 3           /* Runge-Kutta-Fehlberg 4(5), 6 products per step, S = 6 stage samples */
 } tdse_method;
 
 typedef enum {
@@ -150,6 +151,21 @@ tdse_status tdse_hmul(tdse_plan plan, const double *fields, const double *u, dou
 tdse_status tdse_propagate(tdse_plan plan, tdse_method method, int32_t taylor_order, double dt,
                            int64_t nsteps, const double *field, const double *c0, double *cT,
                            double *ckpt, int32_t ckpt_every, void *stream);
+
+/*
+ * Runge-Kutta-Fehlberg 4(5) propagation (the embedded pair of appendix B's
+ * explicit Runge-Kutta family): six stages per step at t_k + c_i dt,
+ * c = (0, 1/4, 3/8, 12/13, 1, 1/2), field [batch][nsteps][6] device samples
+ * at those times; c advances with the fourth-order weights, and if err !=
+ * NULL, err[b][k] (device [batch][nsteps]) receives |dt sum_i (b5_i - b4_i)
+ * k_i|_2, the estimate of step k's local error (for step-size control by the
+ * caller). tdse_propagate with TDSE_RKF45 is this call with err = NULL.
+ * Batch-1 plans run it on a batched twin of themselves. Errors: as
+ * tdse_propagate; TDSE_E_NOMEM if the stage workspace (5 state vectors per
+ * pulse, kept by the plan) cannot be allocated.
+ */
+tdse_status tdse_propagate_rkf45(tdse_plan plan, double dt, int64_t nsteps, const double *field, const double *c0,
+                                 double *cT, double *err, double *ckpt, int32_t ckpt_every, void *stream);
 
 /*
  * Discrete adjoint of tdse_propagate, for RK4 and for the Taylor series of

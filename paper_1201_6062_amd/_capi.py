@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtdse.so")
 
 TDSE_OK, TDSE_E_INVAL, TDSE_E_NOMEM, TDSE_E_HIP, TDSE_E_UNSUPPORTED, TDSE_E_UNSTABLE = range(6)
-TDSE_RK4, TDSE_TAYLOR, TDSE_LANCZOS = 0, 1, 2
+TDSE_RK4, TDSE_TAYLOR, TDSE_LANCZOS, TDSE_RKF45 = 0, 1, 2, 3
 TDSE_LENGTH, TDSE_VELOCITY = 0, 1
 STATUS_NAMES = {0: "TDSE_OK", 1: "TDSE_E_INVAL", 2: "TDSE_E_NOMEM", 3: "TDSE_E_HIP",
                 4: "TDSE_E_UNSUPPORTED", 5: "TDSE_E_UNSTABLE"}
@@ -32,6 +32,7 @@ SIGNATURES = {
     "tdse_plan_shape": (_st, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "tdse_hmul": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "tdse_propagate": (_st, [_vp, _st, _i32, _d, _i64, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "tdse_propagate_rkf45": (_st, [_vp, _d, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "tdse_adjoint": (_st, [_vp, _st, _i32, _d, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "tdse_group_create": (_st, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _vp]),
     "tdse_group_propagate": (_st, [_vp, _st, _i32, _d, ctypes.POINTER(_i64), ctypes.POINTER(_vp),

@@ -12,9 +12,10 @@ import numpy as np
 import torch
 
 from . import _capi
-from ._capi import TDSE_LANCZOS, TDSE_LENGTH, TDSE_RK4, TDSE_TAYLOR, TDSE_VELOCITY, TdseError, check
+from ._capi import TDSE_LANCZOS, TDSE_LENGTH, TDSE_RK4, TDSE_RKF45, TDSE_TAYLOR, TDSE_VELOCITY, TdseError, check
 
-METHODS = {"rk4": TDSE_RK4, "taylor": TDSE_TAYLOR, "lanczos": TDSE_LANCZOS}
+METHODS = {"rk4": TDSE_RK4, "taylor": TDSE_TAYLOR, "lanczos": TDSE_LANCZOS, "rkf45": TDSE_RKF45}
+RKF45_SLOTS = (0.0, 0.25, 0.375, 12.0 / 13.0, 1.0, 0.5)
 GAUGES = {"length": TDSE_LENGTH, "velocity": TDSE_VELOCITY}
 
 
@@ -35,7 +36,7 @@ def _ptr(t):
 
 
 def slots_of(method: str) -> int:
-    return 3 if method == "rk4" else 1
+    return {"rk4": 3, "rkf45": 6}.get(method, 1)
 
 
 class Plan:
@@ -111,6 +112,47 @@ class Plan:
                                        _ptr(cT), _ptr(ck), int(max(ckpt_every, 1)) if ck is not None else 0,
                                        _stream(self.device)))
         return (cT, ck) if ckpt_every > 0 else cT
+
+    def propagate_rkf45(self, field, c0, dt: float, ckpt_every: int = 0, out=None):
+        """Runge-Kutta-Fehlberg 4(5) over field [B, nsteps, 6] (samples at the six
+        stage times); returns (cT, err [B, nsteps]) and the checkpoints if asked."""
+        f = _dev_f64(field, self.device)
+        nsteps = f.numel() // (self.batch * 6)
+        f = f.reshape(self.batch, nsteps, 6).contiguous()
+        c0 = self._state(c0)
+        cT = out if out is not None else torch.empty_like(c0)
+        err = torch.empty(self.batch, nsteps, dtype=torch.float64, device=self.device)
+        ck = None
+        if ckpt_every > 0:
+            ck = torch.empty(self.batch, nsteps // ckpt_every + 1, 2 * self.nstates,
+                             dtype=torch.float64, device=self.device)
+        check(self._lib.tdse_propagate_rkf45(self._h, float(dt), nsteps, _ptr(f), _ptr(c0), _ptr(cT), _ptr(err),
+                                             _ptr(ck), int(max(ckpt_every, 1)) if ck is not None else 0,
+                                             _stream(self.device)))
+        return (cT, err, ck) if ckpt_every > 0 else (cT, err)
+
+    def propagate_adaptive(self, field_fn, c0, t_final: float, dt0: float, tol: float,
+                           dt_min: float = 1e-6, max_steps: int = 100000):
+        """Optional step-size control on top of the Runge-Kutta-Fehlberg error
+        estimate: one step at a time, field_fn(t) giving the field (or vector
+        potential) at an array of times [B, ...]; a step is accepted when every
+        pulse's estimate is <= tol, and the next dt is 0.9 dt (tol / err)^(1/5),
+        clipped to [dt/5, 2 dt]. Returns (c(t_final), accepted step sizes)."""
+        c = self._state(c0).clone()
+        t, dt, steps = 0.0, float(dt0), []
+        slots = np.array(RKF45_SLOTS)
+        while t < t_final * (1.0 - 1e-14) and len(steps) < max_steps:
+            h = min(dt, t_final - t)
+            f = np.asarray(field_fn(t + slots * h), dtype=np.float64)
+            f = np.broadcast_to(f, (self.batch, 6)).reshape(self.batch, 1, 6)
+            cn, err = self.propagate_rkf45(f, c, h)
+            e = float(err.max().item())
+            if e <= tol or h <= dt_min:
+                c, t = cn, t + h
+                steps.append(h)
+            fac = 2.0 if e == 0.0 else min(2.0, max(0.2, 0.9 * (tol / e) ** 0.2))
+            dt = max(dt_min, h * fac)
+        return c, steps
 
     def adjoint(self, field, c0, dt: float, lambda_t, ckpt=None, ckpt_every: int = 64,
                 method: str = "rk4", order: int = 8, want_lambda0: bool = True):

@@ -37,6 +37,21 @@ __device__ __forceinline__ double bat_xor1(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Runge-Kutta-Fehlberg 4(5) tableau (stage times 0, 1/4, 3/8, 12/13, 1, 1/2):
+// stage inputs u_{i+1} = c + dt sum_{q<=i} A[i+1][q] k_q, fourth-order
+// weights B4 (the solution carried forward) and E = B5 - B4 (the error
+// estimate, B5 the fifth-order weights).
+__constant__ double RKF_A[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.0 / 4.0, 0, 0, 0, 0},
+    {3.0 / 32.0, 9.0 / 32.0, 0, 0, 0},
+    {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0, 0},
+    {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0},
+    {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}};
+__constant__ double RKF_B4[6] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0, -1.0 / 5.0, 0.0};
+__constant__ double RKF_E[6] = {16.0 / 135.0 - 25.0 / 216.0, 0.0, 6656.0 / 12825.0 - 1408.0 / 2565.0,
+                                28561.0 / 56430.0 - 2197.0 / 4104.0, -9.0 / 50.0 + 1.0 / 5.0, 2.0 / 55.0};
+
 template <int TM, int TN, int KC>
 struct BatTile {
     static constexpr int THREADS = 256;
@@ -262,6 +277,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
                         b.acc[gi] = a;
                         break;
                     }
+                    case CK_RKF: {
+                        // stage st: keep k_st, then the next stage input, or after
+                        // the sixth stage the fourth-order step and its error
+                        const int st = L.slot;
+                        const size_t ks = (size_t)(lmax + 1) * Np * ldu;
+                        double sacc = 0.0, serr = 0.0;
+                        for (int q = 0; q < st; ++q) {
+                            const double kq = b.kst[(size_t)q * ks + gi];
+                            sacc = fma(st < 5 ? RKF_A[st + 1][q] : RKF_B4[q], kq, sacc);
+                            serr = fma(RKF_E[q], kq, serr);
+                        }
+                        if (st < 5) {
+                            b.kst[(size_t)st * ks + gi] = k;
+                            unext = fma(dt, fma(RKF_A[st + 1][st], k, sacc), c);
+                        } else {
+                            c = fma(dt, fma(RKF_B4[5], k, sacc), c);
+                            const double e = dt * fma(RKF_E[5], k, serr);
+                            gsum[j] = fma(e, e, gsum[j]);
+                            unext = c;
+                            b.c[gi] = c;
+                        }
+                        break;
+                    }
                     default: {  // CK_TAY_END
                         const double tm = L.a_next * dt * k;
                         c = (L.first ? c : a) + tm;
@@ -271,7 +309,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
                     }
                     }
                     Un[gi] = unext;
-                    if (L.ckpt && (L.kind == CK_RK4_END || L.kind == CK_TAY_END) && pulse < B && row < b.n) {
+                    const bool ends = L.kind == CK_RK4_END || L.kind == CK_TAY_END || (L.kind == CK_RKF && L.slot == 5);
+                    if (L.ckpt && ends && pulse < B && row < b.n) {
                         // caller layout [B][rows][2 n]
                         L.ckpt[((size_t)pulse * L.ckpt_rows + L.ckpt_row) * 2 * (size_t)(lmax + 1) * b.n +
                                2 * ((size_t)m * b.n + row) + (is_im ? 1 : 0)] = c;
@@ -280,10 +319,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
             }
         }
     }
-    if constexpr (ADJ) {
-        // Gradient partial of this row tile for each pulse of the column tile:
-        // rows of one lane (i, r), then the four 16-lane row groups, then the
-        // real/imaginary column pair, then the two row halves of the tile.
+    if (ADJ || (L.kind == CK_RKF && L.slot == 5 && L.gpart != nullptr)) {
+        // Per-pulse partial of this row tile (adjoint: the field gradient;
+        // Runge-Kutta-Fehlberg: the squared error estimate): rows of one lane
+        // (i, r), then the four 16-lane row groups, then the real/imaginary
+        // column pair, then the two row halves of the tile.
         __shared__ double gred[2][TN];
 #pragma unroll
         for (int j = 0; j < C::SN; ++j) {
@@ -379,6 +419,22 @@ hipError_t bat_pack(const BatBuffers &b, const double *c0, int taylor, hipStream
     hipLaunchKernelGGL(bat_pack_kernel, dim3(1024), dim3(256), 0, s, b, c0, taylor);
     return hipGetLastError();
 }
+__global__ void bat_reduce_err_kernel(const double *gpart, int rowtiles, int batch, int64_t k, int64_t nsteps,
+                                      double *err) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    double s = 0.0;
+    for (int rt = 0; rt < rowtiles; ++rt) s += gpart[(size_t)rt * batch + b];
+    err[(size_t)b * nsteps + k] = sqrt(s);
+}
+
+hipError_t bat_reduce_err(const double *gpart, int rowtiles, int batch, int64_t k, int64_t nsteps, double *err,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(bat_reduce_err_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, gpart, rowtiles, batch, k,
+                       nsteps, err);
+    return hipGetLastError();
+}
+
 hipError_t bat_unpack(const BatBuffers &b, double *out, hipStream_t s) {
     hipLaunchKernelGGL(bat_unpack_kernel, dim3(1024), dim3(256), 0, s, b, out);
     return hipGetLastError();

@@ -295,6 +295,9 @@ static void bat_schedule(tdse_method m, int order, std::vector<BatLaunch> &out) 
         out.push_back({CK_RK4_MID, 1, 0, 0, 2.0 / 6.0, 0.5, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr});
         out.push_back({CK_RK4_MID, 1, 0, 0, 2.0 / 6.0, 1.0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr});
         out.push_back({CK_RK4_END, 2, 0, 0, 1.0 / 6.0, 0.0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr});
+    } else if (m == TDSE_RKF45) {
+        for (int st = 0; st < 6; ++st)
+            out.push_back({CK_RKF, st, 0, 0, 0.0, 0.0, 0, 0, 0, 0, 0, 0, 0, nullptr, nullptr});
     } else {
         for (int t = 1; t <= order; ++t)
             out.push_back({t == order ? CK_TAY_END : CK_TAY_MID, 0, t == 1 ? 1 : 0, 0, 0.0, 1.0 / t, 0, 0, 0,
@@ -302,11 +305,28 @@ static void bat_schedule(tdse_method m, int order, std::vector<BatLaunch> &out) 
     }
 }
 
+static int slots_of(tdse_method m) { return m == TDSE_RK4 ? 3 : (m == TDSE_RKF45 ? 6 : 1); }
+
 static tdse_status bat_propagate(tdse_plan p, tdse_method m, int order, double dt, int64_t nsteps,
                                  const double *field, const double *c0, double *cT, double *ckpt,
-                                 int32_t K, hipStream_t s) {
+                                 int32_t K, hipStream_t s, double *err = nullptr) {
     BatBuffers b = p->bb;
     b.field = field;
+    double *gp = nullptr;
+    const int rowtiles = (b.lmax + 1) * (b.np / b.tm);
+    if (m == TDSE_RKF45) {
+        // k_1..k_5 and the per-row-tile error partials, kept by the plan
+        if (!p->rkf_mem) {
+            const size_t usz = (size_t)(b.lmax + 1) * b.np * b.ldu;
+            if (hipMalloc(&p->rkf_mem, (5 * usz + (size_t)rowtiles * b.batch) * sizeof(double)) != hipSuccess) {
+                (void)hipGetLastError();
+                p->rkf_mem = nullptr;
+                return fail(TDSE_E_NOMEM, "hipMalloc of the Runge-Kutta-Fehlberg workspace failed");
+            }
+        }
+        b.kst = p->rkf_mem;
+        gp = p->rkf_mem + 5 * (size_t)(b.lmax + 1) * b.np * b.ldu;
+    }
     TDSE_HIP(bat_pack(b, c0, m == TDSE_TAYLOR ? 1 : 0, s));
     const int rows = ckpt ? (int)(nsteps / K + 1) : 0;
     if (ckpt) TDSE_HIP(bat_ckpt0(b, c0, ckpt, rows, s));
@@ -319,15 +339,17 @@ static tdse_status bat_propagate(tdse_plan p, tdse_method m, int order, double d
             L.dt = dt;
             L.step = k;
             L.nsteps = nsteps;
-            L.slots = m == TDSE_RK4 ? 3 : 1;
+            L.slots = slots_of(m);
             if (ckpt && (k + 1) % K == 0) {
                 L.ckpt = ckpt;
                 L.ckpt_row = (int32_t)((k + 1) / K);
                 L.ckpt_rows = rows;
             }
+            if (err && L.kind == CK_RKF && L.slot == 5) L.gpart = gp;
             TDSE_HIP(bat_launch_stage(b, L, s));
             parity ^= 1;
         }
+        if (err) TDSE_HIP(bat_reduce_err(gp, rowtiles, b.batch, k, nsteps, err, s));
     }
     // the current c lives in b.c whatever the parity
     TDSE_HIP(bat_unpack(b, cT, s));
@@ -612,6 +634,21 @@ static tdse_status create_batched_twin(tdse_plan p, hipStream_t s) {
     return TDSE_OK;
 }
 
+// Runge-Kutta-Fehlberg runs on the batched kernels; a batch-1 plan uses its
+// batched twin (built on first use, shared with the adjoint).
+static tdse_status rkf_propagate(tdse_plan p, double dt, int64_t nsteps, const double *field, const double *c0,
+                                 double *cT, double *err, double *ckpt, int32_t K, hipStream_t s) {
+    tdse_plan q = p;
+    if (p->batch == 1) {
+        if (!p->adj_plan) {
+            tdse_status st = create_batched_twin(p, s);
+            if (st != TDSE_OK) return st;
+        }
+        q = p->adj_plan;
+    }
+    return bat_propagate(q, TDSE_RKF45, 0, dt, nsteps, field, c0, cT, ckpt, K, s, err);
+}
+
 }  // namespace tdse
 
 using namespace tdse;
@@ -730,6 +767,7 @@ tdse_status tdse_destroy(tdse_plan p) {
     for (hipGraph_t g : p->graph_defs) (void)hipGraphDestroy(g);
     if (p->scratch) (void)hipFree(p->scratch);
     if (p->bat_mem) (void)hipFree(p->bat_mem);
+    if (p->rkf_mem) (void)hipFree(p->rkf_mem);
     if (p->lz_mem) (void)hipFree(p->lz_mem);
     if (p->adj_mem) (void)hipFree(p->adj_mem);
     if (p->adj_plan) tdse_destroy(p->adj_plan);
@@ -794,6 +832,7 @@ tdse_status tdse_propagate(tdse_plan p, tdse_method method, int32_t order, doubl
     if (ckpt && (st = check_dev(ckpt, "ckpt"))) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (method == TDSE_LANCZOS) return lz_propagate(p, order, dt, nsteps, field, c0, cT, ckpt, ckpt_every, s);
+    if (method == TDSE_RKF45) return rkf_propagate(p, dt, nsteps, field, c0, cT, nullptr, ckpt, ckpt_every, s);
     if (p->batch > 1)
         return bat_propagate(p, method, method == TDSE_RK4 ? 4 : order, dt, nsteps, field, c0, cT, ckpt,
                              ckpt_every, s);
@@ -810,7 +849,8 @@ tdse_status tdse_adjoint(tdse_plan p, tdse_method method, int32_t order, double 
     tdse_status st = validate_propagate(p != nullptr, (int)method, method == TDSE_TAYLOR ? order : 4, dt, nsteps,
                                         true, ckpt_every, &why);
     if (st != TDSE_OK) return fail(st, why);
-    if (method == TDSE_LANCZOS) return fail(TDSE_E_UNSUPPORTED, "no adjoint for the Lanczos propagator");
+    if (method == TDSE_LANCZOS || method == TDSE_RKF45)
+        return fail(TDSE_E_UNSUPPORTED, "the adjoint covers RK4 and Taylor-p");
     if (nsteps > 0 && (st = check_dev(field, "field"))) return st;
     if ((st = check_dev(c0, "c0")) || (st = check_dev(lambdaT, "lambdaT"))) return st;
     if (nsteps > 0 && (st = check_dev(grad_field, "grad_field"))) return st;
@@ -827,6 +867,19 @@ tdse_status tdse_adjoint(tdse_plan p, tdse_method method, int32_t order, double 
         q = p->adj_plan;
     }
     return bat_adjoint(q, method, order, dt, nsteps, field, c0, ckpt, ckpt_every, lambdaT, grad_field, lambda0, s);
+}
+
+tdse_status tdse_propagate_rkf45(tdse_plan p, double dt, int64_t nsteps, const double *field, const double *c0,
+                                 double *cT, double *err, double *ckpt, int32_t ckpt_every, void *stream) {
+    clear_error();
+    std::string why;
+    tdse_status st = validate_propagate(p != nullptr, TDSE_RKF45, 0, dt, nsteps, ckpt != nullptr, ckpt_every, &why);
+    if (st != TDSE_OK) return fail(st, why);
+    if (nsteps > 0 && (st = check_dev(field, "field"))) return st;
+    if ((st = check_dev(c0, "c0")) || (st = check_dev(cT, "cT"))) return st;
+    if (ckpt && (st = check_dev(ckpt, "ckpt"))) return st;
+    if (err && nsteps > 0 && (st = check_dev(err, "err"))) return st;
+    return rkf_propagate(p, dt, nsteps, field, c0, cT, err, ckpt, ckpt_every, reinterpret_cast<hipStream_t>(stream));
 }
 
 // Captured group chunks hold the work-list addresses: drop them before the

@@ -44,6 +44,7 @@ enum CompletionKind : int32_t {
     CK_HMUL = -1,     // no completion: write y = E o u + F z (single product)
     CK_ADJ_MID = 4,   // adjoint stage j > 1 of a reversed RK4 step
     CK_ADJ_LAST = 5,  // adjoint stage 1: finishes the reversed step
+    CK_RKF = 6,       // Runge-Kutta-Fehlberg stage (slot = stage 0..5; batched path)
 };
 
 struct Completion {
@@ -156,6 +157,7 @@ struct BatBuffers {
     double *dT;            // [lmax][np][np]  D_l^T row-major, zero-padded
     double *u[2];          // [parity][(lmax+1)][np][ldu] stage inputs
     double *c, *acc;       // [(lmax+1)][np][ldu]
+    double *kst;           // Runge-Kutta-Fehlberg: stage derivatives k_1..k_5, [5][(lmax+1)][np][ldu]
     const double *field;   // caller [batch][nsteps][S]
     int32_t lmax, n, np, ldu, batch, tm, tn, kc;
     int32_t gauge;         // TDSE_LENGTH or TDSE_VELOCITY (d holds -Q_l in the velocity gauge)
@@ -187,6 +189,9 @@ hipError_t bat_launch_adjoint(const BatBuffers &b, const BatLaunch &l, hipStream
 hipError_t bat_reduce_grad(const double *gpart, int rowtiles, int batch, int64_t k0, int64_t len,
                            int64_t nsteps, int nprod, int rk4, double *grad, hipStream_t s);
 hipError_t bat_unpack(const BatBuffers &b, double *out, hipStream_t s);
+// err[b * nsteps + k] = sqrt(sum over row tiles of the squared-error partials)
+hipError_t bat_reduce_err(const double *gpart, int rowtiles, int batch, int64_t k, int64_t nsteps, double *err,
+                          hipStream_t s);
 hipError_t bat_ckpt0(const BatBuffers &b, const double *c0, double *ckpt, int rows, hipStream_t s);
 hipError_t bat_launch_stage(const BatBuffers &b, const BatLaunch &l, hipStream_t s);
 
@@ -262,6 +267,8 @@ struct tdse_plan_s {
     // Lanczos workspace (allocated on first use): basis, product, coefficients
     double *lz_mem = nullptr;
     size_t lz_bytes = 0;
+    // Runge-Kutta-Fehlberg workspace (batched plans, first use): k_1..k_5, error partials
+    double *rkf_mem = nullptr;
     tdse_plan adj_plan = nullptr;   // batched twin of a batch-1 plan, for the adjoint
     // captured chunk graphs keyed by (method, order, chunk steps, parity)
     std::map<std::string, hipGraphExec_t> graphs;

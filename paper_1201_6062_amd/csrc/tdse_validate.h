@@ -34,7 +34,7 @@ inline tdse_status validate_propagate(bool have_plan, int method, int32_t order,
                                       int64_t nsteps, bool have_ckpt, int32_t ckpt_every,
                                       std::string *why) {
     if (!have_plan) { *why = "plan is NULL"; return TDSE_E_INVAL; }
-    if (method != TDSE_RK4 && method != TDSE_TAYLOR && method != TDSE_LANCZOS) {
+    if (method != TDSE_RK4 && method != TDSE_TAYLOR && method != TDSE_LANCZOS && method != TDSE_RKF45) {
         *why = "unknown method";
         return TDSE_E_INVAL;
     }
