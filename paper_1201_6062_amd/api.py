@@ -144,7 +144,7 @@ class Plan:
         while t < t_final * (1.0 - 1e-14) and len(steps) < max_steps:
             h = min(dt, t_final - t)
             f = np.asarray(field_fn(t + slots * h), dtype=np.float64)
-            f = np.broadcast_to(f, (self.batch, 6)).reshape(self.batch, 1, 6)
+            f = np.array(np.broadcast_to(f, (self.batch, 6))).reshape(self.batch, 1, 6)
             cn, err = self.propagate_rkf45(f, c, h)
             e = float(err.max().item())
             if e <= tol or h <= dt_min:
