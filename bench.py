@@ -310,8 +310,8 @@ def main():
                     help="profiling runs only: propagate the first STEPS time steps")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path "
+              "(each pulse batch would run on its own GPU); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -196,13 +196,13 @@ static tdse_status vec_alloc(tdse_plan p) {
     size_t off = 0;
     for (int par = 0; par < 2; ++par)
         for (int v = 0; v < 3; ++v) {
-            p->vb.st[par][v] = reinterpret_cast<double2 *>(base + off);
+            p->vb.side[par].st[v] = reinterpret_cast<double2 *>(base + off);
             off += al(st_bytes);
         }
     for (int par = 0; par < 2; ++par) {
-        p->vb.rowp[par] = reinterpret_cast<double2 *>(base + off);
+        p->vb.side[par].rowp = reinterpret_cast<double2 *>(base + off);
         off += al(part_bytes);
-        p->vb.colp[par] = reinterpret_cast<double2 *>(base + off);
+        p->vb.side[par].colp = reinterpret_cast<double2 *>(base + off);
         off += al(part_bytes);
     }
     p->vb.desc = reinterpret_cast<CallDesc *>(base + off);

@@ -84,14 +84,22 @@ constexpr int VEC_TILE_MAX = 128;   // max rows/cols of one dipole tile
 constexpr int VEC_THREADS = 512;    // 8 waves per tile workgroup
 
 
+// Buffers of one parity (a launch reads one parity and writes the other).
+struct VecSide {
+    double2 *st[3];        // c, acc, u, each [(lmax+1)*n]
+    double2 *rowp;         // [lmax][T][T][VEC_TILE_MAX]
+    double2 *colp;         // [lmax][T(out seg j)][T(contrib i)][VEC_TILE_MAX]
+};
+
+// Field order: lmax, n, en, dip and side[0] fill the first 64 bytes, the
+// kernel-argument words a tile launch needs before its first memory access.
 struct VecBuffers {
+    int32_t lmax, n;
     const double *en;      // [(lmax+1)*n]
     const double *dip;     // tiles [lmax][T][T][VEC_TILE_MAX * VEC_TILE_MAX], order tile_pos
-    double2 *st[2][3];     // [parity][c, acc, u] each [(lmax+1)*n]
-    double2 *rowp[2];      // [parity][lmax][T][T][VEC_TILE_MAX]
-    double2 *colp[2];      // [parity][lmax][T(out seg j)][T(contrib i)][VEC_TILE_MAX]
+    VecSide side[2];       // [parity]
     CallDesc *desc;
-    int32_t lmax, n, ld, T;
+    int32_t ld, T;
     int32_t gauge;         // TDSE_LENGTH or TDSE_VELOCITY (how the two block uses combine)
 };
 

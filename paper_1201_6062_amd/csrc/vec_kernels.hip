@@ -59,6 +59,15 @@ __device__ __forceinline__ void st_global(double2 *p, double2 v) {
     *(gdv2_t *)(p) = w;
 }
 
+// Keeps a wave-uniform value in scalar registers at this point of the
+// program: the scalar load that produces it is issued here rather than sunk
+// towards its first use, where its round trip would join the critical path.
+// (An empty statement with a register operand: no instruction is emitted.)
+template <typename T>
+__device__ __forceinline__ void pin_sgpr(T &v) {
+    asm volatile("" : "+s"(v));
+}
+
 // Workgroup barrier that orders LDS only. __syncthreads() also orders global
 // memory, which on gfx9 waits for every outstanding global load and store
 // (vmcnt(0)) -- including the tile stream this kernel wants to keep in flight.
@@ -121,12 +130,12 @@ __device__ __forceinline__ void apply_completion(const Completion &cp, double dt
 // Buffer pointers by parity, selected without indexing the kernel-argument
 // struct at run time (that would turn into a dependent memory load).
 __device__ __forceinline__ double2 *st_ptr(const VecBuffers &b, int par, int v) {
-    if (v == 0) return par ? b.st[1][0] : b.st[0][0];
-    if (v == 1) return par ? b.st[1][1] : b.st[0][1];
-    return par ? b.st[1][2] : b.st[0][2];
+    if (v == 0) return par ? b.side[1].st[0] : b.side[0].st[0];
+    if (v == 1) return par ? b.side[1].st[1] : b.side[0].st[1];
+    return par ? b.side[1].st[2] : b.side[0].st[2];
 }
-__device__ __forceinline__ double2 *rowp_ptr(const VecBuffers &b, int par) { return par ? b.rowp[1] : b.rowp[0]; }
-__device__ __forceinline__ double2 *colp_ptr(const VecBuffers &b, int par) { return par ? b.colp[1] : b.colp[0]; }
+__device__ __forceinline__ double2 *rowp_ptr(const VecBuffers &b, int par) { return par ? b.side[1].rowp : b.side[0].rowp; }
+__device__ __forceinline__ double2 *colp_ptr(const VecBuffers &b, int par) { return par ? b.side[1].colp : b.side[0].colp; }
 
 __device__ __forceinline__ bool is_end(int kind) { return kind == CK_RK4_END || kind == CK_TAY_END; }
 
@@ -179,9 +188,9 @@ __device__ __forceinline__ double2 sum_partials(const VecBuffers &b, int T, int 
     return add_partials<TP>(load_partials<TP>(b, T, par, rows, m, q, e), T);
 }
 
-// Where (if anywhere) a launch's completion writes a checkpoint: the values
-// are read from the descriptor at kernel entry, before the tile loads, so no
-// later wait has to include the tile stream.
+// Where (if anywhere) a launch's completion writes a checkpoint. Both
+// descriptor words are read unconditionally and combined with selects, so
+// the two scalar loads issue together and nothing branches on the first.
 struct CkptTarget {
     double2 *slot;  // checkpoint row for this launch's completed step, or null
 };
@@ -190,9 +199,9 @@ __device__ __forceinline__ CkptTarget ckpt_target(const VecBuffers &b, const Vec
                                                   const CallDesc *d) {
     double *ck = d->ckpt;
     const int64_t row = d->chunk_ckpt_row[L.off + L.comp.step_delta + 1];
-    CkptTarget t{nullptr};
-    if (ck && is_end(L.comp.kind) && row >= 0)
-        t.slot = reinterpret_cast<double2 *>(ck) + (size_t)row * (size_t)(b.lmax + 1) * b.n;
+    const bool on = (ck != nullptr) & is_end(L.comp.kind) & (row >= 0);
+    CkptTarget t;
+    t.slot = on ? reinterpret_cast<double2 *>(ck) + (size_t)row * (size_t)(b.lmax + 1) * b.n : nullptr;
     return t;
 }
 
@@ -315,12 +324,10 @@ __device__ __forceinline__ void tile_products(const VecBuffers &b, TileLds &lds,
 // One tile workgroup of the fused path: completes the previous product for
 // segments A = (l, i) and B = (l+1, j) and produces this launch's row and
 // column partials of tile (l, i, j). T is the number of tiles per block
-// dimension (a compile-time constant where TP == T), F the field sample of
-// the completed product.
+// dimension (a compile-time constant where TP == T).
 template <int TP, int G>
 __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &L, int T, int l, int i, int j,
-                                          int r0, int RA, int c0, int RB, double F, double dt,
-                                          const CkptTarget &ct) {
+                                          int r0, int RA, int c0, int RB) {
     const int n = b.n;
     const int tile = (l * T + i) * T + j;
 
@@ -358,6 +365,16 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
     double2 dv[16];
 #pragma unroll
     for (int r = 0; r < EARLY; ++r) dv[r] = Dt[r * 64];
+    __builtin_amdgcn_sched_barrier(0);
+    // Per-call values (field sample, dt, checkpoint row) from the descriptor:
+    // scalar loads issued behind the vector loads, first waited for by the
+    // completion, so they add no round trip of their own to the launch.
+    const CallDesc *d = b.desc;
+    double F = field_of(d, L), dt = d->dt;
+    CkptTarget ct = ckpt_target(b, L, d);
+    pin_sgpr(F);
+    pin_sgpr(dt);
+    pin_sgpr(ct.slot);
     __builtin_amdgcn_sched_barrier(0);
     const double2 zpart = add_partials<TP>(pl, T);
     __builtin_amdgcn_sched_barrier(0);
@@ -428,13 +445,14 @@ __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
     const int xcd = w & 7, per = ntiles >> 3, extra = ntiles & 7;
     const int tile = xcd * per + (xcd < extra ? xcd : extra) + (w >> 3);  // Sec. 4.1 split over XCDs
     const int l = tile / (T * T), rem = tile - l * T * T, i = rem / T, j = rem - i * T;
-    const CallDesc *d = b.desc;
-    const double F = field_of(d, L), dt = d->dt;
-    const CkptTarget ct = ckpt_target(b, L, d);
     int r0, RA, c0, RB;
     segment_of(b.n, T, i, &r0, &RA);
     segment_of(b.n, T, j, &c0, &RB);
-    tile_body<TP, G>(b, L, T, l, i, j, r0, RA, c0, RB, F, dt, ct);
+    // The launcher hands every launch its buffers in parity-0 order (see
+    // vec_launch_tiles), so no buffer pointer is chosen at run time.
+    VecLaunch L0 = L;
+    L0.parity = 0;
+    tile_body<TP, G>(b, L0, T, l, i, j, r0, RA, c0, RB);
 }
 
 // Products-only launch of the split path (after a vec_combine launch).
@@ -546,11 +564,11 @@ __global__ void vec_start_kernel(VecBuffers b, int par, const double2 *c0, int t
     const size_t np = (size_t)b.lmax * b.T * b.T * VEC_TILE_MAX;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const double2 zero = make_double2(0.0, 0.0);
-    double2 *sc = par ? b.st[1][0] : b.st[0][0];
-    double2 *sa = par ? b.st[1][1] : b.st[0][1];
-    double2 *su = par ? b.st[1][2] : b.st[0][2];
-    double2 *rp = par ? b.rowp[1] : b.rowp[0];
-    double2 *cp = par ? b.colp[1] : b.colp[0];
+    double2 *sc = par ? b.side[1].st[0] : b.side[0].st[0];
+    double2 *sa = par ? b.side[1].st[1] : b.side[0].st[1];
+    double2 *su = par ? b.side[1].st[2] : b.side[0].st[2];
+    double2 *rp = par ? b.side[1].rowp : b.side[0].rowp;
+    double2 *cp = par ? b.side[1].colp : b.side[0].colp;
     for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < ns; g += stride) {
         double2 c = c0[g];
         sc[g] = c;
@@ -680,11 +698,26 @@ static void (*tiles_kernel_for(int T))(VecBuffers, VecLaunch) {
     }
 }
 
+// The fused kernel reads the parity-0 buffers and writes the parity-1 ones: a
+// launch of parity 1 is passed the buffer pairs exchanged instead, so the
+// kernel's pointers are fixed kernel-argument words (a pointer picked by a
+// run-time parity becomes a dependent load at kernel entry).
+static VecBuffers parity_view(const VecBuffers &b, int parity) {
+    VecBuffers v = b;
+    if (parity) {
+        v.side[0] = b.side[1];
+        v.side[1] = b.side[0];
+    }
+    return v;
+}
+
 hipError_t vec_launch_tiles(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {
     const int ntiles = b.lmax * b.T * b.T;
     void (*k)(VecBuffers, VecLaunch) = b.gauge ? tiles_kernel_for<1>(b.T) : tiles_kernel_for<0>(b.T);
     if (!k) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k, dim3(ntiles), dim3(VEC_THREADS), 0, s, b, l);
+    VecLaunch l0 = l;
+    l0.parity = 0;
+    hipLaunchKernelGGL(k, dim3(ntiles), dim3(VEC_THREADS), 0, s, parity_view(b, l.parity), l0);
     return hipGetLastError();
 }
 hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {
