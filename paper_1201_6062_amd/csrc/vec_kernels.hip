@@ -58,6 +58,12 @@ __device__ __forceinline__ void st_global(double2 *p, double2 v) {
     dv2_t w = {v.x, v.y};
     *(gdv2_t *)(p) = w;
 }
+// Streaming store through a pointer the compiler cannot trace to a kernel
+// argument (one held in registers with pin_sgpr), spelled as a global store.
+__device__ __forceinline__ void st_nt_global(double2 *p, double2 v) {
+    dv2_t w = {v.x, v.y};
+    __builtin_nontemporal_store(w, (gdv2_t *)(p));
+}
 
 // Keeps a wave-uniform value in scalar registers at this point of the
 // program: the scalar load that produces it is issued here rather than sunk
@@ -257,6 +263,13 @@ __device__ __forceinline__ void tile_products(const VecBuffers &b, TileLds &lds,
                                               int l, int i, int j, int RA, int RB, int npar) {
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
+    // Output bases held in scalar registers: the two partial stores below sit
+    // in branches on the thread index, and merged into one store they would
+    // otherwise pick the base by a per-lane load of the kernel argument (a
+    // vector load whose wait also drains every earlier store of the wave).
+    double2 *colp_out = colp_ptr(b, npar), *rowp_out = rowp_ptr(b, npar);
+    pin_sgpr(colp_out);
+    pin_sgpr(rowp_out);
     // ---- tile products. Lane (h, qq) holds rows qq + 16k and columns
     // cb .. cb+3: dv[2k] = D[row k][cb, cb+1], dv[2k+1] = D[row k][cb+2, cb+3].
     const int h = lane >> 4, qq = lane & 15;
@@ -306,8 +319,8 @@ __device__ __forceinline__ void tile_products(const VecBuffers &b, TileLds &lds,
             double2 s = lds.cbuf[t][0];
 #pragma unroll
             for (int k = 1; k < 16; ++k) s = cadd(s, lds.cbuf[t][k]);
-            double2 *cpo = colp_ptr(b, npar) + ((size_t)(l * T + j) * T + i) * VEC_TILE_MAX;
-            st_nt(cpo + t, s);
+            double2 *cpo = colp_out + ((size_t)(l * T + j) * T + i) * VEC_TILE_MAX;
+            st_nt_global(cpo + t, s);
         }
     } else if (t < 2 * VEC_TILE_MAX) {  // row partial of row a: sum over the 8 waves' columns
         const int a = t - VEC_TILE_MAX;
@@ -315,8 +328,8 @@ __device__ __forceinline__ void tile_products(const VecBuffers &b, TileLds &lds,
             double2 s = lds.rbuf[0][a];
 #pragma unroll
             for (int k = 1; k < VEC_THREADS / 64; ++k) s = cadd(s, lds.rbuf[k][a]);
-            double2 *rp = rowp_ptr(b, npar) + ((size_t)(l * T + i) * T + j) * VEC_TILE_MAX;
-            st_nt(rp + a, s);
+            double2 *rp = rowp_out + ((size_t)(l * T + i) * T + j) * VEC_TILE_MAX;
+            st_nt_global(rp + a, s);
         }
     }
 }
@@ -347,9 +360,15 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
     const int ec = e < len ? e : len - 1;
     const size_t gi = (size_t)m * n + s0 + ec;
     const PartialLoads<TP> pl = load_partials<TP>(b, T, par, half == 0, m, q, ec);
-    const double2 c_in = ld_nt(st_ptr(b, par, 0) + gi), acc_in = ld_nt(st_ptr(b, par, 1) + gi);
-    const double2 u_in = ld_nt(st_ptr(b, par, 2) + gi);
-    const double E0 = __builtin_nontemporal_load(b.en + gi);
+    // The state is read by the completing half only.
+    double2 c_in = make_double2(0.0, 0.0), acc_in = c_in, u_in = c_in;
+    double E0 = 0.0;
+    if (half == 0) {
+        c_in = ld_nt(st_ptr(b, par, 0) + gi);
+        acc_in = ld_nt(st_ptr(b, par, 1) + gi);
+        u_in = ld_nt(st_ptr(b, par, 2) + gi);
+        E0 = __builtin_nontemporal_load(b.en + gi);
+    }
 
     // ---- tile loads (stored in lane order, tile_pos): load jj of wave wv
     // reads 64 consecutive double2, one per lane. Rows and columns past the
@@ -384,19 +403,22 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
     // ---- completion of the previous product (overlaps the tile stream).
     if (half == 1) lds.zc[pe] = zpart;
     lds_barrier();
+    double2 c = c_in, acc = acc_in, u = make_double2(0.0, 0.0);
+    bool owner = false;
     if (half == 0) {
-        double2 u = make_double2(0.0, 0.0);
         if (e < len) {
-            double2 c = c_in, acc = acc_in;
             u = u_in;
             apply_completion(L.comp, dt, F, E0, couple_g<G>(zpart, lds.zc[pe]), c, acc, u);
-            const bool owner = isB ? (l == b.lmax - 1 && i == 0) : (j == 0);
-            if (owner) store_state(b, L, ct, gi, c, acc, u);
+            owner = isB ? (l == b.lmax - 1 && i == 0) : (j == 0);
         }
         (isB ? lds.uB : lds.uA)[e] = u;
     }
     lds_barrier();
     tile_products(b, lds, dv, T, l, i, j, RA, RB, par ^ 1);
+    // The completed state is stored after the products: one counter covers
+    // vector loads and stores, so a store issued before them would be waited
+    // for together with the last tile loads.
+    if (owner) store_state(b, L, ct, gi, c, acc, u);
 }
 
 // One tile workgroup of the split path: the stage inputs were completed by
