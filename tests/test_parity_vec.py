@@ -126,6 +126,21 @@ def test_single_large_truncated(torch_dev):
     assert rel_l2(got, ref) <= TOL
 
 
+def test_split_at_scale(torch_dev):
+    """Lmax=40, N=500 (640 tiles of 128x128, more than two per CU): the
+    library's own choice is the split path; 6 RK4 steps and 3 Taylor-6 steps
+    vs the live oracle."""
+    h = wl.hamiltonian(40, 500, 11)
+    plan = make_plan(h)
+    c0 = wl.ground_state(40, 500)
+    f = wl.rk4_samples(wl.Pulse(0.08, 0.6, 2.0), 0.01, 6)[None]
+    got = plan.propagate(f, c0, 0.01, "rk4").cpu().numpy()
+    assert rel_l2(got, oracle.rk4(h.energies, h.dipole, 0.01, f, c0)) <= TOL
+    ft = wl.taylor_samples(wl.Pulse(0.08, 0.6, 2.0), 0.01, 3)[None]
+    got = plan.propagate(ft, c0, 0.01, "taylor", order=6).cpu().numpy()
+    assert rel_l2(got, oracle.taylor(h.energies, h.dipole, 6, 0.01, ft, c0)) <= TOL
+
+
 @pytest.mark.parametrize("name,method,order", [("single_large_rk4", "rk4", 0),
                                                ("single_large_taylor8", "taylor", 8)])
 def test_single_large_full_length(torch_dev, name, method, order):
