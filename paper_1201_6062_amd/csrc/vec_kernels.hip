@@ -39,16 +39,16 @@ __device__ __forceinline__ double2 couple_g(double2 r, double2 s) {
     else return make_double2(r.x + s.x, r.y + s.y);
 }
 
-// Streaming (non-temporal) access for partials and state, so that they do not
-// displace dipole lines from the caches.
+// 16-byte access to partials and state. Plain (cached) accesses: with the
+// non-temporal hint a product at Lmax=15, N=500 took 6% longer -- the next
+// launch's reads of the partials then came from further out.
 typedef double dv2_t __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ double2 ld_nt(const double2 *p) {
-    dv2_t v = __builtin_nontemporal_load(reinterpret_cast<const dv2_t *>(p));
+__device__ __forceinline__ double2 ld2(const double2 *p) {
+    dv2_t v = *reinterpret_cast<const dv2_t *>(p);
     return make_double2(v.x, v.y);
 }
-__device__ __forceinline__ void st_nt(double2 *p, double2 v) {
-    dv2_t w = {v.x, v.y};
-    __builtin_nontemporal_store(w, reinterpret_cast<dv2_t *>(p));
+__device__ __forceinline__ void st2(double2 *p, double2 v) {
+    *reinterpret_cast<dv2_t *>(p) = dv2_t{v.x, v.y};
 }
 // Store through a pointer that was itself loaded from memory: spelled as a
 // global-address-space store (a generic/flat store would also count against
@@ -58,11 +58,11 @@ __device__ __forceinline__ void st_global(double2 *p, double2 v) {
     dv2_t w = {v.x, v.y};
     *(gdv2_t *)(p) = w;
 }
-// Streaming store through a pointer the compiler cannot trace to a kernel
-// argument (one held in registers with pin_sgpr), spelled as a global store.
-__device__ __forceinline__ void st_nt_global(double2 *p, double2 v) {
+// The same through a pointer the compiler cannot trace to a kernel argument
+// (one held in registers with pin_sgpr), spelled as a global store.
+__device__ __forceinline__ void st2_global(double2 *p, double2 v) {
     dv2_t w = {v.x, v.y};
-    __builtin_nontemporal_store(w, (gdv2_t *)(p));
+    *(gdv2_t *)(p) = w;
 }
 
 // Keeps a wave-uniform value in scalar registers at this point of the
@@ -172,7 +172,7 @@ __device__ __forceinline__ PartialLoads<TP> load_partials(const VecBuffers &b, i
     double2 *pr = rowp_ptr(b, par), *pc = colp_ptr(b, par);
     const double2 *base = (rows ? pr : pc) + ((size_t)(mb * T + q) * T) * VEC_TILE_MAX + e;
 #pragma unroll
-    for (int k = 0; k < TP; ++k) p.v[k] = ld_nt(base + (size_t)(k < T ? k : T - 1) * VEC_TILE_MAX);
+    for (int k = 0; k < TP; ++k) p.v[k] = ld2(base + (size_t)(k < T ? k : T - 1) * VEC_TILE_MAX);
     return p;
 }
 
@@ -217,9 +217,9 @@ __device__ __forceinline__ void store_state(const VecBuffers &b, const VecLaunch
                                             const CkptTarget &ct, size_t gi, double2 c,
                                             double2 acc, double2 u) {
     const int par = L.parity;
-    st_nt(st_ptr(b, par ^ 1, 0) + gi, c);
-    st_nt(st_ptr(b, par ^ 1, 1) + gi, acc);
-    st_nt(st_ptr(b, par ^ 1, 2) + gi, u);
+    st2(st_ptr(b, par ^ 1, 0) + gi, c);
+    st2(st_ptr(b, par ^ 1, 1) + gi, acc);
+    st2(st_ptr(b, par ^ 1, 2) + gi, u);
     if (ct.slot) st_global(ct.slot + gi, c);
 }
 
@@ -320,7 +320,7 @@ __device__ __forceinline__ void tile_products(const VecBuffers &b, TileLds &lds,
 #pragma unroll
             for (int k = 1; k < 16; ++k) s = cadd(s, lds.cbuf[t][k]);
             double2 *cpo = colp_out + ((size_t)(l * T + j) * T + i) * VEC_TILE_MAX;
-            st_nt_global(cpo + t, s);
+            st2_global(cpo + t, s);
         }
     } else if (t < 2 * VEC_TILE_MAX) {  // row partial of row a: sum over the 8 waves' columns
         const int a = t - VEC_TILE_MAX;
@@ -329,7 +329,7 @@ __device__ __forceinline__ void tile_products(const VecBuffers &b, TileLds &lds,
 #pragma unroll
             for (int k = 1; k < VEC_THREADS / 64; ++k) s = cadd(s, lds.rbuf[k][a]);
             double2 *rp = rowp_out + ((size_t)(l * T + i) * T + j) * VEC_TILE_MAX;
-            st_nt_global(rp + a, s);
+            st2_global(rp + a, s);
         }
     }
 }
@@ -364,10 +364,10 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
     double2 c_in = make_double2(0.0, 0.0), acc_in = c_in, u_in = c_in;
     double E0 = 0.0;
     if (half == 0) {
-        c_in = ld_nt(st_ptr(b, par, 0) + gi);
-        acc_in = ld_nt(st_ptr(b, par, 1) + gi);
-        u_in = ld_nt(st_ptr(b, par, 2) + gi);
-        E0 = __builtin_nontemporal_load(b.en + gi);
+        c_in = ld2(st_ptr(b, par, 0) + gi);
+        acc_in = ld2(st_ptr(b, par, 1) + gi);
+        u_in = ld2(st_ptr(b, par, 2) + gi);
+        E0 = b.en[gi];
     }
 
     // ---- tile loads (stored in lane order, tile_pos): load jj of wave wv
@@ -439,7 +439,7 @@ __device__ __forceinline__ void products_body(const VecBuffers &b, int par, int 
     double2 u = make_double2(0.0, 0.0);
     if (t < 2 * VEC_TILE_MAX) {
         const size_t gi = (size_t)(isB ? l + 1 : l) * b.n + (isB ? c0 : r0) + (e < len ? e : len - 1);
-        u = ld_nt(st_ptr(b, par ^ 1, 2) + gi);
+        u = ld2(st_ptr(b, par ^ 1, 2) + gi);
     }
     double2 dv[16];
 #pragma unroll
@@ -530,7 +530,7 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_group_combine_kernel(const G
     const int par = L.parity;
     const double2 z = couple(b.gauge, sum_partials<8>(b, b.T, par, true, gs.m, gs.q, e),
                              sum_partials<8>(b, b.T, par, false, gs.m, gs.q, e));
-    double2 c = ld_nt(st_ptr(b, par, 0) + g), acc = ld_nt(st_ptr(b, par, 1) + g), u = ld_nt(st_ptr(b, par, 2) + g);
+    double2 c = ld2(st_ptr(b, par, 0) + g), acc = ld2(st_ptr(b, par, 1) + g), u = ld2(st_ptr(b, par, 2) + g);
     apply_completion(L.comp, desc->dt, F, b.en[g], z, c, acc, u);
     store_state(b, L, CkptTarget{nullptr}, g, c, acc, u);
 }
@@ -569,7 +569,7 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_combine_kernel(VecBuffers b,
     double2 z = make_double2(0.0, 0.0);
     if (b.lmax > 0)
         z = couple(b.gauge, sum_partials<TP>(b, T, par, true, m, q, e), sum_partials<TP>(b, T, par, false, m, q, e));
-    double2 c = ld_nt(st_ptr(b, par, 0) + gi), acc = ld_nt(st_ptr(b, par, 1) + gi), u = ld_nt(st_ptr(b, par, 2) + gi);
+    double2 c = ld2(st_ptr(b, par, 0) + gi), acc = ld2(st_ptr(b, par, 1) + gi), u = ld2(st_ptr(b, par, 2) + gi);
     const double E0 = b.en[gi];
     if (L.comp.kind == CK_HMUL) {
         double yr = fma(F, z.x, E0 * u.x), yi = fma(F, z.y, E0 * u.y);
