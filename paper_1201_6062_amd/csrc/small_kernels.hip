@@ -5,13 +5,15 @@
 // Each state entry (m, a) is owned by a group of 4 lanes. Row a of H's
 // off-diagonal blocks (Sec. 4, the block product after Eq. ode) is the
 // concatenation of row a of D_m (towards u_{m+1}) and column a of D_{m-1}
-// (towards u_{m-1}); its 2n dipole elements are split over the 4 lanes and
-// held in registers for the whole run. Per product every lane forms its
-// partial dot product against u (double-buffered in LDS), the group sums the
-// 4 partials with DPP in fixed order, and the group's first lane completes
-// the RK4 stage or Taylor term (appendix B) with c and the stage accumulator
-// kept in its registers. One LDS barrier per product; field samples are
-// staged into LDS 64 steps at a time, one chunk ahead.
+// (towards u_{m-1}): lanes 0 and 1 of the group hold the two halves of the
+// first, lanes 2 and 3 the two halves of the second, in registers for the
+// whole run. A lane's elements multiply consecutive entries of u, so its LDS
+// reads are one base address plus compile-time offsets. Per product every
+// lane forms its partial dot product against u (double-buffered in LDS), the
+// group sums the 4 partials with DPP in fixed order, and the group's first
+// lane completes the RK4 stage or Taylor term (appendix B) with c and the
+// stage accumulator kept in its registers. One LDS barrier per product; field
+// samples are staged into LDS 64 steps at a time, one chunk ahead.
 #include "tdse_internal.h"
 
 namespace tdse {
@@ -42,7 +44,11 @@ struct SmallArgs {
     int32_t lmax, n, method, order, gauge;
 };
 
-// EPL: compiled bound on the dipole elements per lane, ceil(2n / 4) <= EPL.
+// Entries of one u buffer in LDS: the states plus room for the reads of the
+// lanes whose elements run past their block (those elements are zero).
+constexpr int SMALL_UBUF = 256 + 64;
+
+// EPL: compiled bound on the dipole elements per lane, ceil(n / 2) <= EPL.
 template <int EPL>
 __global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
     const int n = A.n, lmax = A.lmax, ns = (lmax + 1) * n;
@@ -52,34 +58,43 @@ __global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
     const bool live = entry < ns;
     const int es = live ? entry : 0;
     const int m = es / n, a = es - m * n;
-    const int epl = (2 * n + 3) / 4;
+    const int half = (n + 1) / 2;  // elements per lane
 
-    __shared__ double2 ubuf[2][256];
+    __shared__ double2 ubuf[2][SMALL_UBUF];
     __shared__ double fbuf[2][64 * 3];
+    __shared__ double tay_scale[64];  // dt / (p + 1) of Taylor term p + 1
 
-    // dipole elements of this lane (zero where the element does not exist);
-    // element e < n multiplies u_{m+1}[e], element e >= n multiplies u_{m-1}[e-n]
+    // dipole elements of this lane (zero where the element does not exist):
+    // lanes 0, 1: row a of D_m, columns b = (g & 1) half + k, times u_{m+1}[b];
+    // lanes 2, 3: column a of D_{m-1}, rows b = (g & 1) half + k, times u_{m-1}[b]
+    const bool up = g < 2;
+    const int b0 = (g & 1) * half;
     double d[EPL];
     const size_t tile = (size_t)VEC_TILE_MAX * VEC_TILE_MAX;
 #pragma unroll
     for (int k = 0; k < EPL; ++k) {
-        const int e = g * epl + k;
+        const int bb = b0 + k;
         double v = 0.0;
-        if (live && k < epl && e < 2 * n) {
-            if (e < n) {  // row a of D_m
-                if (m < lmax) v = A.dip[(size_t)m * tile + tile_pos(a, e)];
-            } else {      // column a of D_{m-1}
+        if (live && k < half && bb < n) {
+            if (up) {
+                if (m < lmax) v = A.dip[(size_t)m * tile + tile_pos(a, bb)];
+            } else {
                 // velocity gauge: the column use enters with a minus sign, -i (r - s)
-                if (m > 0) v = (A.gauge ? -1.0 : 1.0) * A.dip[(size_t)(m - 1) * tile + tile_pos(e - n, a)];
+                if (m > 0) v = (A.gauge ? -1.0 : 1.0) * A.dip[(size_t)(m - 1) * tile + tile_pos(bb, a)];
             }
         }
         d[k] = v;
     }
-    const int e0 = g * epl;
-    const int row_base = (m + 1) * n, col_base = (m - 1) * n - n;
+    // first u entry this lane reads; a missing neighbour block reads entries
+    // 0.. instead (its elements are zero)
+    int ubase = up ? (m + 1) * n + b0 : (m - 1) * n + b0;
+    if ((up && m >= lmax) || (!up && m <= 0) || !live) ubase = 0;
     const double E0 = live ? A.en[es] : 0.0;
     double2 c = make_double2(0.0, 0.0), acc = c;
     if (live) c = reinterpret_cast<const double2 *>(A.c0)[es];
+    for (int x = t; x < 2 * SMALL_UBUF; x += blockDim.x) ubuf[x / SMALL_UBUF][x % SMALL_UBUF] = make_double2(0.0, 0.0);
+    if (t < 64) tay_scale[t] = A.dt / (double)(t + 1);
+    __syncthreads();
     if (live && g == 0) {
         ubuf[0][es] = c;
         if (A.ckpt) reinterpret_cast<double2 *>(A.ckpt)[es] = c;
@@ -104,21 +119,24 @@ __global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
             }
         }
         for (int p = 0; p < nprod; ++p) {
-            // partial dot product of this lane
-            double zr = 0.0, zi = 0.0;
+            // partial dot product of this lane (two interleaved chains)
+            const double2 *ub = &ubuf[par][ubase];
+            double zr = 0.0, zi = 0.0, zr1 = 0.0, zi1 = 0.0;
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
-                if (k < epl) {
-                    const int e = e0 + k;
-                    int idx = e < n ? row_base + e : col_base + e;
-                    idx = (idx >= 0 && idx < ns) ? idx : 0;  // d[k] == 0 there
-                    const double2 u = ubuf[par][idx];
+                const double2 u = ub[k];
+                if (k & 1) {
+                    zr1 = fma(d[k], u.x, zr1);
+                    zi1 = fma(d[k], u.y, zi1);
+                } else {
                     zr = fma(d[k], u.x, zr);
                     zi = fma(d[k], u.y, zi);
                 }
                 // keep at most 8 LDS reads in flight (register budget at 1024 threads)
                 if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
             }
+            zr += zr1;
+            zi += zi1;
             zr += small_dpp(zr, 1);
             zi += small_dpp(zi, 1);
             zr += small_dpp(zr, 2);
@@ -139,7 +157,7 @@ __global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
                 double2 un;
                 if (A.method == TDSE_RK4) {
                     if (p == 0) {
-                        acc = make_double2(kr / 6.0, ki / 6.0);
+                        acc = make_double2(kr * (1.0 / 6.0), ki * (1.0 / 6.0));
                         un = make_double2(fma(0.5 * dt, kr, c.x), fma(0.5 * dt, ki, c.y));
                     } else if (p < 3) {
                         acc = make_double2(fma(1.0 / 3.0, kr, acc.x), fma(1.0 / 3.0, ki, acc.y));
@@ -152,7 +170,7 @@ __global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
                     }
                 } else {
                     // Taylor term T_{p+1} = (dt / (p+1)) k, accumulated onto c
-                    const double sc = dt / (double)(p + 1);
+                    const double sc = tay_scale[p];
                     un = make_double2(sc * kr, sc * ki);
                     acc = p == 0 ? make_double2(c.x + un.x, c.y + un.y)
                                  : make_double2(acc.x + un.x, acc.y + un.y);
@@ -179,7 +197,7 @@ hipError_t small_propagate(const double *en, const double *dip, int gauge, int l
                            int64_t ckpt_every, hipStream_t s) {
     SmallArgs A{en, dip, field, c0, cT, ckpt, nsteps, ckpt_every > 0 ? ckpt_every : 1, dt, lmax, n, method, order, gauge};
     const int threads = (((lmax + 1) * n * 4 + 63) / 64) * 64;
-    const int epl = (2 * n + 3) / 4;
+    const int epl = (n + 1) / 2;  // dipole elements per lane
     if (epl <= 16) hipLaunchKernelGGL(small_propagate_kernel<16>, dim3(1), dim3(threads), 0, s, A);
     else if (epl <= 26) hipLaunchKernelGGL(small_propagate_kernel<26>, dim3(1), dim3(threads), 0, s, A);
     else hipLaunchKernelGGL(small_propagate_kernel<32>, dim3(1), dim3(threads), 0, s, A);
