@@ -375,7 +375,7 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
     // segment are stored as zeros.
     const double2 *Dt = reinterpret_cast<const double2 *>(b.dip) +
                         (size_t)tile * (VEC_TILE_MAX * VEC_TILE_MAX / 2) + wv * 16 * 64 + lane;
-    // The partial sums wait for the partial loads only (issued first); they
+    // The partial sums wait for the prologue loads only (issued first); they
     // are placed after the first EARLY tile loads are in flight, so the tile
     // stream is not held back by the prologue. With 8 partials per entry the
     // remaining loads are issued after the sum to stay within 128 VGPRs (with
