@@ -52,7 +52,8 @@ def test_batched_hmul(lmax, n, batch):
 
 
 @pytest.mark.parametrize("lmax,n,batch,nsteps", [(1, 1, 2, 40), (2, 3, 2, 50), (3, 50, 5, 40),
-                                                 (2, 130, 17, 20), (0, 6, 3, 30), (15, 500, 32, 6)])
+                                                 (2, 130, 17, 20), (0, 6, 3, 30), (15, 500, 32, 6),
+                                                 (1, 2048, 3, 6)])
 def test_batched_rk4(lmax, n, batch, nsteps):
     h = wl.hamiltonian(lmax, n, 4)
     dt = 0.01

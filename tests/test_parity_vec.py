@@ -86,6 +86,27 @@ def test_rk4_parity(torch_dev, lmax, n, nsteps, path, monkeypatch):
     assert rel_l2(got, ref) <= TOL
 
 
+@pytest.mark.parametrize("lmax,n,nsteps", [(2, 1100, 10), (1, 2048, 8)])
+def test_rk4_parity_largest_blocks(torch_dev, lmax, n, nsteps, path, monkeypatch):
+    """N beyond 1024 (9 tiles per block dimension) up to the largest supported
+    N = 2048 (16): the tile kernels with a run-time tile count."""
+    apply_path(path, monkeypatch, n)
+    h, f, c0 = _rk4_case(lmax, n, nsteps, 0.01)
+    plan = make_plan(h)
+    got = plan.propagate(f, c0, 0.01, "rk4").cpu().numpy()
+    ref = oracle.rk4(h.energies, h.dipole, 0.01, f, c0, n=n)
+    assert rel_l2(got, ref) <= TOL
+
+
+def test_block_size_beyond_limit_is_rejected(torch_dev):
+    """N = 2049 would need 17 tiles per block dimension: plan creation fails
+    with an error, nothing is launched."""
+    from paper_1201_6062_amd.api import Plan, TdseError
+    n = 2049
+    with pytest.raises(TdseError):
+        Plan(np.linspace(-0.5, 1.0, 2 * n), np.zeros((1, n, n)))
+
+
 @pytest.mark.parametrize("order", [1, 2, 4, 8, 10])
 @pytest.mark.parametrize("lmax,n,nsteps", [(2, 3, 70), (3, 130, 66), (0, 5, 64)])
 def test_taylor_parity(torch_dev, order, lmax, n, nsteps, path, monkeypatch):
