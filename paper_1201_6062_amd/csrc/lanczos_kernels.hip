@@ -6,8 +6,11 @@
 // T the tridiagonal of the alphas and betas. The products H v_j are the
 // plan's own product kernels; these kernels do the per-pulse reductions,
 // the recurrence, the small exponential and the recombination. Vectors are in
-// the caller layout [pulse][2 n] (interleaved complex); every reduction runs
-// in one workgroup per pulse, in a fixed order.
+// the caller layout [pulse][2 n] (interleaved complex). With several pulses
+// the recurrence runs in one workgroup per pulse; a single pulse spreads it
+// over many workgroups (alpha from the product launch's per-segment dots,
+// then an update and a normalisation launch). Every reduction has a fixed
+// order.
 #include "tdse_internal.h"
 
 namespace tdse {
@@ -79,8 +82,9 @@ __global__ __launch_bounds__(LZ_THREADS) void lz_orth_kernel(const double *vj, c
 // over s sub-steps, s chosen so that dt |T| / s <= 1/2 (|T| bounded by its
 // largest Gershgorin row sum): truncation below 1e-17 per sub-step.
 __global__ __launch_bounds__(64) void lz_expm_kernel(const double *alpha, const double *beta, const double *beta0,
-                                                     double dt, int m, double2 *y) {
+                                                     double dt_arg, const double *dt_dev, int m, double2 *y) {
     const int b = blockIdx.x, j = threadIdx.x;
+    const double dt = dt_dev ? *dt_dev : dt_arg;  // a captured step reads the call's dt from device memory
     const bool in = j < m;
     const double a = in ? alpha[(size_t)b * m + j] : 0.0;
     const double bu = (in && j + 1 < m) ? beta[(size_t)b * m + j] : 0.0;       // T[j][j+1]
@@ -145,6 +149,104 @@ __global__ void lz_ckpt0_kernel(const double *c0, double *ckpt, int batch, int64
     }
 }
 
+// One pulse over many workgroups (a single workgroup would stream the
+// vectors through one CU). Reductions: every workgroup reduces the same
+// partial array in the same tree order, so all of them hold the same sum.
+constexpr int LZ_WIDE_THREADS = 256;
+
+// Sum of p[0 .. count) in a fixed tree order (same in every workgroup).
+__device__ __forceinline__ double lz_tree_sum(const double *p, int count, double *red) {
+    const int t = threadIdx.x;
+    double v = 0.0;
+    for (int k = t; k < count; k += LZ_WIDE_THREADS) v += p[k];
+    red[t] = v;
+    __syncthreads();
+    for (int h = LZ_WIDE_THREADS / 2; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// alpha_j = sum of the per-segment parts of Re <v_j, w>; unless last,
+// w <- w - alpha_j v_j - beta_{j-1} v_{j-1} and this workgroup's part of |w|^2
+// to normp[workgroup]. Workgroup 0 stores alpha_j.
+__global__ __launch_bounds__(LZ_WIDE_THREADS) void lz_update_kernel(const double *dotp, int nseg, const double *vj,
+                                                                    const double *vjm1, double *w, double *alpha,
+                                                                    const double *beta, int j, int last,
+                                                                    double *normp, int64_t ncplx) {
+    __shared__ double red[LZ_WIDE_THREADS];
+    const double a = lz_tree_sum(dotp, nseg, red);
+    if (blockIdx.x == 0 && threadIdx.x == 0) alpha[j] = a;
+    if (last) return;
+    const double bprev = j > 0 ? beta[j - 1] : 0.0;
+    double s2 = 0.0;
+    const double2 *v2 = reinterpret_cast<const double2 *>(vj), *p2 = reinterpret_cast<const double2 *>(vjm1);
+    double2 *w2 = reinterpret_cast<double2 *>(w);
+    for (int64_t g = (int64_t)blockIdx.x * LZ_WIDE_THREADS + threadIdx.x; g < ncplx;
+         g += (int64_t)gridDim.x * LZ_WIDE_THREADS) {
+        double2 x = w2[g];
+        const double2 v = v2[g];
+        x.x -= a * v.x;
+        x.y -= a * v.y;
+        if (j > 0) {
+            const double2 pv = p2[g];
+            x.x -= bprev * pv.x;
+            x.y -= bprev * pv.y;
+        }
+        w2[g] = x;
+        s2 = fma(x.x, x.x, fma(x.y, x.y, s2));
+    }
+    red[threadIdx.x] = s2;
+    __syncthreads();
+    for (int h = LZ_WIDE_THREADS / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) normp[blockIdx.x] = red[0];
+}
+
+// beta_j = |w| (with the breakdown rule of lz_orth_kernel), v_{j+1} = w / beta_j.
+__global__ __launch_bounds__(LZ_WIDE_THREADS) void lz_normalize_kernel(const double *normp, int nparts,
+                                                                       const double *w, double *vnext,
+                                                                       const double *alpha, double *beta, int j,
+                                                                       int64_t ncplx) {
+    __shared__ double red[LZ_WIDE_THREADS];
+    double bj = sqrt(lz_tree_sum(normp, nparts, red));
+    const double bprev = j > 0 ? beta[j - 1] : 0.0;
+    if (bj <= 1e-13 * (fabs(alpha[j]) + bprev)) bj = 0.0;
+    const double inv = bj > 0.0 ? 1.0 / bj : 0.0;
+    const double2 *w2 = reinterpret_cast<const double2 *>(w);
+    double2 *v2 = reinterpret_cast<double2 *>(vnext);
+    for (int64_t g = (int64_t)blockIdx.x * LZ_WIDE_THREADS + threadIdx.x; g < ncplx;
+         g += (int64_t)gridDim.x * LZ_WIDE_THREADS) {
+        const double2 x = w2[g];
+        v2[g] = make_double2(x.x * inv, x.y * inv);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) beta[j] = bj;
+}
+
+int lz_wide_groups(int64_t ncplx) {
+    const int64_t g = (ncplx + LZ_WIDE_THREADS - 1) / LZ_WIDE_THREADS;
+    return (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
+}
+
+hipError_t lz_update(const double *dotp, int nseg, const double *vj, const double *vjm1, double *w, double *alpha,
+                     const double *beta, int j, int last, double *normp, int64_t ncplx, hipStream_t s) {
+    hipLaunchKernelGGL(lz_update_kernel, dim3(last ? 1 : lz_wide_groups(ncplx)), dim3(LZ_WIDE_THREADS), 0, s, dotp,
+                       nseg, vj, vjm1, w, alpha, beta, j, last, normp, ncplx);
+    return hipGetLastError();
+}
+hipError_t lz_normalize(const double *normp, const double *w, double *vnext, const double *alpha, double *beta,
+                        int j, int64_t ncplx, hipStream_t s) {
+    const int g = lz_wide_groups(ncplx);
+    hipLaunchKernelGGL(lz_normalize_kernel, dim3(g), dim3(LZ_WIDE_THREADS), 0, s, normp, g, w, vnext, alpha, beta, j,
+                       ncplx);
+    return hipGetLastError();
+}
+
 hipError_t lz_begin(const double *c, double *v1, double *beta0, int batch, int64_t len, hipStream_t s) {
     hipLaunchKernelGGL(lz_begin_kernel, dim3(batch), dim3(LZ_THREADS), 0, s, c, v1, beta0, len);
     return hipGetLastError();
@@ -155,9 +257,9 @@ hipError_t lz_orth(const double *vj, const double *vjm1, double *w, double *vnex
                        last, len);
     return hipGetLastError();
 }
-hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0, double dt, int m, int batch,
-                   double *y, hipStream_t s) {
-    hipLaunchKernelGGL(lz_expm_kernel, dim3(batch), dim3(64), 0, s, alpha, beta, beta0, dt, m,
+hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0, double dt, const double *dt_dev,
+                   int m, int batch, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(lz_expm_kernel, dim3(batch), dim3(64), 0, s, alpha, beta, beta0, dt, dt_dev, m,
                        reinterpret_cast<double2 *>(y));
     return hipGetLastError();
 }

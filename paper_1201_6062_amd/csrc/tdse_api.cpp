@@ -383,7 +383,7 @@ static tdse_status bat_hmul(tdse_plan p, const double *fields, const double *u, 
 // y = H(field[., k]) u for the plan's pulses (caller layout). Single-vector
 // plans read the sample from the chunk staged at `base` by chunk_begin.
 static hipError_t lz_product(tdse_plan p, const double *field, int64_t nsteps, int64_t k, int64_t base,
-                             const double *u, double *y, hipStream_t s) {
+                             const double *u, double *y, double *dotp, hipStream_t s) {
     hipError_t e;
     if (p->batch > 1) {
         BatBuffers b = p->bb;
@@ -399,20 +399,68 @@ static hipError_t lz_product(tdse_plan p, const double *field, int64_t nsteps, i
         L.out = y;
         return bat_launch_stage(b, L, s);
     }
-    if ((e = vec_launch_start(p->vb, 0, u, TDSE_RK4, s)) != hipSuccess) return e;
-    VecLaunch L{};
-    L.comp = {CK_RK4_END, 0, -1, 0, 1.0 / 6.0, 0.0};  // no-op completion: forms the input u
-    L.parity = 0;
-    L.slots = 1;
-    e = p->lmax > 0 ? vec_launch_tiles(p->vb, L, s) : vec_launch_combine(p->vb, L, s);
-    if (e != hipSuccess) return e;
+    // The Krylov vector itself is the product input: the products launch of
+    // the split path reads u from the parity-0 state buffers, which this
+    // launch's copy of the buffers points at u; the completion launch then
+    // forms y = E o u + F z from the partials and u.
+    VecBuffers vb = p->vb;
+    vb.side[0].st[2] = reinterpret_cast<double2 *>(const_cast<double *>(u));
+    if (p->lmax > 0) {
+        VecLaunch P{};
+        P.parity = 1;  // reads u from parity 0, writes the partials of parity 0
+        P.slots = 1;
+        if ((e = vec_launch_products(vb, P, s)) != hipSuccess) return e;
+    }
     VecLaunch H{};
     H.comp = {CK_HMUL, 0, 0, 0, 0.0, 0.0};
-    H.parity = 1;
+    H.parity = 0;
     H.slots = 1;
     H.off = (int32_t)(k - base);
     H.out = y;
-    return vec_launch_combine(p->vb, H, s);
+    return dotp ? vec_launch_hmul_dot(vb, H, dotp, s) : vec_launch_combine(vb, H, s);
+}
+
+// The steps of short-iterative Lanczos from k0 (k0 - base: offset in the
+// field chunk) on the state c: per step the Krylov basis, m products with the
+// recurrence, the small exponential and the recombination. ckpt rows are
+// written when ckpt is given.
+struct LzWork {
+    double *V, *W, *alpha, *beta, *beta0, *y, *C;
+    double *dotp, *normp;  // one pulse: per-segment dots, per-workgroup norms
+    size_t vstride;
+    int64_t len, ncplx;
+};
+
+static hipError_t lz_enqueue_steps(tdse_plan p, const LzWork &w, int m, double dt, const double *dt_dev,
+                                   int64_t nsteps, const double *field, int64_t k0, int64_t count, int64_t base,
+                                   double *c, double *ckpt, int32_t K, int64_t rows, hipStream_t s) {
+    const int B = p->batch;
+    hipError_t e = hipSuccess;
+    for (int64_t k = k0; k < k0 + count && e == hipSuccess; ++k) {
+        e = lz_begin(c, w.V, w.beta0, B, w.len, s);
+        for (int j = 0; j < m && e == hipSuccess; ++j) {
+            const double *vj = w.V + (size_t)j * w.vstride;
+            const bool last = j + 1 == m;
+            double *vnext = last ? nullptr : w.V + (size_t)(j + 1) * w.vstride;
+            if (B == 1) {  // the recurrence spread over many workgroups
+                e = lz_product(p, field, nsteps, k, base, vj, w.W, w.dotp, s);
+                if (e == hipSuccess)
+                    e = lz_update(w.dotp, (p->lmax + 1) * p->T, vj, j > 0 ? vj - w.vstride : nullptr, w.W, w.alpha,
+                                  w.beta, j, last ? 1 : 0, w.normp, w.ncplx, s);
+                if (e == hipSuccess && !last) e = lz_normalize(w.normp, w.W, vnext, w.alpha, w.beta, j, w.ncplx, s);
+            } else {       // one workgroup per pulse
+                e = lz_product(p, field, nsteps, k, base, vj, w.W, nullptr, s);
+                if (e == hipSuccess)
+                    e = lz_orth(vj, j > 0 ? vj - w.vstride : nullptr, w.W, vnext, w.alpha, w.beta, j, m, last ? 1 : 0,
+                                B, w.len, s);
+            }
+        }
+        if (e == hipSuccess) e = lz_expm(w.alpha, w.beta, w.beta0, dt, dt_dev, m, B, w.y, s);
+        const bool row = ckpt && (k + 1) % K == 0;
+        if (e == hipSuccess)
+            e = lz_combine(w.V, w.vstride, w.y, m, B, w.ncplx, c, row ? ckpt : nullptr, rows, row ? (k + 1) / K : 0, s);
+    }
+    return e;
 }
 
 static tdse_status lz_propagate(tdse_plan p, int m, double dt, int64_t nsteps, const double *field,
@@ -420,24 +468,50 @@ static tdse_status lz_propagate(tdse_plan p, int m, double dt, int64_t nsteps, c
     const int B = p->batch;
     const int64_t ncplx = (int64_t)(p->lmax + 1) * p->n, len = 2 * ncplx;
     const size_t vstride = (size_t)B * len;
-    const size_t need = ((size_t)(m + 1) * vstride + (size_t)B * (4 * m + 1)) * sizeof(double);
+    // V (m vectors), W, the recurrence coefficients and y, and for captured
+    // steps a state vector of the plan's own (a graph cannot follow cT)
+    const size_t nseg = (size_t)(p->lmax + 1) * (p->T > 0 ? p->T : 1);
+    const size_t need = ((size_t)(m + 2) * vstride + (size_t)B * (4 * m + 1) + nseg + (size_t)lz_wide_groups(ncplx)) *
+                        sizeof(double);
     if (need > p->lz_bytes) {
         if (p->lz_mem) (void)hipFree(p->lz_mem);
         p->lz_mem = nullptr;
         p->lz_bytes = 0;
+        for (auto it = p->graphs.begin(); it != p->graphs.end();) {  // captured with the old workspace
+            if (it->first.rfind("lz:", 0) == 0) {
+                (void)hipGraphExecDestroy(it->second);
+                it = p->graphs.erase(it);
+            } else {
+                ++it;
+            }
+        }
         if (hipMalloc(&p->lz_mem, need) != hipSuccess) {
             (void)hipGetLastError();
             return fail(TDSE_E_NOMEM, "hipMalloc of the Lanczos workspace failed");
         }
         p->lz_bytes = need;
     }
-    double *V = p->lz_mem;                       // v_1 .. v_m, then w
-    double *W = V + (size_t)m * vstride;
-    double *alpha = W + vstride, *beta = alpha + (size_t)B * m, *beta0 = beta + (size_t)B * m;
-    double *y = beta0 + B;                       // [B][m] complex
-    if (cT != c0) TDSE_HIP(hipMemcpyAsync(cT, c0, vstride * sizeof(double), hipMemcpyDeviceToDevice, s));
+    LzWork w;
+    w.V = p->lz_mem;                             // v_1 .. v_m, then w
+    w.W = w.V + (size_t)m * vstride;
+    w.C = w.W + vstride;
+    w.alpha = w.C + vstride;
+    w.beta = w.alpha + (size_t)B * m;
+    w.beta0 = w.beta + (size_t)B * m;
+    w.y = w.beta0 + B;                           // [B][m] complex
+    w.dotp = w.y + (size_t)2 * B * m;
+    w.normp = w.dotp + nseg;
+    w.vstride = vstride;
+    w.len = len;
+    w.ncplx = ncplx;
     const int64_t rows = ckpt ? nsteps / K + 1 : 0;
     if (ckpt) TDSE_HIP(lz_ckpt0(c0, ckpt, B, len, rows, s));
+    // Single pulse, no checkpoints: whole 64-step chunks replay a captured
+    // graph on the plan's state vector (the launches of a step are many and
+    // short, so enqueueing them one by one would dominate).
+    const bool capture = B == 1 && !ckpt && graphs_enabled() && nsteps >= CHUNK_STEPS;
+    double *c = capture ? w.C : cT;
+    if (c != c0) TDSE_HIP(hipMemcpyAsync(c, c0, vstride * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (B == 1) {
         CallDesc d{};
         d.nsteps = nsteps;
@@ -447,23 +521,41 @@ static tdse_status lz_propagate(tdse_plan p, int m, double dt, int64_t nsteps, c
         d.slots = 1;
         TDSE_HIP(set_desc(p->vb.desc, d, s));
     }
-    int64_t base = 0;
-    for (int64_t k = 0; k < nsteps; ++k) {
-        if (B == 1 && k % CHUNK_STEPS == 0) {
-            base = k;
-            TDSE_HIP(chunk_begin(p->vb.desc, base, s));
+    hipGraphExec_t ge = nullptr;
+    if (capture) {
+        char key[64];
+        snprintf(key, sizeof key, "lz:%d:%d", m, CHUNK_STEPS);
+        auto it = p->graphs.find(key);
+        if (it != p->graphs.end()) {
+            ge = it->second;
+        } else {
+            hipStream_t cs;
+            TDSE_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            // offsets 0 .. 63 of a chunk; field and dt come from the descriptor
+            if (e == hipSuccess)
+                e = lz_enqueue_steps(p, w, m, dt, &p->vb.desc->dt, nsteps, field, 0, CHUNK_STEPS, 0, w.C, nullptr, K,
+                                     0, cs);
+            hipError_t e2 = hipStreamEndCapture(cs, &g);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipStreamDestroy(cs);
+            if (e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(e, "graph capture of a Lanczos chunk");
+            }
+            p->graphs[key] = ge;
+            p->graph_defs.push_back(g);
         }
-        TDSE_HIP(lz_begin(cT, V, beta0, B, len, s));
-        for (int j = 0; j < m; ++j) {
-            const double *vj = V + (size_t)j * vstride;
-            TDSE_HIP(lz_product(p, field, nsteps, k, base, vj, W, s));
-            TDSE_HIP(lz_orth(vj, j > 0 ? vj - vstride : nullptr, W, j + 1 < m ? V + (size_t)(j + 1) * vstride : nullptr,
-                             alpha, beta, j, m, j + 1 == m, B, len, s));
-        }
-        TDSE_HIP(lz_expm(alpha, beta, beta0, dt, m, B, y, s));
-        const bool row = ckpt && (k + 1) % K == 0;
-        TDSE_HIP(lz_combine(V, vstride, y, m, B, ncplx, cT, row ? ckpt : nullptr, rows, row ? (k + 1) / K : 0, s));
     }
+    for (int64_t done = 0; done < nsteps; done += CHUNK_STEPS) {
+        const int64_t count = nsteps - done < CHUNK_STEPS ? nsteps - done : CHUNK_STEPS;
+        if (B == 1) TDSE_HIP(chunk_begin(p->vb.desc, done, s));
+        if (ge && count == CHUNK_STEPS) TDSE_HIP(hipGraphLaunch(ge, s));
+        else TDSE_HIP(lz_enqueue_steps(p, w, m, dt, nullptr, nsteps, field, done, count, done, c, ckpt, K, rows, s));
+    }
+    if (c != cT) TDSE_HIP(hipMemcpyAsync(cT, c, vstride * sizeof(double), hipMemcpyDeviceToDevice, s));
     return TDSE_OK;
 }
 

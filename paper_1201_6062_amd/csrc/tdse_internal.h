@@ -208,8 +208,19 @@ hipError_t bat_launch_stage(const BatBuffers &b, const BatLaunch &l, hipStream_t
 hipError_t lz_begin(const double *c, double *v1, double *beta0, int batch, int64_t len, hipStream_t s);
 hipError_t lz_orth(const double *vj, const double *vjm1, double *w, double *vnext, double *alpha, double *beta,
                    int j, int m, int last, int batch, int64_t len, hipStream_t s);
-hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0, double dt, int m, int batch,
-                   double *y, hipStream_t s);
+// One pulse over many workgroups: alpha_j from per-segment partial dots,
+// the recurrence update with per-workgroup partial norms, then beta_j and
+// v_{j+1}. lz_wide_groups: the workgroup count (normp holds that many).
+int lz_wide_groups(int64_t ncplx);
+hipError_t lz_update(const double *dotp, int nseg, const double *vj, const double *vjm1, double *w, double *alpha,
+                     const double *beta, int j, int last, double *normp, int64_t ncplx, hipStream_t s);
+hipError_t lz_normalize(const double *normp, const double *w, double *vnext, const double *alpha, double *beta,
+                        int j, int64_t ncplx, hipStream_t s);
+// y = H u with the per-segment parts of Re <u, y> in dotp[(lmax+1) T]
+hipError_t vec_launch_hmul_dot(const VecBuffers &b, const VecLaunch &l, double *dotp, hipStream_t s);
+// dt_dev: if not null, dt is read from there at run time (captured steps)
+hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0, double dt, const double *dt_dev,
+                   int m, int batch, double *y, hipStream_t s);
 hipError_t lz_combine(const double *V, size_t vstride, const double *y, int m, int batch, int64_t ncplx, double *c,
                       double *ckpt, int64_t ckpt_rows, int64_t ckpt_row, hipStream_t s);
 hipError_t lz_ckpt0(const double *c0, double *ckpt, int batch, int64_t len, int64_t rows, hipStream_t s);

@@ -581,6 +581,41 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_combine_kernel(VecBuffers b,
     if (L.finish) reinterpret_cast<double2 *>(L.out)[gi] = c;
 }
 
+// y = E o u + F z (the single product, as CK_HMUL of vec_combine_kernel)
+// together with this segment's part of Re <u, y>, summed over the segment in
+// a fixed tree order: dotp[segment]. For the Lanczos recurrence.
+template <int TP>
+__global__ __launch_bounds__(VEC_TILE_MAX) void vec_hmul_dot_kernel(VecBuffers b, VecLaunch L, double *dotp) {
+    __shared__ double red[VEC_TILE_MAX];
+    const int T = TP <= 8 ? TP : b.T;
+    const int seg = blockIdx.x;
+    const int m = seg / T, q = seg - m * T;
+    const int s0 = (int)split_start(b.n, T, q), len = (int)split_len(b.n, T, q);
+    const int e = threadIdx.x;
+    const int par = L.parity;
+    const double F = field_of(b.desc, L);
+    double dot = 0.0;
+    if (e < len) {
+        const size_t gi = (size_t)m * b.n + s0 + e;
+        double2 z = make_double2(0.0, 0.0);
+        if (b.lmax > 0)
+            z = couple(b.gauge, sum_partials<TP>(b, T, par, true, m, q, e),
+                       sum_partials<TP>(b, T, par, false, m, q, e));
+        const double2 u = ld2(st_ptr(b, par, 2) + gi);
+        const double E0 = b.en[gi];
+        const double yr = fma(F, z.x, E0 * u.x), yi = fma(F, z.y, E0 * u.y);
+        reinterpret_cast<double2 *>(L.out)[gi] = make_double2(yr, yi);
+        dot = fma(u.x, yr, u.y * yi);
+    }
+    red[e] = dot;
+    __syncthreads();
+    for (int h = VEC_TILE_MAX / 2; h > 0; h >>= 1) {
+        if (e < h) red[e] += red[e + h];
+        __syncthreads();
+    }
+    if (e == 0) dotp[seg] = red[0];
+}
+
 __global__ void vec_start_kernel(VecBuffers b, int par, const double2 *c0, int taylor) {
     const size_t ns = (size_t)(b.lmax + 1) * b.n;
     const size_t np = (size_t)b.lmax * b.T * b.T * VEC_TILE_MAX;
@@ -744,6 +779,10 @@ hipError_t vec_launch_tiles(const VecBuffers &b, const VecLaunch &l, hipStream_t
 }
 hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {
     TDSE_TP_DISPATCH(b.T, vec_combine_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s, b, l);
+    return hipGetLastError();
+}
+hipError_t vec_launch_hmul_dot(const VecBuffers &b, const VecLaunch &l, double *dotp, hipStream_t s) {
+    TDSE_TP_DISPATCH(b.T, vec_hmul_dot_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s, b, l, dotp);
     return hipGetLastError();
 }
 hipError_t vec_launch_products(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {

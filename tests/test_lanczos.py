@@ -42,6 +42,23 @@ def test_lanczos_matches_oracle(lmax, n, batch, m, nsteps):
     assert rel_l2(got, ref) <= TOL
 
 
+@pytest.mark.parametrize("lmax,n", [(2, 70), (0, 9)])
+def test_lanczos_captured_chunks(lmax, n):
+    """A single pulse without checkpoints replays captured 64-step chunks:
+    150 steps (two chunks and a 22-step tail), then the same plan again with
+    another dt, state and field (the chunk graph is reused; dt and the field
+    come from the call's descriptor)."""
+    h = wl.hamiltonian(lmax, n, 5)
+    blocks = h.dipole if lmax > 0 else np.zeros((0, n, n))
+    plan = make_plan(h.energies, blocks, 1)
+    for dt, seed, nsteps in ((0.05, 1, 150), (0.03, 2, 130)):
+        f = samples(1, dt, nsteps)
+        c0 = wl.random_state(np.random.default_rng(seed), h.nstates, 1)
+        got = plan.propagate(f, c0, dt, "lanczos", order=6).cpu().numpy()
+        ref = oracle.lanczos(h.energies, h.dipole, 6, dt, f, c0, n=n)
+        assert rel_l2(got, ref) <= TOL, (dt, nsteps)
+
+
 @pytest.mark.parametrize("batch", [1, 4])
 def test_lanczos_velocity_gauge(batch):
     h = wl.hamiltonian(2, 90, 3)
