@@ -136,8 +136,13 @@ __device__ __forceinline__ void bat_chunk(const char *__restrict__ la, const cha
 // ubar = i H(F) kbar (since (-iH)^H = iH for real symmetric H), the co-state
 // of c accumulates sum ubar, and the field gradient Im((D kbar)^H u) is
 // reduced per row tile (u = the forward input of the stage).
-template <int TM, int TN, int KC, bool ADJ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void bat_stage_kernel(BatBuffers b, BatLaunch L) {
+// KS = 2: the workgroup holds two groups of four waves, one per neighbour
+// block (the row use of D_m and the transposed use of D_{m-1}), each with its
+// own panels; the second group's accumulators are added to the first's in
+// LDS before the epilogue. For grids of few tiles (few pulses): twice the
+// waves per CU.
+template <int TM, int TN, int KC, bool ADJ, int KS>
+__global__ __launch_bounds__(256 * KS) __attribute__((amdgpu_waves_per_eu(1, 2))) void bat_stage_kernel(BatBuffers b, BatLaunch L) {
     using C = BatTile<TM, TN, KC>;
     static_assert(C::A_PER_W >= 1 && C::B_PER_W >= 1 && C::A_GROUPS % 4 == 0 && C::B_GROUPS % 4 == 0,
                   "panel groups must split evenly over the 4 waves");
@@ -150,10 +155,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     const int m = tile / (RT * CT), rem = tile - m * RT * CT, rt = rem / CT, ct = rem - rt * CT;
     const int r0 = rt * TM, c0 = ct * TN;
 
-    __shared__ __attribute__((aligned(16))) char lds_a[2][C::A_BYTES];
-    __shared__ __attribute__((aligned(16))) char lds_b[2][C::B_BYTES];
+    __shared__ __attribute__((aligned(16))) char lds_a[KS][2][C::A_BYTES];
+    __shared__ __attribute__((aligned(16))) char lds_b[KS][2][C::B_BYTES];
 
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int t = threadIdx.x % 256, lane = t & 63, wv = t >> 6;
+    const int kg = KS == 2 ? (int)(threadIdx.x >> 8) : 0;  // K group of this wave
     const int wy = wv >> 1, wx = wv & 1;
     const int par = L.parity;
     const double *U = par ? b.u[1] : b.u[0];
@@ -184,19 +190,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 #pragma unroll
         for (int j = 0; j < C::SN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
-    if (nchunks > 0) {
-        bat_chunk<TM, TN, KC>(nullptr, nullptr, lds_a[0], lds_b[0], a_src(0), b_src(0), Np, ldu, lane, wv, acc);
+    // Chunks [kbeg, kbeg + kcnt) of this wave's K group. With two groups a
+    // tile with both neighbours gives each group one; a tile with one gives
+    // it to group 0. Both groups pass the same niter barriers.
+    const bool both = has_up && has_dn;
+    const int kbeg = KS == 2 && both ? kg * kchunks : 0;
+    const int kcnt = KS == 1 ? nchunks : (both ? kchunks : (kg == 0 ? nchunks : 0));
+    const int niter = KS == 1 ? nchunks : (nchunks > 0 ? kchunks : 0);
+    char(*la)[C::A_BYTES] = lds_a[kg];
+    char(*lb)[C::B_BYTES] = lds_b[kg];
+    if (niter > 0) {
+        if (kcnt > 0)
+            bat_chunk<TM, TN, KC>(nullptr, nullptr, la[0], lb[0], a_src(kbeg), b_src(kbeg), Np, ldu, lane, wv, acc);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         bat_lds_barrier();
-        for (int kc = 0; kc < nchunks; ++kc) {
-            const int buf = kc & 1;
-            const bool next = kc + 1 < nchunks;
-            bat_chunk<TM, TN, KC>(lds_a[buf], lds_b[buf], next ? lds_a[buf ^ 1] : nullptr,
-                                  next ? lds_b[buf ^ 1] : nullptr, next ? a_src(kc + 1) : nullptr,
-                                  next ? b_src(kc + 1) : nullptr, Np, ldu, lane, wv, acc);
+        for (int q = 0; q < niter; ++q) {
+            if (q < kcnt) {
+                const int buf = q & 1;
+                const bool next = q + 1 < kcnt;
+                bat_chunk<TM, TN, KC>(la[buf], lb[buf], next ? la[buf ^ 1] : nullptr, next ? lb[buf ^ 1] : nullptr,
+                                      next ? a_src(kbeg + q + 1) : nullptr, next ? b_src(kbeg + q + 1) : nullptr, Np,
+                                      ldu, lane, wv, acc);
+            }
             // the next chunk's panels have landed and every wave is done with this one
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             bat_lds_barrier();
+        }
+    }
+    if constexpr (KS == 2) {
+        // group 1's accumulators onto group 0's (one addition per element)
+        __shared__ double kred[TM * TN];
+        if (kg == 1) {
+#pragma unroll
+            for (int i = 0; i < C::SM; ++i)
+#pragma unroll
+                for (int j = 0; j < C::SN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) kred[(((wv * C::SM + i) * C::SN + j) * 4 + r) * 64 + lane] = acc[i][j][r];
+        }
+        bat_lds_barrier();
+        if (kg == 0) {
+#pragma unroll
+            for (int i = 0; i < C::SM; ++i)
+#pragma unroll
+                for (int j = 0; j < C::SN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[i][j][r] += kred[(((wv * C::SM + i) * C::SN + j) * 4 + r) * 64 + lane];
         }
     }
 
@@ -208,8 +247,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
     double gsum[C::SN];
 #pragma unroll
     for (int j = 0; j < C::SN; ++j) gsum[j] = 0.0;
+    // (with two K groups, group 0 completes the stage; group 1 only passes
+    // the barriers below)
 #pragma unroll
-    for (int i = 0; i < C::SM; ++i) {
+    for (int i = 0; i < (kg == 0 ? C::SM : 0); ++i) {
 #pragma unroll
         for (int j = 0; j < C::SN; ++j) {
             const int col = c0 + wx * C::WN + j * 16 + (lane & 15);
@@ -331,10 +372,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
             g += __shfl_xor(g, 16);
             g += __shfl_xor(g, 32);
             g += bat_xor1(g);
-            if (lane < 16) gred[wy][wx * C::WN + j * 16 + lane] = g;
+            if (lane < 16 && kg == 0) gred[wy][wx * C::WN + j * 16 + lane] = g;
         }
         bat_lds_barrier();
-        if (t < TN / 2) {
+        if (t < TN / 2 && kg == 0) {
             const int pulse = c0 / 2 + t;
             if (pulse < B) L.gpart[(size_t)(m * RT + rt) * B + pulse] = gred[0][2 * t] + gred[1][2 * t];
         }
@@ -447,12 +488,19 @@ hipError_t bat_ckpt0(const BatBuffers &b, const double *c0, double *ckpt, int ro
 template <bool ADJ>
 static hipError_t bat_launch(const BatBuffers &b, const BatLaunch &l, hipStream_t s) {
     const int ntiles = (b.lmax + 1) * (b.np / b.tm) * (b.ldu / b.tn);
-    const dim3 g(ntiles), blk(256);
+    const dim3 g(ntiles), blk(256), blk2(512);
 #define TDSE_BAT(TM_, TN_, KC_)                                                                \
-    if (b.tm == TM_ && b.tn == TN_ && b.kc == KC_) {                                           \
-        hipLaunchKernelGGL((bat_stage_kernel<TM_, TN_, KC_, ADJ>), g, blk, 0, s, b, l);      \
+    if (b.tm == TM_ && b.tn == TN_ && b.kc == KC_ && b.ks == 1) {                              \
+        hipLaunchKernelGGL((bat_stage_kernel<TM_, TN_, KC_, ADJ, 1>), g, blk, 0, s, b, l);   \
         return hipGetLastError();                                                              \
     }
+#define TDSE_BAT2(TM_, TN_, KC_)                                                               \
+    if (b.tm == TM_ && b.tn == TN_ && b.kc == KC_ && b.ks == 2) {                              \
+        hipLaunchKernelGGL((bat_stage_kernel<TM_, TN_, KC_, ADJ, 2>), g, blk2, 0, s, b, l);  \
+        return hipGetLastError();                                                              \
+    }
+    TDSE_BAT2(32, 64, 32)
+    TDSE_BAT2(32, 32, 16)
     TDSE_BAT(128, 128, 16)
     TDSE_BAT(128, 64, 16)
     TDSE_BAT(64, 128, 16)
@@ -465,6 +513,7 @@ static hipError_t bat_launch(const BatBuffers &b, const BatLaunch &l, hipStream_
     TDSE_BAT(64, 64, 32)
     TDSE_BAT(32, 64, 32)
 #undef TDSE_BAT
+#undef TDSE_BAT2
     return hipErrorInvalidValue;
 }
 

@@ -222,7 +222,8 @@ static tdse_status vec_alloc(tdse_plan p) {
 // Tile shape for a batched plan: TN from the padded column count, TM the
 // largest of 128/64/32 that still gives >= 256 workgroups (one per CU).
 // TDSE_TILE="TMxTN" overrides (the autotuner writes the same choice).
-static void bat_pick_tile(int lmax, int n, int batch, const TileChoice *force, int *tm, int *tn, int *kc) {
+static void bat_pick_tile(int lmax, int n, int batch, const TileChoice *force, int *tm, int *tn, int *kc,
+                          int *ks) {
     // Default: 128 x 64 tiles where the grid still fills the chip (two
     // workgroups per CU measured fastest at Lmax=15, N=500, 256 pulses).
     const int ldu = ((2 * batch + 31) / 32) * 32;
@@ -239,12 +240,21 @@ static void bat_pick_tile(int lmax, int n, int batch, const TileChoice *force, i
         }
     }
     if (*tn != 64) *kc = 16;  // compiled K-chunk-32 shapes have TN = 64 or 128
-    TileChoice tc{0, *tm, *tn, *kc};
+    // such grids also get two K groups (eight waves) per workgroup
+    *ks = *kc == 32 || (*tm == 32 && *tn == 32) ? 2 : 1;
+    TileChoice tc{0, 0, 0, 0};
     if (force) tc = *force;
     else tune_lookup(lmax, n, batch, &tc);
+    if (tc.tm > 0 || tc.tn > 0 || tc.kc > 0) *ks = 1;  // a forced or tuned shape: one K group
     if (tc.tm > 0) *tm = tc.tm;
     if (tc.tn > 0) *tn = tc.tn;
     if (tc.kc > 0) *kc = tc.kc;
+    // two K groups exist for 32x64x32 and 32x32x16; $TDSE_KGROUPS=1/2 overrides
+    if (const char *kg = getenv("TDSE_KGROUPS")) {
+        if (kg[0] == '1') *ks = 1;
+        if (kg[0] == '2') *ks = 2;
+    }
+    if (!((*tm == 32 && *tn == 64 && *kc == 32) || (*tm == 32 && *tn == 32 && *kc == 16))) *ks = 1;
 }
 
 static tdse_status bat_create(tdse_plan p, const double *energies, const double *dipole,
@@ -254,7 +264,7 @@ static tdse_status bat_create(tdse_plan p, const double *energies, const double 
     b.lmax = p->lmax;
     b.n = p->n;
     b.batch = p->batch;
-    bat_pick_tile(p->lmax, p->n, p->batch, force, &b.tm, &b.tn, &b.kc);
+    bat_pick_tile(p->lmax, p->n, p->batch, force, &b.tm, &b.tn, &b.kc, &b.ks);
     b.np = ((p->n + b.tm - 1) / b.tm) * b.tm;
     b.ldu = ((2 * p->batch + b.tn - 1) / b.tn) * b.tn;
     const size_t ns_pad = (size_t)(p->lmax + 1) * b.np;

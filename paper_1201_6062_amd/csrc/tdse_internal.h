@@ -168,6 +168,7 @@ struct BatBuffers {
     double *kst;           // Runge-Kutta-Fehlberg: stage derivatives k_1..k_5, [5][(lmax+1)][np][ldu]
     const double *field;   // caller [batch][nsteps][S]
     int32_t lmax, n, np, ldu, batch, tm, tn, kc;
+    int32_t ks;            // K groups per workgroup (1, or 2: one per neighbour block)
     int32_t gauge;         // TDSE_LENGTH or TDSE_VELOCITY (d holds -Q_l in the velocity gauge)
 };
 
