@@ -145,8 +145,9 @@ tdse_status tdse_hmul(tdse_plan plan, const double *fields, const double *u, dou
  * The result is the discrete RK4 / Taylor map applied to the given samples.
  * Errors: TDSE_E_INVAL (null/misaligned/host pointers, dt <= 0 or not finite,
  * nsteps < 0, order out of range, ckpt_every < 1 with ckpt != NULL).
- * The Lanczos workspace ((m+1) state vectors per pulse) is allocated on
- * first use and kept by the plan (TDSE_E_NOMEM if it cannot be).
+ * The Lanczos workspace ((m+2) state vectors per pulse and the recurrence
+ * coefficients) is allocated on first use and kept by the plan
+ * (TDSE_E_NOMEM if it cannot be).
  */
 tdse_status tdse_propagate(tdse_plan plan, tdse_method method, int32_t taylor_order, double dt,
                            int64_t nsteps, const double *field, const double *c0, double *cT,

@@ -552,8 +552,10 @@ __global__ void bat_reduce_grad_kernel(const double *gpart, int rowtiles, int ba
                                        int64_t nsteps, int nprod, int rk4, double *grad) {
     const int64_t total = (int64_t)batch * len;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        const int pulse = (int)(g / len);
-        const int64_t kl = g % len;
+        // neighbouring threads take neighbouring pulses: the partials of one
+        // (step, product, row tile) are contiguous over the pulses
+        const int pulse = (int)(g % batch);
+        const int64_t kl = g / batch;
         double sj[TAYLOR_MAX_ORDER];
         for (int j = 0; j < nprod; ++j) {
             const double *p = gpart + ((size_t)(kl * nprod + j) * rowtiles) * batch + pulse;
