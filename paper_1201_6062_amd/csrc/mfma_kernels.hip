@@ -548,38 +548,52 @@ hipError_t bat_pack_strided(const BatBuffers &b, const double *src, size_t pulse
 // gpart layout for one segment: [step][product j][row tiles][batch]. RK4:
 // stage 1 -> slot 0, stages 2 and 3 -> slot 1, stage 4 -> slot 2; Taylor:
 // all terms of a step -> its one sample.
-__global__ void bat_reduce_grad_kernel(const double *gpart, int rowtiles, int batch, int64_t k0, int64_t len,
-                                       int64_t nsteps, int nprod, int rk4, double *grad) {
+// Field gradient of a segment from the per-row-tile partials: for every
+// (pulse, step) the sum over row tiles of each product's partial (in row-tile
+// order), then the stage weights of the map. A block takes 64 (pulse, step)
+// items; four threads share an item's products, neighbouring items are
+// neighbouring pulses (the partials of one product and row tile are
+// contiguous over the pulses).
+constexpr int GRAD_ITEMS = 64;
+__global__ __launch_bounds__(4 * GRAD_ITEMS) void bat_reduce_grad_kernel(const double *gpart, int rowtiles, int batch,
+                                                                          int64_t k0, int64_t len, int64_t nsteps,
+                                                                          int nprod, int rk4, double *grad) {
+    __shared__ double sj[GRAD_ITEMS][TAYLOR_MAX_ORDER];
+    const int t = threadIdx.x, it = t % GRAD_ITEMS, sub = t / GRAD_ITEMS;
     const int64_t total = (int64_t)batch * len;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
-        // neighbouring threads take neighbouring pulses: the partials of one
-        // (step, product, row tile) are contiguous over the pulses
-        const int pulse = (int)(g % batch);
-        const int64_t kl = g / batch;
-        double sj[TAYLOR_MAX_ORDER];
-        for (int j = 0; j < nprod; ++j) {
+    const int64_t g = (int64_t)blockIdx.x * GRAD_ITEMS + it;
+    const bool live = g < total;
+    const int pulse = live ? (int)(g % batch) : 0;
+    const int64_t kl = live ? g / batch : 0;
+    if (live) {
+        for (int j = sub; j < nprod; j += 4) {
             const double *p = gpart + ((size_t)(kl * nprod + j) * rowtiles) * batch + pulse;
             double acc = 0.0;
             for (int rt = 0; rt < rowtiles; ++rt) acc += p[(size_t)rt * batch];
-            sj[j] = acc;
+            sj[it][j] = acc;
         }
-        if (rk4) {
-            double *out = grad + ((size_t)pulse * nsteps + (k0 + kl)) * 3;
-            out[0] = sj[0];
-            out[1] = sj[2] + sj[1];
-            out[2] = sj[3];
-        } else {
-            double t = 0.0;
-            for (int j = nprod - 1; j >= 0; --j) t += sj[j];
-            grad[(size_t)pulse * nsteps + (k0 + kl)] = t;
-        }
+    }
+    __syncthreads();
+    if (!live || sub != 0) return;
+    if (rk4) {
+        double *out = grad + ((size_t)pulse * nsteps + (k0 + kl)) * 3;
+        out[0] = sj[it][0];
+        out[1] = sj[it][2] + sj[it][1];
+        out[2] = sj[it][3];
+    } else {
+        double tsum = 0.0;
+        for (int q = nprod - 1; q >= 0; --q) tsum += sj[it][q];
+        grad[(size_t)pulse * nsteps + (k0 + kl)] = tsum;
     }
 }
 
 hipError_t bat_reduce_grad(const double *gpart, int rowtiles, int batch, int64_t k0, int64_t len,
                            int64_t nsteps, int nprod, int rk4, double *grad, hipStream_t s) {
-    hipLaunchKernelGGL(bat_reduce_grad_kernel, dim3(64), dim3(256), 0, s, gpart, rowtiles, batch, k0, len, nsteps,
-                       nprod, rk4, grad);
+    const int64_t items = (int64_t)batch * len;
+    const int blocks = (int)((items + GRAD_ITEMS - 1) / GRAD_ITEMS);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(bat_reduce_grad_kernel, dim3(blocks), dim3(4 * GRAD_ITEMS), 0, s, gpart, rowtiles, batch, k0,
+                       len, nsteps, nprod, rk4, grad);
     return hipGetLastError();
 }
 
