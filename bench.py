@@ -281,6 +281,58 @@ def group_measure(torch, steps: int = 400):
             "state_steps_per_s": ss / s, "GBps": nbytes / s / 1e9, "frac_of_hbm_peak": nbytes / s / 1e9 / HBM_PEAK_GBS}
 
 
+def rkf45_measure(torch, batch: int = 256, steps: int = 50):
+    """256 pulses on the Lmax=15 N=500 Hamiltonian, Runge-Kutta-Fehlberg 4(5)
+    with per-step error estimates (six stages per step), dt=0.005."""
+    from paper_1201_6062_amd import workloads as wl
+    from paper_1201_6062_amd.api import Plan
+    h, dt = wl.hamiltonian(15, 500, 0), 0.005
+    plan = Plan(h.energies, h.dipole, batch=batch)
+    pulses = wl.random_pulses(np.random.default_rng(1), batch)
+    f = torch.as_tensor(np.stack([wl.rkf45_samples(p, dt, steps) for p in pulses]), device="cuda")
+    c0 = torch.as_tensor(wl.ground_state(15, 500, batch), device="cuda")
+    plan.propagate_rkf45(f[:, :2], c0, dt)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plan.propagate_rkf45(f, c0, dt)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3
+    flop_stage = 8.0 * h.lmax * h.n * h.n * batch
+    tf = flop_stage * 6 * steps / s / 1e12
+    plan.close()
+    return {"workload": f"{batch} pulses, Lmax=15 N=500, RKF 4(5) with error estimates, dt={dt}, {steps} steps",
+            "state_steps_per_s": h.nstates * batch * steps / s, "us_per_stage": s / (6 * steps) * 1e6,
+            "tflops": tf, "frac_of_fp64_peak": tf / FP64_PEAK_TFLOPS}
+
+
+def velocity_measure(torch, steps: int = 2048):
+    """The single-instance workload in the velocity gauge (coupling A(t) P,
+    P = -i Q): RK4 dt=0.005 on the first `steps` steps of the 20-cycle pulse."""
+    from paper_1201_6062_amd import workloads as wl
+    from paper_1201_6062_amd.api import Plan
+    h = wl.hamiltonian(15, 500, 0)
+    q = wl.velocity_coupling(h.energies, h.dipole)
+    plan = Plan(h.energies, q, gauge="velocity")
+    f = torch.as_tensor(wl.vector_potential_samples(wl.Pulse(0.05, 0.5, 20.0), 0.005, steps)[None], device="cuda")
+    c0 = torch.as_tensor(wl.ground_state(15, 500), device="cuda")
+    plan.propagate(f[:, :64], c0, 0.005, "rk4")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plan.propagate(f, c0, 0.005, "rk4")
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3
+    per = s / (4 * steps)
+    bpp = algorithmic_bytes_per_product(15, 500)
+    plan.close()
+    return {"workload": f"Lmax=15 N=500 velocity gauge, RK4 dt=0.005, first {steps} steps",
+            "state_steps_per_s": h.nstates * steps / s, "us_per_product": per * 1e6,
+            "GBps": bpp / per / 1e9, "frac_of_hbm_peak": bpp / per / 1e9 / HBM_PEAK_GBS}
+
+
 def adjoint_measure(torch, steps: int = 2048):
     """The adjoint workload (32 pulses of piecewise-constant samples on the
     Lmax=15 N=500 Hamiltonian, RK4 dt=0.01, checkpoints every 64 steps), first
@@ -341,7 +393,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the small-problem and group measurements")
     ap.add_argument("--only", choices=["single", "diag", "batched", "small", "small_tiles", "group", "taylor8",
-                                       "lanczos", "lsweep", "adjoint"], default=None,
+                                       "lanczos", "lsweep", "adjoint", "rkf45", "velocity"], default=None,
                     help="profiling runs: measure one workload and print its record alone")
     ap.add_argument("--tile", default=None, help="batched tile TMxTN (tuning experiments)")
     ap.add_argument("--method", choices=["rk4", "taylor"], default="rk4")
@@ -370,7 +422,9 @@ def main():
             "taylor8": lambda: taylor8_measure(torch),
             "lanczos": lambda: lanczos_measure(torch),
             "lsweep": lambda: lmax_sweep(torch),
-            "adjoint": lambda: adjoint_measure(torch, steps=a.truncate or 2048)}
+            "adjoint": lambda: adjoint_measure(torch, steps=a.truncate or 2048),
+            "rkf45": lambda: rkf45_measure(torch, steps=a.truncate or 50),
+            "velocity": lambda: velocity_measure(torch)}
     if a.only in only:
         print(json.dumps(only[a.only]()))
         return
@@ -436,6 +490,8 @@ def main():
         out["single_taylor8"] = taylor8_measure(torch)
         out["lanczos"] = lanczos_measure(torch)
         out["adjoint"] = adjoint_measure(torch)
+        out["rkf45"] = rkf45_measure(torch)
+        out["velocity_gauge"] = velocity_measure(torch)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
