@@ -30,7 +30,8 @@ def samples(batch, dt, nsteps, gauge="length"):
 
 
 @pytest.mark.parametrize("lmax,n,batch,m,nsteps", [(2, 130, 1, 8, 30), (3, 50, 1, 12, 25), (1, 7, 1, 1, 40),
-                                                  (2, 70, 3, 6, 20), (3, 257, 2, 10, 12), (0, 9, 2, 4, 15)])
+                                                  (2, 70, 3, 6, 20), (3, 257, 2, 10, 12), (0, 9, 2, 4, 15),
+                                                  (2, 70, 1, 64, 8), (1, 40, 2, 64, 6)])
 def test_lanczos_matches_oracle(lmax, n, batch, m, nsteps):
     h = wl.hamiltonian(lmax, n, 2)
     dt = 0.05

@@ -65,7 +65,7 @@ def test_batched_rk4(lmax, n, batch, nsteps):
     assert rel_l2(got, ref) <= TOL
 
 
-@pytest.mark.parametrize("order", [1, 3, 8])
+@pytest.mark.parametrize("order", [1, 3, 8, 32])
 def test_batched_taylor(order):
     h = wl.hamiltonian(3, 70, 5)
     dt, nsteps, batch = 0.02, 25, 6

@@ -107,7 +107,7 @@ def test_block_size_beyond_limit_is_rejected(torch_dev):
         Plan(np.linspace(-0.5, 1.0, 2 * n), np.zeros((1, n, n)))
 
 
-@pytest.mark.parametrize("order", [1, 2, 4, 8, 10])
+@pytest.mark.parametrize("order", [1, 2, 4, 8, 10, 32])
 @pytest.mark.parametrize("lmax,n,nsteps", [(2, 3, 70), (3, 130, 66), (0, 5, 64)])
 def test_taylor_parity(torch_dev, order, lmax, n, nsteps, path, monkeypatch):
     apply_path(path, monkeypatch, n)
