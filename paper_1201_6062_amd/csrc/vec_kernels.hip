@@ -50,17 +50,12 @@ __device__ __forceinline__ double2 ld2(const double2 *p) {
 __device__ __forceinline__ void st2(double2 *p, double2 v) {
     *reinterpret_cast<dv2_t *>(p) = dv2_t{v.x, v.y};
 }
-// Store through a pointer that was itself loaded from memory: spelled as a
+// Store through a pointer the compiler cannot trace to a kernel argument
+// (one loaded from memory, or held in registers with pin_sgpr): spelled as a
 // global-address-space store (a generic/flat store would also count against
 // the LDS counter and force waits on the tile stream).
 typedef __attribute__((address_space(1))) dv2_t gdv2_t;
 __device__ __forceinline__ void st_global(double2 *p, double2 v) {
-    dv2_t w = {v.x, v.y};
-    *(gdv2_t *)(p) = w;
-}
-// The same through a pointer the compiler cannot trace to a kernel argument
-// (one held in registers with pin_sgpr), spelled as a global store.
-__device__ __forceinline__ void st2_global(double2 *p, double2 v) {
     dv2_t w = {v.x, v.y};
     *(gdv2_t *)(p) = w;
 }
@@ -320,7 +315,7 @@ __device__ __forceinline__ void tile_products(const VecBuffers &b, TileLds &lds,
 #pragma unroll
             for (int k = 1; k < 16; ++k) s = cadd(s, lds.cbuf[t][k]);
             double2 *cpo = colp_out + ((size_t)(l * T + j) * T + i) * VEC_TILE_MAX;
-            st2_global(cpo + t, s);
+            st_global(cpo + t, s);
         }
     } else if (t < 2 * VEC_TILE_MAX) {  // row partial of row a: sum over the 8 waves' columns
         const int a = t - VEC_TILE_MAX;
@@ -329,7 +324,7 @@ __device__ __forceinline__ void tile_products(const VecBuffers &b, TileLds &lds,
 #pragma unroll
             for (int k = 1; k < VEC_THREADS / 64; ++k) s = cadd(s, lds.rbuf[k][a]);
             double2 *rp = rowp_out + ((size_t)(l * T + i) * T + j) * VEC_TILE_MAX;
-            st2_global(rp + a, s);
+            st_global(rp + a, s);
         }
     }
 }
