@@ -8,10 +8,11 @@
 // the recurrence, the small exponential and the recombination. Vectors are in
 // the caller layout [pulse][2 n] (interleaved complex). With several pulses
 // the recurrence runs in one workgroup per pulse; a single pulse spreads it
-// over many workgroups (alpha from the product launch's per-segment dots,
-// then an update and a normalisation launch). Every reduction has a fixed
-// order.
+// over many workgroups: alpha from the completion launch's per-segment dots,
+// then one update launch per product, each Krylov vector normalised inside
+// its own product's completion launch. Every reduction has a fixed order.
 #include "tdse_internal.h"
+#include "tdse_reduce.h"
 
 namespace tdse {
 
@@ -150,82 +151,99 @@ __global__ void lz_ckpt0_kernel(const double *c0, double *ckpt, int batch, int64
 }
 
 // One pulse over many workgroups (a single workgroup would stream the
-// vectors through one CU). Reductions: every workgroup reduces the same
-// partial array in the same tree order, so all of them hold the same sum.
+// vectors through one CU). Each Krylov vector is formed unnormalised with
+// per-workgroup parts of its squared norm; its product launch reads it as is
+// and the completion launch after it (vec_hmul_dot_kernel) sums the parts,
+// normalises the vector in place and scales the product. Every workgroup that
+// needs a sum reduces the same parts in the same order (block_sum_array), so
+// all of them hold the same value.
 constexpr int LZ_WIDE_THREADS = 256;
 
-// Sum of p[0 .. count) in a fixed tree order (same in every workgroup).
-__device__ __forceinline__ double lz_tree_sum(const double *p, int count, double *red) {
-    const int t = threadIdx.x;
-    double v = 0.0;
-    for (int k = t; k < count; k += LZ_WIDE_THREADS) v += p[k];
-    red[t] = v;
-    __syncthreads();
-    for (int h = LZ_WIDE_THREADS / 2; h > 0; h >>= 1) {
-        if (t < h) red[t] += red[t + h];
-        __syncthreads();
+// x_0 = c; normp[workgroup] = this workgroup's part of |c|^2.
+__global__ __launch_bounds__(LZ_WIDE_THREADS) void lz_begin_wide_kernel(const double2 *c, double2 *x0,
+                                                                        double *normp, int64_t ncplx) {
+    __shared__ double red[LZ_WIDE_THREADS / 64];
+    double s2 = 0.0;
+    for (int64_t g = (int64_t)blockIdx.x * LZ_WIDE_THREADS + threadIdx.x; g < ncplx;
+         g += (int64_t)gridDim.x * LZ_WIDE_THREADS) {
+        const double2 x = c[g];
+        x0[g] = x;
+        s2 = fma(x.x, x.x, fma(x.y, x.y, s2));
     }
-    const double r = red[0];
-    __syncthreads();
-    return r;
+    const double part = block_sum<LZ_WIDE_THREADS>(s2, red);
+    if (threadIdx.x == 0) normp[blockIdx.x] = part;
 }
 
-// alpha_j = sum of the per-segment parts of Re <v_j, w>; unless last,
-// w <- w - alpha_j v_j - beta_{j-1} v_{j-1} and this workgroup's part of |w|^2
-// to normp[workgroup]. Workgroup 0 stores alpha_j.
-__global__ __launch_bounds__(LZ_WIDE_THREADS) void lz_update_kernel(const double *dotp, int nseg, const double *vj,
-                                                                    const double *vjm1, double *w, double *alpha,
+// alpha_j = sum of the per-segment parts of Re <v_j, w> (w = H v_j); unless
+// last, xnext = w - alpha_j v_j - beta_{j-1} v_{j-1} and this workgroup's
+// part of |xnext|^2 to normp[workgroup]. Workgroup 0 stores alpha_j. The
+// first element's operands are loaded before the alpha reduction.
+__global__ __launch_bounds__(LZ_WIDE_THREADS) void lz_update_kernel(const double *dotp, int nseg, const double2 *vj,
+                                                                    const double2 *vjm1, const double2 *w,
+                                                                    double2 *xnext, double *alpha,
                                                                     const double *beta, int j, int last,
                                                                     double *normp, int64_t ncplx) {
-    __shared__ double red[LZ_WIDE_THREADS];
-    const double a = lz_tree_sum(dotp, nseg, red);
+    __shared__ double red[LZ_WIDE_THREADS / 64];
+    int64_t g = (int64_t)blockIdx.x * LZ_WIDE_THREADS + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * LZ_WIDE_THREADS;
+    const double2 zero = make_double2(0.0, 0.0);
+    double2 x = zero, v = zero, pv = zero;
+    if (!last && g < ncplx) {
+        x = w[g];
+        v = vj[g];
+        if (j > 0) pv = vjm1[g];
+    }
+    const double a = block_sum_array<LZ_WIDE_THREADS>(dotp, nseg, red);
     if (blockIdx.x == 0 && threadIdx.x == 0) alpha[j] = a;
     if (last) return;
     const double bprev = j > 0 ? beta[j - 1] : 0.0;
     double s2 = 0.0;
-    const double2 *v2 = reinterpret_cast<const double2 *>(vj), *p2 = reinterpret_cast<const double2 *>(vjm1);
-    double2 *w2 = reinterpret_cast<double2 *>(w);
-    for (int64_t g = (int64_t)blockIdx.x * LZ_WIDE_THREADS + threadIdx.x; g < ncplx;
-         g += (int64_t)gridDim.x * LZ_WIDE_THREADS) {
-        double2 x = w2[g];
-        const double2 v = v2[g];
+    while (g < ncplx) {
         x.x -= a * v.x;
         x.y -= a * v.y;
         if (j > 0) {
-            const double2 pv = p2[g];
             x.x -= bprev * pv.x;
             x.y -= bprev * pv.y;
         }
-        w2[g] = x;
+        xnext[g] = x;
         s2 = fma(x.x, x.x, fma(x.y, x.y, s2));
+        g += stride;
+        if (g < ncplx) {
+            x = w[g];
+            v = vj[g];
+            if (j > 0) pv = vjm1[g];
+        }
     }
-    red[threadIdx.x] = s2;
-    __syncthreads();
-    for (int h = LZ_WIDE_THREADS / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) normp[blockIdx.x] = red[0];
+    const double part = block_sum<LZ_WIDE_THREADS>(s2, red);
+    if (threadIdx.x == 0) normp[blockIdx.x] = part;
 }
 
-// beta_j = |w| (with the breakdown rule of lz_orth_kernel), v_{j+1} = w / beta_j.
-__global__ __launch_bounds__(LZ_WIDE_THREADS) void lz_normalize_kernel(const double *normp, int nparts,
-                                                                       const double *w, double *vnext,
-                                                                       const double *alpha, double *beta, int j,
-                                                                       int64_t ncplx) {
-    __shared__ double red[LZ_WIDE_THREADS];
-    double bj = sqrt(lz_tree_sum(normp, nparts, red));
-    const double bprev = j > 0 ? beta[j - 1] : 0.0;
-    if (bj <= 1e-13 * (fabs(alpha[j]) + bprev)) bj = 0.0;
-    const double inv = bj > 0.0 ? 1.0 / bj : 0.0;
-    const double2 *w2 = reinterpret_cast<const double2 *>(w);
-    double2 *v2 = reinterpret_cast<double2 *>(vnext);
+// c = sum_j y_j v_j (as lz_combine_kernel, one pulse), the checkpoint row if
+// one is due, x_0 = c over v_0 (each thread reads its entries of every v_j
+// before it writes that entry of v_0) and the norm parts of x_0.
+__global__ __launch_bounds__(LZ_WIDE_THREADS) void lz_combine_wide_kernel(double2 *V, int64_t vstride2,
+                                                                          const double2 *y, int m, int64_t ncplx,
+                                                                          double2 *c, double2 *ckpt,
+                                                                          double *normp) {
+    __shared__ double red[LZ_WIDE_THREADS / 64];
+    double s2 = 0.0;
     for (int64_t g = (int64_t)blockIdx.x * LZ_WIDE_THREADS + threadIdx.x; g < ncplx;
          g += (int64_t)gridDim.x * LZ_WIDE_THREADS) {
-        const double2 x = w2[g];
-        v2[g] = make_double2(x.x * inv, x.y * inv);
+        double sr = 0.0, si = 0.0;
+        for (int j = 0; j < m; ++j) {
+            const double2 yj = y[j];
+            const double2 v = V[(size_t)j * vstride2 + g];
+            sr = fma(yj.x, v.x, fma(-yj.y, v.y, sr));
+            si = fma(yj.x, v.y, fma(yj.y, v.x, si));
+        }
+        const double2 r = make_double2(sr, si);
+        c[g] = r;
+        if (ckpt) ckpt[g] = r;
+        V[g] = r;
+        s2 = fma(sr, sr, fma(si, si, s2));
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) beta[j] = bj;
+    const double part = block_sum<LZ_WIDE_THREADS>(s2, red);
+    if (threadIdx.x == 0) normp[blockIdx.x] = part;
 }
 
 int lz_wide_groups(int64_t ncplx) {
@@ -233,17 +251,28 @@ int lz_wide_groups(int64_t ncplx) {
     return (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
 }
 
-hipError_t lz_update(const double *dotp, int nseg, const double *vj, const double *vjm1, double *w, double *alpha,
-                     const double *beta, int j, int last, double *normp, int64_t ncplx, hipStream_t s) {
-    hipLaunchKernelGGL(lz_update_kernel, dim3(last ? 1 : lz_wide_groups(ncplx)), dim3(LZ_WIDE_THREADS), 0, s, dotp,
-                       nseg, vj, vjm1, w, alpha, beta, j, last, normp, ncplx);
+hipError_t lz_begin_wide(const double *c, double *x0, double *normp, int64_t ncplx, hipStream_t s) {
+    hipLaunchKernelGGL(lz_begin_wide_kernel, dim3(lz_wide_groups(ncplx)), dim3(LZ_WIDE_THREADS), 0, s,
+                       reinterpret_cast<const double2 *>(c), reinterpret_cast<double2 *>(x0), normp, ncplx);
     return hipGetLastError();
 }
-hipError_t lz_normalize(const double *normp, const double *w, double *vnext, const double *alpha, double *beta,
-                        int j, int64_t ncplx, hipStream_t s) {
-    const int g = lz_wide_groups(ncplx);
-    hipLaunchKernelGGL(lz_normalize_kernel, dim3(g), dim3(LZ_WIDE_THREADS), 0, s, normp, g, w, vnext, alpha, beta, j,
-                       ncplx);
+
+hipError_t lz_update(const double *dotp, int nseg, const double *vj, const double *vjm1, const double *w,
+                     double *xnext, double *alpha, const double *beta, int j, int last, double *normp,
+                     int64_t ncplx, hipStream_t s) {
+    hipLaunchKernelGGL(lz_update_kernel, dim3(last ? 1 : lz_wide_groups(ncplx)), dim3(LZ_WIDE_THREADS), 0, s, dotp,
+                       nseg, reinterpret_cast<const double2 *>(vj), reinterpret_cast<const double2 *>(vjm1),
+                       reinterpret_cast<const double2 *>(w), reinterpret_cast<double2 *>(xnext), alpha, beta, j,
+                       last, normp, ncplx);
+    return hipGetLastError();
+}
+
+hipError_t lz_combine_wide(double *V, const double *y, int m, int64_t ncplx, double *c, double *ckpt,
+                           int64_t ckpt_row, double *normp, hipStream_t s) {
+    hipLaunchKernelGGL(lz_combine_wide_kernel, dim3(lz_wide_groups(ncplx)), dim3(LZ_WIDE_THREADS), 0, s,
+                       reinterpret_cast<double2 *>(V), ncplx, reinterpret_cast<const double2 *>(y), m, ncplx,
+                       reinterpret_cast<double2 *>(c),
+                       ckpt ? reinterpret_cast<double2 *>(ckpt) + (size_t)ckpt_row * ncplx : nullptr, normp);
     return hipGetLastError();
 }
 

@@ -393,7 +393,7 @@ static tdse_status bat_hmul(tdse_plan p, const double *fields, const double *u, 
 // y = H(field[., k]) u for the plan's pulses (caller layout). Single-vector
 // plans read the sample from the chunk staged at `base` by chunk_begin.
 static hipError_t lz_product(tdse_plan p, const double *field, int64_t nsteps, int64_t k, int64_t base,
-                             const double *u, double *y, double *dotp, hipStream_t s) {
+                             const double *u, double *y, double *dotp, const LzNorm *nz, hipStream_t s) {
     hipError_t e;
     if (p->batch > 1) {
         BatBuffers b = p->bb;
@@ -412,7 +412,8 @@ static hipError_t lz_product(tdse_plan p, const double *field, int64_t nsteps, i
     // The Krylov vector itself is the product input: the products launch of
     // the split path reads u from the parity-0 state buffers, which this
     // launch's copy of the buffers points at u; the completion launch then
-    // forms y = E o u + F z from the partials and u.
+    // forms y = E o u + F z from the partials and u (with nz: u is the
+    // unnormalised x_j, which that launch normalises in place).
     VecBuffers vb = p->vb;
     vb.side[0].st[2] = reinterpret_cast<double2 *>(const_cast<double *>(u));
     if (p->lmax > 0) {
@@ -427,7 +428,7 @@ static hipError_t lz_product(tdse_plan p, const double *field, int64_t nsteps, i
     H.slots = 1;
     H.off = (int32_t)(k - base);
     H.out = y;
-    return dotp ? vec_launch_hmul_dot(vb, H, dotp, s) : vec_launch_combine(vb, H, s);
+    return nz ? vec_launch_hmul_dot(vb, H, dotp, *nz, s) : vec_launch_combine(vb, H, s);
 }
 
 // The steps of short-iterative Lanczos from k0 (k0 - base: offset in the
@@ -447,26 +448,40 @@ static hipError_t lz_enqueue_steps(tdse_plan p, const LzWork &w, int m, double d
     const int B = p->batch;
     hipError_t e = hipSuccess;
     for (int64_t k = k0; k < k0 + count && e == hipSuccess; ++k) {
+        const bool row = ckpt && (k + 1) % K == 0;
+        if (B == 1) {  // the recurrence spread over many workgroups
+            // x_0 = c with its norm parts; after the first step the previous
+            // step's recombination has left both
+            if (k == k0) e = lz_begin_wide(c, w.V, w.normp, w.ncplx, s);
+            const int nseg = (p->lmax + 1) * p->T;
+            for (int j = 0; j < m && e == hipSuccess; ++j) {
+                double *vj = w.V + (size_t)j * w.vstride;
+                const bool last = j + 1 == m;
+                const LzNorm nz{w.normp, lz_wide_groups(w.ncplx), j, w.beta0, w.alpha, w.beta};
+                e = lz_product(p, field, nsteps, k, base, vj, w.W, w.dotp, &nz, s);
+                if (e == hipSuccess)
+                    e = lz_update(w.dotp, nseg, vj, j > 0 ? vj - w.vstride : nullptr, w.W,
+                                  last ? nullptr : vj + w.vstride, w.alpha, w.beta, j, last ? 1 : 0, w.normp,
+                                  w.ncplx, s);
+            }
+            if (e == hipSuccess) e = lz_expm(w.alpha, w.beta, w.beta0, dt, dt_dev, m, B, w.y, s);
+            if (e == hipSuccess)
+                e = lz_combine_wide(w.V, w.y, m, w.ncplx, c, row ? ckpt : nullptr, row ? (k + 1) / K : 0, w.normp,
+                                    s);
+            continue;
+        }
+        // one workgroup per pulse
         e = lz_begin(c, w.V, w.beta0, B, w.len, s);
         for (int j = 0; j < m && e == hipSuccess; ++j) {
             const double *vj = w.V + (size_t)j * w.vstride;
             const bool last = j + 1 == m;
             double *vnext = last ? nullptr : w.V + (size_t)(j + 1) * w.vstride;
-            if (B == 1) {  // the recurrence spread over many workgroups
-                e = lz_product(p, field, nsteps, k, base, vj, w.W, w.dotp, s);
-                if (e == hipSuccess)
-                    e = lz_update(w.dotp, (p->lmax + 1) * p->T, vj, j > 0 ? vj - w.vstride : nullptr, w.W, w.alpha,
-                                  w.beta, j, last ? 1 : 0, w.normp, w.ncplx, s);
-                if (e == hipSuccess && !last) e = lz_normalize(w.normp, w.W, vnext, w.alpha, w.beta, j, w.ncplx, s);
-            } else {       // one workgroup per pulse
-                e = lz_product(p, field, nsteps, k, base, vj, w.W, nullptr, s);
-                if (e == hipSuccess)
-                    e = lz_orth(vj, j > 0 ? vj - w.vstride : nullptr, w.W, vnext, w.alpha, w.beta, j, m, last ? 1 : 0,
-                                B, w.len, s);
-            }
+            e = lz_product(p, field, nsteps, k, base, vj, w.W, nullptr, nullptr, s);
+            if (e == hipSuccess)
+                e = lz_orth(vj, j > 0 ? vj - w.vstride : nullptr, w.W, vnext, w.alpha, w.beta, j, m, last ? 1 : 0,
+                            B, w.len, s);
         }
         if (e == hipSuccess) e = lz_expm(w.alpha, w.beta, w.beta0, dt, dt_dev, m, B, w.y, s);
-        const bool row = ckpt && (k + 1) % K == 0;
         if (e == hipSuccess)
             e = lz_combine(w.V, w.vstride, w.y, m, B, w.ncplx, c, row ? ckpt : nullptr, rows, row ? (k + 1) / K : 0, s);
     }

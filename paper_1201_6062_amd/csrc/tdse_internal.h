@@ -209,21 +209,42 @@ hipError_t bat_launch_stage(const BatBuffers &b, const BatLaunch &l, hipStream_t
 hipError_t lz_begin(const double *c, double *v1, double *beta0, int batch, int64_t len, hipStream_t s);
 hipError_t lz_orth(const double *vj, const double *vjm1, double *w, double *vnext, double *alpha, double *beta,
                    int j, int m, int last, int batch, int64_t len, hipStream_t s);
-// One pulse over many workgroups: alpha_j from per-segment partial dots,
-// the recurrence update with per-workgroup partial norms, then beta_j and
-// v_{j+1}. lz_wide_groups: the workgroup count (normp holds that many).
+// One pulse over many workgroups. The Krylov vectors are formed unnormalised
+// (x_0 = c, x_{j+1} = H v_j - alpha_j v_j - beta_{j-1} v_{j-1}), each launch
+// that forms one leaving per-workgroup parts of |x|^2 in normp; the product
+// launch of x_j reads it as is, and the completion (vec_launch_hmul_dot)
+// takes the norm from the parts, stores beta (beta0 for j = 0), v_j = x_j /
+// beta in place and y = H v_j, with the per-segment parts of Re <v_j, y> in
+// dotp. lz_wide_groups: the workgroup count of the launches that leave norm
+// parts (normp holds that many).
 int lz_wide_groups(int64_t ncplx);
-hipError_t lz_update(const double *dotp, int nseg, const double *vj, const double *vjm1, double *w, double *alpha,
-                     const double *beta, int j, int last, double *normp, int64_t ncplx, hipStream_t s);
-hipError_t lz_normalize(const double *normp, const double *w, double *vnext, const double *alpha, double *beta,
-                        int j, int64_t ncplx, hipStream_t s);
-// y = H u with the per-segment parts of Re <u, y> in dotp[(lmax+1) T]
-hipError_t vec_launch_hmul_dot(const VecBuffers &b, const VecLaunch &l, double *dotp, hipStream_t s);
+// x_0 = c and its norm parts
+hipError_t lz_begin_wide(const double *c, double *x0, double *normp, int64_t ncplx, hipStream_t s);
+// alpha_j from dotp; unless last, xnext = w - alpha_j v_j - beta_{j-1} v_{j-1}
+// and its norm parts
+hipError_t lz_update(const double *dotp, int nseg, const double *vj, const double *vjm1, const double *w,
+                     double *xnext, double *alpha, const double *beta, int j, int last, double *normp,
+                     int64_t ncplx, hipStream_t s);
+// Normalisation of Krylov vector j inside its completion launch.
+struct LzNorm {
+    const double *normp;  // parts of |x_j|^2
+    int32_t nparts;
+    int32_t j;
+    double *beta0;        // j == 0: receives |x_0|
+    const double *alpha;  // alpha_{j-1} (breakdown test)
+    double *beta;         // j > 0: receives beta_{j-1} = |x_j| (0 on breakdown)
+};
+hipError_t vec_launch_hmul_dot(const VecBuffers &b, const VecLaunch &l, double *dotp, const LzNorm &nz,
+                               hipStream_t s);
 // dt_dev: if not null, dt is read from there at run time (captured steps)
 hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0, double dt, const double *dt_dev,
                    int m, int batch, double *y, hipStream_t s);
 hipError_t lz_combine(const double *V, size_t vstride, const double *y, int m, int batch, int64_t ncplx, double *c,
                       double *ckpt, int64_t ckpt_rows, int64_t ckpt_row, hipStream_t s);
+// One pulse: c = sum_j y_j v_j as lz_combine, also x0 = c (the next step's
+// first Krylov vector, in place over v_0) and its norm parts.
+hipError_t lz_combine_wide(double *V, const double *y, int m, int64_t ncplx, double *c, double *ckpt,
+                           int64_t ckpt_row, double *normp, hipStream_t s);
 hipError_t lz_ckpt0(const double *c0, double *ckpt, int batch, int64_t len, int64_t rows, hipStream_t s);
 
 // ---------------------------------------------------------------------------

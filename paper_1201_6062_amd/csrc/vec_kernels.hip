@@ -20,6 +20,7 @@
 // XCD (workgroups are dispatched round-robin over the 8 XCDs) and each XCD
 // works on a contiguous range of tiles.
 #include "tdse_internal.h"
+#include "tdse_reduce.h"
 
 namespace tdse {
 
@@ -585,12 +586,16 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_combine_kernel(VecBuffers b,
     if (L.finish) reinterpret_cast<double2 *>(L.out)[gi] = c;
 }
 
-// y = E o u + F z (the single product, as CK_HMUL of vec_combine_kernel)
-// together with this segment's part of Re <u, y>, summed over the segment in
-// a fixed tree order: dotp[segment]. For the Lanczos recurrence.
+// Completion of the product of Krylov vector j (one pulse): the norm of the
+// unnormalised x_j from the parts its forming launch left, beta (with the
+// recurrence's breakdown rule: beta_{j-1} <= 1e-13 (|alpha_{j-1}| +
+// beta_{j-2}) counts as zero), v_j = x_j / beta in place, y = H v_j = (E o x_j
+// + F D x_j) / beta, and this segment's part of Re <v_j, y>, summed over the
+// segment in a fixed order: dotp[segment].
 template <int TP>
-__global__ __launch_bounds__(VEC_TILE_MAX) void vec_hmul_dot_kernel(VecBuffers b, VecLaunch L, double *dotp) {
-    __shared__ double red[VEC_TILE_MAX];
+__global__ __launch_bounds__(VEC_TILE_MAX) void vec_hmul_dot_kernel(VecBuffers b, VecLaunch L, double *dotp,
+                                                                    LzNorm nz) {
+    __shared__ double red[VEC_TILE_MAX / 64];
     const int T = TP <= 8 ? TP : b.T;
     const int seg = blockIdx.x;
     const int m = seg / T, q = seg - m * T;
@@ -598,26 +603,38 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_hmul_dot_kernel(VecBuffers b
     const int e = threadIdx.x;
     const int par = L.parity;
     const double F = field_of(b.desc, L);
-    double dot = 0.0;
-    if (e < len) {
-        const size_t gi = (size_t)m * b.n + s0 + e;
-        double2 z = make_double2(0.0, 0.0);
+    const bool live = e < len;
+    const size_t gi = (size_t)m * b.n + s0 + (live ? e : 0);
+    double2 *up = st_ptr(b, par, 2) + gi;
+    double2 z = make_double2(0.0, 0.0), x = make_double2(0.0, 0.0);
+    double E0 = 0.0;
+    if (live) {
         if (b.lmax > 0)
             z = couple(b.gauge, sum_partials<TP>(b, T, par, true, m, q, e),
                        sum_partials<TP>(b, T, par, false, m, q, e));
-        const double2 u = ld2(st_ptr(b, par, 2) + gi);
-        const double E0 = b.en[gi];
-        const double yr = fma(F, z.x, E0 * u.x), yi = fma(F, z.y, E0 * u.y);
+        x = ld2(up);
+        E0 = b.en[gi];
+    }
+    double bj = sqrt(block_sum_array<VEC_TILE_MAX>(nz.normp, nz.nparts, red));
+    if (nz.j > 0) {
+        const double bprev = nz.j > 1 ? nz.beta[nz.j - 2] : 0.0;
+        if (bj <= 1e-13 * (fabs(nz.alpha[nz.j - 1]) + bprev)) bj = 0.0;
+    }
+    const double inv = bj > 0.0 ? 1.0 / bj : 0.0;
+    if (seg == 0 && e == 0) {
+        if (nz.j == 0) *nz.beta0 = bj;
+        else nz.beta[nz.j - 1] = bj;
+    }
+    double dot = 0.0;
+    if (live) {
+        const double2 v = make_double2(x.x * inv, x.y * inv);
+        const double yr = fma(F, z.x * inv, E0 * v.x), yi = fma(F, z.y * inv, E0 * v.y);
+        st2(up, v);
         reinterpret_cast<double2 *>(L.out)[gi] = make_double2(yr, yi);
-        dot = fma(u.x, yr, u.y * yi);
+        dot = fma(v.x, yr, v.y * yi);
     }
-    red[e] = dot;
-    __syncthreads();
-    for (int h = VEC_TILE_MAX / 2; h > 0; h >>= 1) {
-        if (e < h) red[e] += red[e + h];
-        __syncthreads();
-    }
-    if (e == 0) dotp[seg] = red[0];
+    const double part = block_sum<VEC_TILE_MAX>(dot, red);
+    if (e == 0) dotp[seg] = part;
 }
 
 __global__ void vec_start_kernel(VecBuffers b, int par, const double2 *c0, int taylor) {
@@ -785,8 +802,9 @@ hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream
     TDSE_TP_DISPATCH(b.T, vec_combine_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s, b, l);
     return hipGetLastError();
 }
-hipError_t vec_launch_hmul_dot(const VecBuffers &b, const VecLaunch &l, double *dotp, hipStream_t s) {
-    TDSE_TP_DISPATCH(b.T, vec_hmul_dot_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s, b, l, dotp);
+hipError_t vec_launch_hmul_dot(const VecBuffers &b, const VecLaunch &l, double *dotp, const LzNorm &nz,
+                               hipStream_t s) {
+    TDSE_TP_DISPATCH(b.T, vec_hmul_dot_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s, b, l, dotp, nz);
     return hipGetLastError();
 }
 hipError_t vec_launch_products(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {

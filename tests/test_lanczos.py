@@ -85,9 +85,10 @@ def test_lanczos_full_size_short():
             assert rel_l2(got[b:b + 1], ref) <= TOL, batch
 
 
-def test_lanczos_checkpoints_and_alias():
+@pytest.mark.parametrize("batch", [1, 2])
+def test_lanczos_checkpoints_and_alias(batch):
     h = wl.hamiltonian(2, 40, 6)
-    dt, nsteps, m, k, batch = 0.05, 23, 8, 5, 2
+    dt, nsteps, m, k = 0.05, 23, 8, 5
     f = samples(batch, dt, nsteps)
     c0 = wl.random_state(np.random.default_rng(9), h.nstates, batch)
     plan = make_plan(h.energies, h.dipole, batch)
