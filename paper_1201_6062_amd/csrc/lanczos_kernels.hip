@@ -83,11 +83,18 @@ __global__ __launch_bounds__(LZ_THREADS) void lz_orth_kernel(const double *vj, c
 // over s sub-steps, s chosen so that dt |T| / s <= 1/2 (|T| bounded by its
 // largest Gershgorin row sum): truncation below 1e-17 per sub-step.
 __global__ __launch_bounds__(64) void lz_expm_kernel(const double *alpha, const double *beta, const double *beta0,
-                                                     double dt_arg, const double *dt_dev, int m, double2 *y) {
+                                                     double dt_arg, const double *dt_dev, int m, double2 *y,
+                                                     const double *dotp, int nseg) {
     const int b = blockIdx.x, j = threadIdx.x;
     const double dt = dt_dev ? *dt_dev : dt_arg;  // a captured step reads the call's dt from device memory
     const bool in = j < m;
-    const double a = in ? alpha[(size_t)b * m + j] : 0.0;
+    // one pulse with dotp: alpha_{m-1} from its per-segment parts
+    double alast = 0.0;
+    if (dotp) {
+        for (int k = j; k < nseg; k += 64) alast += dotp[k];
+        alast = wave_sum(alast);
+    }
+    const double a = in ? (dotp && j == m - 1 ? alast : alpha[(size_t)b * m + j]) : 0.0;
     const double bu = (in && j + 1 < m) ? beta[(size_t)b * m + j] : 0.0;       // T[j][j+1]
     const double bl = (in && j > 0) ? beta[(size_t)b * m + j - 1] : 0.0;       // T[j][j-1]
     double g = fabs(a) + bu + bl;
@@ -287,9 +294,9 @@ hipError_t lz_orth(const double *vj, const double *vjm1, double *w, double *vnex
     return hipGetLastError();
 }
 hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0, double dt, const double *dt_dev,
-                   int m, int batch, double *y, hipStream_t s) {
+                   int m, int batch, double *y, const double *dotp, int nseg, hipStream_t s) {
     hipLaunchKernelGGL(lz_expm_kernel, dim3(batch), dim3(64), 0, s, alpha, beta, beta0, dt, dt_dev, m,
-                       reinterpret_cast<double2 *>(y));
+                       reinterpret_cast<double2 *>(y), dotp, nseg);
     return hipGetLastError();
 }
 hipError_t lz_combine(const double *V, size_t vstride, const double *y, int m, int batch, int64_t ncplx, double *c,

@@ -393,7 +393,8 @@ static tdse_status bat_hmul(tdse_plan p, const double *fields, const double *u, 
 // y = H(field[., k]) u for the plan's pulses (caller layout). Single-vector
 // plans read the sample from the chunk staged at `base` by chunk_begin.
 static hipError_t lz_product(tdse_plan p, const double *field, int64_t nsteps, int64_t k, int64_t base,
-                             const double *u, double *y, double *dotp, const LzNorm *nz, hipStream_t s) {
+                             const double *u, double *y, double *dotp, const LzNorm *nz, bool products,
+                             hipStream_t s) {
     hipError_t e;
     if (p->batch > 1) {
         BatBuffers b = p->bb;
@@ -416,7 +417,7 @@ static hipError_t lz_product(tdse_plan p, const double *field, int64_t nsteps, i
     // unnormalised x_j, which that launch normalises in place).
     VecBuffers vb = p->vb;
     vb.side[0].st[2] = reinterpret_cast<double2 *>(const_cast<double *>(u));
-    if (p->lmax > 0) {
+    if (p->lmax > 0 && products) {  // (else the partials come from vec_launch_lz_products)
         VecLaunch P{};
         P.parity = 1;  // reads u from parity 0, writes the partials of parity 0
         P.slots = 1;
@@ -457,14 +458,27 @@ static hipError_t lz_enqueue_steps(tdse_plan p, const LzWork &w, int m, double d
             for (int j = 0; j < m && e == hipSuccess; ++j) {
                 double *vj = w.V + (size_t)j * w.vstride;
                 const bool last = j + 1 == m;
-                const LzNorm nz{w.normp, lz_wide_groups(w.ncplx), j, w.beta0, w.alpha, w.beta};
-                e = lz_product(p, field, nsteps, k, base, vj, w.W, w.dotp, &nz, s);
-                if (e == hipSuccess)
+                // with dipole blocks the update of step j - 1 runs inside the
+                // product launch of x_j, which leaves per-segment norm parts
+                const bool folded = p->lmax > 0 && j > 0;
+                const LzNorm nz{w.normp, folded ? nseg : lz_wide_groups(w.ncplx), j, w.beta0, w.alpha, w.beta};
+                if (folded) {
+                    const LzUpdate u{w.dotp, nseg, j - 1, w.W, vj - w.vstride, j > 1 ? vj - 2 * w.vstride : nullptr,
+                                     vj, w.alpha, w.beta, w.normp};
+                    e = vec_launch_lz_products(p->vb, u, s);
+                    if (e == hipSuccess) e = lz_product(p, field, nsteps, k, base, vj, w.W, w.dotp, &nz, false, s);
+                } else {
+                    e = lz_product(p, field, nsteps, k, base, vj, w.W, w.dotp, &nz, true, s);
+                }
+                // without dipole blocks a separate update launch
+                if (e == hipSuccess && p->lmax == 0)
                     e = lz_update(w.dotp, nseg, vj, j > 0 ? vj - w.vstride : nullptr, w.W,
                                   last ? nullptr : vj + w.vstride, w.alpha, w.beta, j, last ? 1 : 0, w.normp,
                                   w.ncplx, s);
             }
-            if (e == hipSuccess) e = lz_expm(w.alpha, w.beta, w.beta0, dt, dt_dev, m, B, w.y, s);
+            if (e == hipSuccess)
+                e = lz_expm(w.alpha, w.beta, w.beta0, dt, dt_dev, m, B, w.y, p->lmax > 0 ? w.dotp : nullptr, nseg,
+                            s);
             if (e == hipSuccess)
                 e = lz_combine_wide(w.V, w.y, m, w.ncplx, c, row ? ckpt : nullptr, row ? (k + 1) / K : 0, w.normp,
                                     s);
@@ -476,12 +490,12 @@ static hipError_t lz_enqueue_steps(tdse_plan p, const LzWork &w, int m, double d
             const double *vj = w.V + (size_t)j * w.vstride;
             const bool last = j + 1 == m;
             double *vnext = last ? nullptr : w.V + (size_t)(j + 1) * w.vstride;
-            e = lz_product(p, field, nsteps, k, base, vj, w.W, nullptr, nullptr, s);
+            e = lz_product(p, field, nsteps, k, base, vj, w.W, nullptr, nullptr, true, s);
             if (e == hipSuccess)
                 e = lz_orth(vj, j > 0 ? vj - w.vstride : nullptr, w.W, vnext, w.alpha, w.beta, j, m, last ? 1 : 0,
                             B, w.len, s);
         }
-        if (e == hipSuccess) e = lz_expm(w.alpha, w.beta, w.beta0, dt, dt_dev, m, B, w.y, s);
+        if (e == hipSuccess) e = lz_expm(w.alpha, w.beta, w.beta0, dt, dt_dev, m, B, w.y, nullptr, 0, s);
         if (e == hipSuccess)
             e = lz_combine(w.V, w.vstride, w.y, m, B, w.ncplx, c, row ? ckpt : nullptr, rows, row ? (k + 1) / K : 0, s);
     }
@@ -496,8 +510,8 @@ static tdse_status lz_propagate(tdse_plan p, int m, double dt, int64_t nsteps, c
     // V (m vectors), W, the recurrence coefficients and y, and for captured
     // steps a state vector of the plan's own (a graph cannot follow cT)
     const size_t nseg = (size_t)(p->lmax + 1) * (p->T > 0 ? p->T : 1);
-    const size_t need = ((size_t)(m + 2) * vstride + (size_t)B * (4 * m + 1) + nseg + (size_t)lz_wide_groups(ncplx)) *
-                        sizeof(double);
+    const size_t need = ((size_t)(m + 2) * vstride + (size_t)B * (4 * m + 1) + 2 * nseg +
+                         (size_t)lz_wide_groups(ncplx)) * sizeof(double);
     if (need > p->lz_bytes) {
         if (p->lz_mem) (void)hipFree(p->lz_mem);
         p->lz_mem = nullptr;

@@ -236,9 +236,27 @@ struct LzNorm {
 };
 hipError_t vec_launch_hmul_dot(const VecBuffers &b, const VecLaunch &l, double *dotp, const LzNorm &nz,
                                hipStream_t s);
-// dt_dev: if not null, dt is read from there at run time (captured steps)
+// The update of step j folded into the product launch of the next vector:
+// every workgroup sums alpha_j from dotp (workgroup 0 stores it) and forms its
+// input segments of x_{j+1} = w - alpha_j v_j - beta_{j-1} v_{j-1}; one owner
+// workgroup per segment stores that segment to xnext and its part of
+// |x_{j+1}|^2 to normp[m T + q]. Needs lmax >= 1.
+struct LzUpdate {
+    const double *dotp;   // per-segment parts of alpha_j
+    int32_t nseg;
+    int32_t j;
+    const double *w;      // H v_j
+    const double *vj, *vjm1;
+    double *xnext;
+    double *alpha;
+    const double *beta;
+    double *normp;
+};
+hipError_t vec_launch_lz_products(const VecBuffers &b, const LzUpdate &z, hipStream_t s);
+// dt_dev: if not null, dt is read from there at run time (captured steps).
+// dotp (one pulse, optional): alpha_{m-1} is the sum of its nseg parts.
 hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0, double dt, const double *dt_dev,
-                   int m, int batch, double *y, hipStream_t s);
+                   int m, int batch, double *y, const double *dotp, int nseg, hipStream_t s);
 hipError_t lz_combine(const double *V, size_t vstride, const double *y, int m, int batch, int64_t ncplx, double *c,
                       double *ckpt, int64_t ckpt_rows, int64_t ckpt_row, hipStream_t s);
 // One pulse: c = sum_j y_j v_j as lz_combine, also x0 = c (the next step's

@@ -17,6 +17,14 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Workgroup barrier ordering LDS accesses only: global loads in flight stay
+// in flight across it.
+__device__ __forceinline__ void lds_only_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Sum of v over a workgroup of NT threads (NT a multiple of 64). red: NT / 64
 // doubles of LDS, free again when the call returns.
 template <int NT>
@@ -24,11 +32,11 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     static_assert(NT % 64 == 0, "whole waves");
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
+    lds_only_barrier();
     double s = red[0];
 #pragma unroll
     for (int k = 1; k < NT / 64; ++k) s += red[k];
-    __syncthreads();
+    lds_only_barrier();
     return s;
 }
 

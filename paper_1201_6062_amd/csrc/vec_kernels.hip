@@ -61,6 +61,27 @@ __device__ __forceinline__ void st_global(double2 *p, double2 v) {
     *(gdv2_t *)(p) = w;
 }
 
+// Tile loads that may be skipped (all-padding parts of a tile), as raw buffer
+// loads over the one tile: a skipped load gets an offset past the buffer's
+// end, which the hardware answers with zeros and no memory access. Every load
+// is issued either way, so the wait counter stays exact; with loads under
+// branches the compiler has to wait for all of them before the first use of
+// anything loaded earlier. Used where a value loaded before the tiles is
+// needed early (the Krylov update's alpha); the split path's products launch
+// keeps branch-skipped loads, which measured 1-2% faster there (its inputs
+// are needed only at the LDS barrier). 0x00020000: the fourth descriptor word
+// for untyped buffer access on gfx9-family GPUs.
+constexpr int TILE_BYTES = VEC_TILE_MAX * VEC_TILE_MAX * 8;
+constexpr int TILE_SKIP = 0x40000000;  // offset of a skipped load (past the end)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const double *dip, int tile) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(dip) + (size_t)tile * (TILE_BYTES / 8), 0,
+                                             TILE_BYTES, 0x00020000);
+}
+__device__ __forceinline__ double2 tile_ld(__amdgpu_buffer_rsrc_t rs, int off) {
+    const dv2_t v = __builtin_bit_cast(dv2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    return make_double2(v.x, v.y);
+}
+
 // Keeps a wave-uniform value in scalar registers at this point of the
 // program: the scalar load that produces it is issued here rather than sunk
 // towards its first use, where its round trip would join the critical path.
@@ -497,6 +518,95 @@ __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
     products_body(b, L.parity, T, l, i, j, r0, RA, c0, RB);
 }
 
+// Products launch of the next Krylov vector with the recurrence's update
+// folded in (one pulse, lmax >= 1): the input segments are x_{j+1} = w -
+// alpha_j v_j - beta_{j-1} v_{j-1}, alpha_j summed from the per-segment parts
+// in every workgroup (while the tile loads are in flight). Segment (m, q) is
+// owned by tile (m, q, 0) for m < lmax (its row-side input) and by tile
+// (lmax - 1, 0, q) for m = lmax (its column-side input); the owner stores the
+// segment of x_{j+1} and its part of |x_{j+1}|^2.
+template <int TP>
+__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_lz_products_kernel(VecBuffers b, LzUpdate z) {
+    __shared__ TileLds lds;
+    __shared__ double red[VEC_THREADS / 64];
+    __shared__ double nred[4];
+    const int T = TP <= 8 ? TP : b.T;
+    const int ntiles = b.lmax * T * T;
+    const int w = blockIdx.x;
+    const int xcd = w & 7, per = ntiles >> 3, extra = ntiles & 7;
+    const int tile = xcd * per + (xcd < extra ? xcd : extra) + (w >> 3);
+    const int l = tile / (T * T), rem = tile - l * T * T, i = rem / T, j = rem - i * T;
+    int r0, RA, c0, RB;
+    segment_of(b.n, T, i, &r0, &RA);
+    segment_of(b.n, T, j, &c0, &RB);
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    const __amdgpu_buffer_rsrc_t rs = tile_rsrc(b.dip, tile);
+    const int lofs = (wv * 16 * 64 + lane) * 16;
+    const bool isB = t >= VEC_TILE_MAX, seg_thread = t < 2 * VEC_TILE_MAX;
+    const int e = t & (VEC_TILE_MAX - 1), len = isB ? RB : RA;
+    const int sm = isB ? l + 1 : l;
+    const size_t gi = (size_t)sm * b.n + (isB ? c0 : r0) + (e < len ? e : len - 1);
+    // (plain doubles: vector-type members assigned under branches were kept
+    // in scratch memory)
+    double xr = 0.0, xi = 0.0, vr = 0.0, vi = 0.0, pr = 0.0, pi = 0.0;
+    if (seg_thread) {
+        const double2 x = ld2(reinterpret_cast<const double2 *>(z.w) + gi);
+        const double2 v = ld2(reinterpret_cast<const double2 *>(z.vj) + gi);
+        xr = x.x;
+        xi = x.y;
+        vr = v.x;
+        vi = v.y;
+        if (z.j > 0) {
+            const double2 q = ld2(reinterpret_cast<const double2 *>(z.vjm1) + gi);
+            pr = q.x;
+            pi = q.y;
+        }
+    }
+    const double bprev = z.j > 0 ? z.beta[z.j - 1] : 0.0;
+    // Up to 2 * VEC_THREADS parts: two loads per thread at clamped indices,
+    // issued before the tile loads, so that waiting for them leaves the tile
+    // stream in flight (a loop would wait inside it, before the tile loads
+    // are issued). More parts: a loop after the tile loads.
+    const int nseg = z.nseg;
+    const bool fixed = nseg <= 2 * VEC_THREADS;
+    double d0 = 0.0, d1 = 0.0;
+    if (fixed) {
+        d0 = z.dotp[t < nseg ? t : nseg - 1];
+        d1 = z.dotp[t + VEC_THREADS < nseg ? t + VEC_THREADS : nseg - 1];
+    }
+    const int cb = wv * 16 + 4 * (lane >> 4);
+    double2 dv[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const bool need = 16 * (r >> 1) < RA && cb + 2 * (r & 1) < RB;
+        dv[r] = tile_ld(rs, need ? lofs + r * 64 * 16 : TILE_SKIP);
+    }
+    double dpart = (t < nseg ? d0 : 0.0) + (t + VEC_THREADS < nseg ? d1 : 0.0);
+    if (!fixed)
+        for (int k = t; k < nseg; k += VEC_THREADS) dpart += z.dotp[k];
+    const double a = block_sum<VEC_THREADS>(dpart, red);
+    if (w == 0 && t == 0) z.alpha[z.j] = a;
+    // same operation order as lz_update_kernel
+    xr -= a * vr;
+    xi -= a * vi;
+    if (z.j > 0) {
+        xr -= bprev * pr;
+        xi -= bprev * pi;
+    }
+    const bool live = seg_thread && e < len;
+    const bool own = isB ? (l == b.lmax - 1 && i == 0) : (j == 0);
+    if (live && own) st_global(reinterpret_cast<double2 *>(z.xnext) + gi, make_double2(xr, xi));
+    if (seg_thread) {
+        const double n2 = wave_sum(live ? fma(xr, xr, xi * xi) : 0.0);
+        if (lane == 0) nred[wv] = n2;
+        (isB ? lds.uB : lds.uA)[e] = live ? make_double2(xr, xi) : make_double2(0.0, 0.0);
+    }
+    lds_barrier();
+    if (own && (t == 0 || t == VEC_TILE_MAX)) z.normp[sm * T + (isB ? j : i)] = nred[wv] + nred[wv + 1];
+    tile_products(b, lds, dv, T, l, i, j, RA, RB, 0);
+}
+
 // Uneven group: every RK4 stage-round of the active instances is one
 // combine launch over their segments (work list of (instance, m, q)) and one
 // products launch over their tiles (work list of (instance, l, i, j)); each
@@ -800,6 +910,11 @@ hipError_t vec_launch_tiles(const VecBuffers &b, const VecLaunch &l, hipStream_t
 }
 hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {
     TDSE_TP_DISPATCH(b.T, vec_combine_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s, b, l);
+    return hipGetLastError();
+}
+hipError_t vec_launch_lz_products(const VecBuffers &b, const LzUpdate &z, hipStream_t s) {
+    if (b.lmax == 0) return hipErrorInvalidValue;
+    TDSE_TP_DISPATCH(b.T, vec_lz_products_kernel, dim3(b.lmax * b.T * b.T), dim3(VEC_THREADS), 0, s, b, z);
     return hipGetLastError();
 }
 hipError_t vec_launch_hmul_dot(const VecBuffers &b, const VecLaunch &l, double *dotp, const LzNorm &nz,
