@@ -78,6 +78,19 @@ __global__ __launch_bounds__(LZ_THREADS) void lz_orth_kernel(const double *vj, c
     if (threadIdx.x == 0) beta[(size_t)b * m + j] = bj;
 }
 
+// Value of the previous (lane - 1) and next (lane + 1) lane, zero at the ends
+// of the wave: DPP whole-wave shifts by one lane (controls 0x138 and 0x130 of
+// the gfx9-family DPP encoding), two 32-bit moves per double.
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(x & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_prev(double v) { return lane_shift<0x138>(v); }
+__device__ __forceinline__ double lane_next(double v) { return lane_shift<0x130>(v); }
+
 // y = beta0 exp(-i dt T) e_1 for every pulse, one wave per pulse (lane j holds
 // component j, m <= 64). The exponential is the Taylor series of 16 terms
 // over s sub-steps, s chosen so that dt |T| / s <= 1/2 (|T| bounded by its
@@ -101,19 +114,23 @@ __global__ __launch_bounds__(64) void lz_expm_kernel(const double *alpha, const 
     for (int o = 32; o > 0; o >>= 1) g = fmax(g, __shfl_xor(g, o));
     const int sub = (int)fmax(1.0, ceil(2.0 * dt * g));
     const double h = dt / sub;
+    double ck[16];  // h / k, k = 1 .. 16
+#pragma unroll
+    for (int k = 0; k < 16; ++k) ck[k] = h / (k + 1);
     double yr = (j == 0) ? 1.0 : 0.0, yi = 0.0;
     for (int st = 0; st < sub; ++st) {
         double tr = yr, ti = yi, sr = yr, si = yi;
-        for (int k = 1; k <= 16; ++k) {
-            // (T t)_j = a t_j + bl t_{j-1} + bu t_{j+1}
-            const double pr = __shfl_up(tr, 1), pi = __shfl_up(ti, 1);
-            const double nr = __shfl_down(tr, 1), ni = __shfl_down(ti, 1);
-            const double qr = fma(bu, nr, fma(bl, j > 0 ? pr : 0.0, a * tr));
-            const double qi = fma(bu, ni, fma(bl, j > 0 ? pi : 0.0, a * ti));
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            // (T t)_j = a t_j + bl t_{j-1} + bu t_{j+1} (neighbour lanes
+            // outside the wave read as zero)
+            const double pr = lane_prev(tr), pi = lane_prev(ti);
+            const double nr = lane_next(tr), ni = lane_next(ti);
+            const double qr = fma(bu, nr, fma(bl, pr, a * tr));
+            const double qi = fma(bu, ni, fma(bl, pi, a * ti));
             // t <- (-i h / k) (T t): (-i c)(x + iy) = c y - i c x
-            const double c = h / k;
-            tr = in ? c * qi : 0.0;
-            ti = in ? -c * qr : 0.0;
+            tr = in ? ck[k] * qi : 0.0;
+            ti = in ? -ck[k] * qr : 0.0;
             sr += tr;
             si += ti;
         }
@@ -237,7 +254,20 @@ __global__ __launch_bounds__(LZ_WIDE_THREADS) void lz_combine_wide_kernel(double
     for (int64_t g = (int64_t)blockIdx.x * LZ_WIDE_THREADS + threadIdx.x; g < ncplx;
          g += (int64_t)gridDim.x * LZ_WIDE_THREADS) {
         double sr = 0.0, si = 0.0;
-        for (int j = 0; j < m; ++j) {
+        // in groups of eight, all loads of a group issued before its sums
+        int j = 0;
+        for (; j + 8 <= m; j += 8) {
+            double2 v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = V[(size_t)(j + q) * vstride2 + g];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double2 yj = y[j + q];
+                sr = fma(yj.x, v[q].x, fma(-yj.y, v[q].y, sr));
+                si = fma(yj.x, v[q].y, fma(yj.y, v[q].x, si));
+            }
+        }
+        for (; j < m; ++j) {
             const double2 yj = y[j];
             const double2 v = V[(size_t)j * vstride2 + g];
             sr = fma(yj.x, v.x, fma(-yj.y, v.y, sr));
