@@ -1,20 +1,54 @@
 // Workgroup sums in a fixed order, for the reductions of the Krylov
-// recurrence. Within a wave a butterfly over the lane-index bits: at every
-// level a lane adds its partner's value to its own, and the partner adds the
-// same two values in the other order, so (addition being commutative) all 64
-// lanes end with the identical sum. The wave sums are then added in ascending
-// wave order. Every workgroup that reduces the same array with the same
-// thread count therefore holds bit-identical results.
+// recurrence. Within a wave a butterfly: at every level a lane adds the value
+// of its partner lane (pairs: lane bit 0, bit 1, mirror images within 8 and
+// within 16 lanes, lane bit 4, lane bit 5), and the partner adds the same two
+// values in the other order, so (addition being commutative) all 64 lanes
+// end with the identical sum. The wave sums are then added in ascending wave
+// order. Every workgroup that reduces the same array with the same thread
+// count therefore holds bit-identical results.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace tdse {
 
+// v of the partner lane under DPP control CTRL (a permutation within rows of
+// 16 lanes), two 32-bit moves per double
+template <int CTRL>
+__device__ __forceinline__ double dpp_partner(double v) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(x & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// v + v of the lane whose index differs in bit 4 (BIT = 4) or bit 5 (BIT =
+// 5): the permlane swaps exchange whole 16- or 32-lane groups, so every lane
+// adds the lower group's value and the upper group's value in that order
+template <int BIT>
+__device__ __forceinline__ double swap_add(double v) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+    unsigned l0, l1, h0, h1;
+    if constexpr (BIT == 5) {
+        auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        l0 = l[0], l1 = l[1], h0 = h[0], h1 = h[1];
+    } else {
+        auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        l0 = l[0], l1 = l[1], h0 = h[0], h1 = h[1];
+    }
+    return __longlong_as_double(((long long)h0 << 32) | l0) + __longlong_as_double(((long long)h1 << 32) | l1);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += dpp_partner<0xB1>(v);   // quad_perm(1,0,3,2): lane bit 0
+    v += dpp_partner<0x4E>(v);   // quad_perm(2,3,0,1): lane bit 1
+    v += dpp_partner<0x141>(v);  // row_half_mirror: lane i <-> 7 - i within 8 lanes
+    v += dpp_partner<0x140>(v);  // row_mirror: lane i <-> 15 - i within 16 lanes
+    v = swap_add<4>(v);
+    return swap_add<5>(v);
 }
 
 // Workgroup barrier ordering LDS accesses only: global loads in flight stay

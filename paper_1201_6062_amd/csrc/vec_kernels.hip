@@ -702,9 +702,12 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_combine_kernel(VecBuffers b,
 // beta_{j-2}) counts as zero), v_j = x_j / beta in place, y = H v_j = (E o x_j
 // + F D x_j) / beta, and this segment's part of Re <v_j, y>, summed over the
 // segment in a fixed order: dotp[segment].
-template <int TP>
-__global__ __launch_bounds__(VEC_TILE_MAX) void vec_hmul_dot_kernel(VecBuffers b, VecLaunch L, double *dotp,
-                                                                    LzNorm nz) {
+// HASD: the plan has dipole blocks (lmax > 0); the two cases are separate
+// straight-line bodies, so the loads issue without a branch between them
+// (after a join the compiler waits for every outstanding load).
+template <int TP, bool HASD>
+__device__ __forceinline__ void hmul_dot_body(const VecBuffers &b, const VecLaunch &L, double *dotp,
+                                              const LzNorm &nz) {
     __shared__ double red[VEC_TILE_MAX / 64];
     const int T = TP <= 8 ? TP : b.T;
     const int seg = blockIdx.x;
@@ -713,28 +716,39 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_hmul_dot_kernel(VecBuffers b
     const int e = threadIdx.x;
     const int par = L.parity;
     const double F = field_of(b.desc, L);
+    // the breakdown test's alpha_{j-1} and beta_{j-2}: loaded up front and
+    // unconditionally (clamped indices; the unused values are dropped below)
+    const double aprev_ld = nz.alpha[nz.j > 0 ? nz.j - 1 : 0];
+    const double bprev_ld = nz.beta[nz.j > 1 ? nz.j - 2 : 0];
     const bool live = e < len;
-    const size_t gi = (size_t)m * b.n + s0 + (live ? e : 0);
+    const int ee = live ? e : 0;
+    const size_t gi = (size_t)m * b.n + s0 + ee;
     double2 *up = st_ptr(b, par, 2) + gi;
-    double2 z = make_double2(0.0, 0.0), x = make_double2(0.0, 0.0);
-    double E0 = 0.0;
-    if (live) {
-        if (b.lmax > 0)
-            z = couple(b.gauge, sum_partials<TP>(b, T, par, true, m, q, e),
-                       sum_partials<TP>(b, T, par, false, m, q, e));
-        x = ld2(up);
-        E0 = b.en[gi];
+    // every load first, in the order the values are needed (unconditional,
+    // at in-bounds indices): the vector entry, its energy, this thread's first
+    // norm part, then the partials
+    const double2 x = ld2(up);
+    const double E0 = b.en[gi];
+    const int np = nz.nparts;
+    const double n0 = nz.normp[e < np ? e : np - 1];
+    PartialLoads<TP> pr, pc;
+    if constexpr (HASD) {
+        pr = load_partials<TP>(b, T, par, true, m, q, ee);
+        pc = load_partials<TP>(b, T, par, false, m, q, ee);
     }
-    double bj = sqrt(block_sum_array<VEC_TILE_MAX>(nz.normp, nz.nparts, red));
-    if (nz.j > 0) {
-        const double bprev = nz.j > 1 ? nz.beta[nz.j - 2] : 0.0;
-        if (bj <= 1e-13 * (fabs(nz.alpha[nz.j - 1]) + bprev)) bj = 0.0;
-    }
+    double nsum = e < np ? n0 : 0.0;
+    if (np > VEC_TILE_MAX)  // (a loop here would wait for every load above)
+        for (int k = e + VEC_TILE_MAX; k < np; k += VEC_TILE_MAX) nsum += nz.normp[k];
+    double bj = sqrt(block_sum<VEC_TILE_MAX>(nsum, red));
+    const double bprev = nz.j > 1 ? bprev_ld : 0.0;
+    if (nz.j > 0 && bj <= 1e-13 * (fabs(aprev_ld) + bprev)) bj = 0.0;
     const double inv = bj > 0.0 ? 1.0 / bj : 0.0;
     if (seg == 0 && e == 0) {
         if (nz.j == 0) *nz.beta0 = bj;
         else nz.beta[nz.j - 1] = bj;
     }
+    double2 z = make_double2(0.0, 0.0);
+    if constexpr (HASD) z = couple(b.gauge, add_partials<TP>(pr, T), add_partials<TP>(pc, T));
     double dot = 0.0;
     if (live) {
         const double2 v = make_double2(x.x * inv, x.y * inv);
@@ -745,6 +759,13 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_hmul_dot_kernel(VecBuffers b
     }
     const double part = block_sum<VEC_TILE_MAX>(dot, red);
     if (e == 0) dotp[seg] = part;
+}
+
+template <int TP>
+__global__ __launch_bounds__(VEC_TILE_MAX) void vec_hmul_dot_kernel(VecBuffers b, VecLaunch L, double *dotp,
+                                                                    LzNorm nz) {
+    if (b.lmax > 0) hmul_dot_body<TP, true>(b, L, dotp, nz);
+    else hmul_dot_body<TP, false>(b, L, dotp, nz);
 }
 
 __global__ void vec_start_kernel(VecBuffers b, int par, const double2 *c0, int taylor) {
