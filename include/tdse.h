@@ -189,13 +189,22 @@ tdse_status tdse_adjoint(tdse_plan plan, tdse_method method, int32_t taylor_orde
 
 /*
  * Uneven multi-instance propagation: `count` plans (each batch == 1, any
- * lmax and n) advanced together in one persistent launch per chunk of steps.
+ * lmax, n <= 1024) advanced together. Every RK4 stage of the instances still
+ * running is one completion launch over all their state segments and one
+ * product launch over all their dipole tiles (work lists of (instance,
+ * segment) and (instance, tile), each item with its instance's own sizes,
+ * buffers and field samples); chunks of 64 such rounds replay a captured HIP
+ * graph. Instances are ordered by step count, so the ones still running form
+ * a prefix of both lists.
  * tdse_group_create: plans[count] (host array), the group keeps references
- * (the plans must outlive the group).
- * tdse_group_propagate: RK4 only; nsteps[count] (host), fields, c0, cT:
- * host arrays of `count` device pointers laid out as in tdse_propagate.
- * Instance i runs its own nsteps[i] steps; the launch ends when every
- * instance is done.
+ * (the plans must outlive the group). Errors: TDSE_E_INVAL (a plan with
+ * batch != 1, plans on different devices), TDSE_E_UNSUPPORTED (n > 1024).
+ * tdse_group_propagate: RK4 only (TDSE_E_UNSUPPORTED otherwise); nsteps[count]
+ * (host), fields, c0, cT: host arrays of `count` device pointers laid out as
+ * in tdse_propagate. Instance i runs its own nsteps[i] steps; instances that
+ * finish early leave the later rounds. Instances without dipole blocks
+ * (lmax == 0) are propagated on their own. The group keeps its work lists
+ * and captured graphs between calls (reallocated when a call needs more).
  */
 tdse_status tdse_group_create(tdse_group *out, int32_t count, const tdse_plan *plans,
                               void *stream);
