@@ -43,6 +43,20 @@ def test_lanczos_matches_oracle(lmax, n, batch, m, nsteps):
     assert rel_l2(got, ref) <= TOL
 
 
+def test_lanczos_many_segments():
+    """One pulse with Lmax=520, N=130 (1042 segments of at most 128 states,
+    2080 tiles; 67730 states): more norm and dot parts than one workgroup
+    reads in one pass, so the completion and product launches take their
+    looping reductions; 3 steps of Krylov dimension 4."""
+    h = wl.hamiltonian(520, 130, 4)
+    dt, nsteps, m = 0.02, 3, 4
+    f = samples(1, dt, nsteps)
+    c0 = wl.random_state(np.random.default_rng(21), h.nstates, 1)
+    got = make_plan(h.energies, h.dipole, 1).propagate(f, c0, dt, "lanczos", order=m).cpu().numpy()
+    ref = oracle.lanczos(h.energies, h.dipole, m, dt, f, c0, n=130)
+    assert rel_l2(got, ref) <= TOL
+
+
 @pytest.mark.parametrize("lmax,n", [(2, 70), (0, 9)])
 def test_lanczos_captured_chunks(lmax, n):
     """A single pulse without checkpoints replays captured 64-step chunks:
