@@ -91,25 +91,13 @@ __device__ __forceinline__ double lane_shift(double v) {
 __device__ __forceinline__ double lane_prev(double v) { return lane_shift<0x138>(v); }
 __device__ __forceinline__ double lane_next(double v) { return lane_shift<0x130>(v); }
 
-// y = beta0 exp(-i dt T) e_1 for every pulse, one wave per pulse (lane j holds
-// component j, m <= 64). The exponential is the Taylor series of 16 terms
-// over s sub-steps, s chosen so that dt |T| / s <= 1/2 (|T| bounded by its
-// largest Gershgorin row sum): truncation below 1e-17 per sub-step.
-__global__ __launch_bounds__(64) void lz_expm_kernel(const double *alpha, const double *beta, const double *beta0,
-                                                     double dt_arg, const double *dt_dev, int m, double2 *y,
-                                                     const double *dotp, int nseg) {
-    const int b = blockIdx.x, j = threadIdx.x;
-    const double dt = dt_dev ? *dt_dev : dt_arg;  // a captured step reads the call's dt from device memory
-    const bool in = j < m;
-    // one pulse with dotp: alpha_{m-1} from its per-segment parts
-    double alast = 0.0;
-    if (dotp) {
-        for (int k = j; k < nseg; k += 64) alast += dotp[k];
-        alast = wave_sum(alast);
-    }
-    const double a = in ? (dotp && j == m - 1 ? alast : alpha[(size_t)b * m + j]) : 0.0;
-    const double bu = (in && j + 1 < m) ? beta[(size_t)b * m + j] : 0.0;       // T[j][j+1]
-    const double bl = (in && j > 0) ? beta[(size_t)b * m + j - 1] : 0.0;       // T[j][j-1]
+// exp(-i dt T) e_1 for the tridiagonal T held one row per lane (a: diagonal,
+// bu / bl: the entries right / left of it; zero outside the matrix), as the
+// Taylor series of 16 terms over s sub-steps, s chosen so that dt |T| / s <=
+// 1/2 (|T| bounded by its largest Gershgorin row sum): truncation below 1e-17
+// per sub-step. Lane j returns component j.
+__device__ __forceinline__ void lz_exp_series(double a, double bu, double bl, double dt, bool in, int j, double &yr,
+                                              double &yi) {
     double g = fabs(a) + bu + bl;
     for (int o = 32; o > 0; o >>= 1) g = fmax(g, __shfl_xor(g, o));
     const int sub = (int)fmax(1.0, ceil(2.0 * dt * g));
@@ -117,7 +105,8 @@ __global__ __launch_bounds__(64) void lz_expm_kernel(const double *alpha, const 
     double ck[16];  // h / k, k = 1 .. 16
 #pragma unroll
     for (int k = 0; k < 16; ++k) ck[k] = h / (k + 1);
-    double yr = (j == 0) ? 1.0 : 0.0, yi = 0.0;
+    yr = (j == 0) ? 1.0 : 0.0;
+    yi = 0.0;
     for (int st = 0; st < sub; ++st) {
         double tr = yr, ti = yi, sr = yr, si = yi;
 #pragma unroll
@@ -137,9 +126,78 @@ __global__ __launch_bounds__(64) void lz_expm_kernel(const double *alpha, const 
         yr = sr;
         yi = si;
     }
+}
+
+// y = beta0 exp(-i dt T) e_1 for every pulse, one wave per pulse (lane j holds
+// component j, m <= 64). The exponential is the Taylor series of 16 terms
+// over s sub-steps, s chosen so that dt |T| / s <= 1/2 (|T| bounded by its
+// largest Gershgorin row sum): truncation below 1e-17 per sub-step.
+__global__ __launch_bounds__(64) void lz_expm_kernel(const double *alpha, const double *beta, const double *beta0,
+                                                     double dt_arg, const double *dt_dev, int m, double2 *y,
+                                                     const double *dotp, int nseg) {
+    const int b = blockIdx.x, j = threadIdx.x;
+    const double dt = dt_dev ? *dt_dev : dt_arg;  // a captured step reads the call's dt from device memory
+    const bool in = j < m;
+    // one pulse with dotp: alpha_{m-1} from its per-segment parts
+    double alast = 0.0;
+    if (dotp) {
+        for (int k = j; k < nseg; k += 64) alast += dotp[k];
+        alast = wave_sum(alast);
+    }
+    const double a = in ? (dotp && j == m - 1 ? alast : alpha[(size_t)b * m + j]) : 0.0;
+    const double bu = (in && j + 1 < m) ? beta[(size_t)b * m + j] : 0.0;       // T[j][j+1]
+    const double bl = (in && j > 0) ? beta[(size_t)b * m + j - 1] : 0.0;       // T[j][j-1]
+    double yr, yi;
+    lz_exp_series(a, bu, bl, dt, in, j, yr, yi);
     if (in) {
         const double nb = beta0[b];
         y[(size_t)b * m + j] = make_double2(nb * yr, nb * yi);
+    }
+}
+
+// One pulse, one launch per Krylov product: the last vector's alpha and norm
+// from the parts its launch left, the exponential, and y_j scaled by
+// beta0 / beta_{j-1} (beta_{-1} = beta0), so that c = sum_j y_j x_j over the
+// unnormalised vectors x_j. qin/ein/nin: the parts of x_{m-1}.
+__global__ __launch_bounds__(64) void lz_expm_fused_kernel(double *alpha, double *beta, double *beta0,
+                                                           const double *qin, const double *ein, const double *nin,
+                                                           int ntiles, int nseg, const double *fsample,
+                                                           const double *dt_dev, double dt_arg, int m, double2 *y) {
+    const int j = threadIdx.x;
+    const double dt = dt_dev ? *dt_dev : dt_arg;
+    const bool in = j < m;
+    double qs = 0.0, es = 0.0, ns = 0.0;
+    for (int k = j; k < ntiles; k += 64) qs += qin[k];
+    for (int k = j; k < nseg; k += 64) {
+        es += ein[k];
+        ns += nin[k];
+    }
+    qs = wave_sum(qs);
+    es = wave_sum(es);
+    ns = wave_sum(ns);
+    const double F = *fsample;
+    // beta_{m-2} (beta0 for m = 1) with the breakdown rule, then alpha_{m-1}
+    double blast = sqrt(ns);
+    if (m >= 2 && blast <= 1e-13 * (fabs(alpha[m - 2]) + (m >= 3 ? beta[m - 3] : 0.0))) blast = 0.0;
+    const double sl = blast > 0.0 ? 1.0 / blast : 0.0;
+    const double alast = (es + F * qs) * (sl * sl);
+    // beta_q for q = 0 .. m-2 (the last from blast)
+    auto beta_of = [&](int q) { return q == m - 2 ? blast : beta[q]; };
+    const double a = in ? (j == m - 1 ? alast : alpha[j]) : 0.0;
+    const double bu = (in && j + 1 < m) ? beta_of(j) : 0.0;
+    const double bl = (in && j > 0) ? beta_of(j - 1) : 0.0;
+    const double b0 = m == 1 ? blast : *beta0;
+    double yr, yi;
+    lz_exp_series(a, bu, bl, dt, in, j, yr, yi);
+    if (in) {
+        const double bj = j == 0 ? b0 : beta_of(j - 1);  // |x_j| as used: v_j = x_j / bj
+        const double sc = bj > 0.0 ? b0 / bj : 0.0;
+        y[j] = make_double2(sc * yr, sc * yi);
+    }
+    if (j == 0) {
+        alpha[m - 1] = alast;
+        if (m == 1) *beta0 = blast;
+        else beta[m - 2] = blast;
     }
 }
 
@@ -327,6 +385,13 @@ hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0,
                    int m, int batch, double *y, const double *dotp, int nseg, hipStream_t s) {
     hipLaunchKernelGGL(lz_expm_kernel, dim3(batch), dim3(64), 0, s, alpha, beta, beta0, dt, dt_dev, m,
                        reinterpret_cast<double2 *>(y), dotp, nseg);
+    return hipGetLastError();
+}
+hipError_t lz_expm_fused(double *alpha, double *beta, double *beta0, const double *qin, const double *ein,
+                         const double *nin, int ntiles, int nseg, const double *fsample, double dt,
+                         const double *dt_dev, int m, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(lz_expm_fused_kernel, dim3(1), dim3(64), 0, s, alpha, beta, beta0, qin, ein, nin, ntiles, nseg,
+                       fsample, dt_dev, dt, m, reinterpret_cast<double2 *>(y));
     return hipGetLastError();
 }
 hipError_t lz_combine(const double *V, size_t vstride, const double *y, int m, int batch, int64_t ncplx, double *c,

@@ -439,6 +439,7 @@ static hipError_t lz_product(tdse_plan p, const double *field, int64_t nsteps, i
 struct LzWork {
     double *V, *W, *alpha, *beta, *beta0, *y, *C;
     double *dotp, *normp;  // one pulse: per-segment dots, per-workgroup norms
+    double *qp[2], *ep[2], *np[2];  // one pulse, one launch per product: parts by parity
     size_t vstride;
     int64_t len, ncplx;
 };
@@ -450,6 +451,42 @@ static hipError_t lz_enqueue_steps(tdse_plan p, const LzWork &w, int m, double d
     hipError_t e = hipSuccess;
     for (int64_t k = k0; k < k0 + count && e == hipSuccess; ++k) {
         const bool row = ckpt && (k + 1) % K == 0;
+        // one launch per Krylov product on plans of the fused tile path (at
+        // most 512 tiles; the split path's plans re-read fewer partials with
+        // separate product and completion launches)
+        if (B == 1 && p->lmax > 0 && !p->split && (int64_t)p->lmax * p->T * p->T <= 512) {
+            if (k == k0) e = lz_begin_wide(c, w.V, w.normp, w.ncplx, s);  // x_0 = c
+            const double *fs = reinterpret_cast<const double *>(reinterpret_cast<const char *>(p->vb.desc) +
+                                                                offsetof(CallDesc, chunk_field)) +
+                               (k - base) + 1;
+            for (int j = 0; j < m && e == hipSuccess; ++j) {
+                const int pw = j & 1, pr = pw ^ 1;
+                LzFused f{};
+                f.xprev = w.V + (size_t)(j > 0 ? j - 1 : 0) * w.vstride;
+                f.xprev2 = w.V + (size_t)(j > 1 ? j - 2 : 0) * w.vstride;
+                f.xout = w.V + (size_t)j * w.vstride;
+                f.qin = w.qp[pr];
+                f.ein = w.ep[pr];
+                f.nin = w.np[pr];
+                f.qout = w.qp[pw];
+                f.eout = w.ep[pw];
+                f.nout = w.np[pw];
+                f.fsample = fs;
+                f.alpha = w.alpha;
+                f.beta = w.beta;
+                f.beta0 = w.beta0;
+                f.k = j;
+                e = vec_launch_lz_fused(p->vb, f, s);
+            }
+            const int pl = (m - 1) & 1;
+            if (e == hipSuccess)
+                e = lz_expm_fused(w.alpha, w.beta, w.beta0, w.qp[pl], w.ep[pl], w.np[pl], p->lmax * p->T * p->T,
+                                  (p->lmax + 1) * p->T, fs, dt, dt_dev, m, w.y, s);
+            if (e == hipSuccess)
+                e = lz_combine_wide(w.V, w.y, m, w.ncplx, c, row ? ckpt : nullptr, row ? (k + 1) / K : 0, w.normp,
+                                    s);
+            continue;
+        }
         if (B == 1) {  // the recurrence spread over many workgroups
             // x_0 = c with its norm parts; after the first step the previous
             // step's recombination has left both
@@ -510,8 +547,9 @@ static tdse_status lz_propagate(tdse_plan p, int m, double dt, int64_t nsteps, c
     // V (m vectors), W, the recurrence coefficients and y, and for captured
     // steps a state vector of the plan's own (a graph cannot follow cT)
     const size_t nseg = (size_t)(p->lmax + 1) * (p->T > 0 ? p->T : 1);
+    const size_t ntl = (size_t)p->lmax * (p->T > 0 ? p->T : 1) * (p->T > 0 ? p->T : 1);
     const size_t need = ((size_t)(m + 2) * vstride + (size_t)B * (4 * m + 1) + 2 * nseg +
-                         (size_t)lz_wide_groups(ncplx)) * sizeof(double);
+                         (size_t)lz_wide_groups(ncplx) + 2 * (ntl + 2 * nseg)) * sizeof(double);
     if (need > p->lz_bytes) {
         if (p->lz_mem) (void)hipFree(p->lz_mem);
         p->lz_mem = nullptr;
@@ -540,6 +578,17 @@ static tdse_status lz_propagate(tdse_plan p, int m, double dt, int64_t nsteps, c
     w.y = w.beta0 + B;                           // [B][m] complex
     w.dotp = w.y + (size_t)2 * B * m;
     w.normp = w.dotp + nseg;
+    {
+        double *pp = w.normp + nseg + lz_wide_groups(ncplx);
+        for (int q = 0; q < 2; ++q) {
+            w.qp[q] = pp;
+            pp += ntl;
+            w.ep[q] = pp;
+            pp += nseg;
+            w.np[q] = pp;
+            pp += nseg;
+        }
+    }
     w.vstride = vstride;
     w.len = len;
     w.ncplx = ncplx;

@@ -253,12 +253,42 @@ struct LzUpdate {
     double *normp;
 };
 hipError_t vec_launch_lz_products(const VecBuffers &b, const LzUpdate &z, hipStream_t s);
+// One launch per Krylov product (one pulse, plans on the fused tile path).
+// Launch k forms x_k and its products: for k >= 1 every tile workgroup
+// completes, for its two input segments, the product of x_{k-1} from the
+// previous launch's partials, and forms x_k = H v_{k-1} - alpha_{k-1} v_{k-1}
+// - beta_{k-2} v_{k-2} with v_j = x_j / beta_{j-1} (beta_{-1} = beta0 =
+// |x_0|); alpha_{k-1} = (sum E|x|^2 + F x^H D x) / |x|^2 of x_{k-1} and its
+// norm come from the previous launch's parts, summed in the same order in
+// every workgroup (workgroup 0 stores alpha_{k-1} and beta_{k-2}, or beta0
+// for k = 1). Launch 0 takes x_0 as it is. Every launch leaves, for x_k:
+// the partials (parity k & 1), x^H D x per tile (real part, length gauge;
+// imaginary part, velocity gauge; times 2), and per segment sum E|x|^2 and
+// |x|^2 (the segment's owner tile), and the owners store x_k (k >= 1).
+struct LzFused {
+    const double *xprev;   // k >= 1: x_{k-1}; k = 0: x_0
+    const double *xprev2;  // x_{k-2} (k >= 2; any valid vector otherwise)
+    double *xout;          // x_k (k >= 1)
+    const double *qin, *ein, *nin;  // parts of x_{k-1}
+    double *qout, *eout, *nout;     // parts of x_k
+    const double *fsample; // this step's field sample
+    double *alpha, *beta, *beta0;
+    int32_t k;
+    int32_t pad_;
+};
+hipError_t vec_launch_lz_fused(const VecBuffers &b, const LzFused &z, hipStream_t s);
 // dt_dev: if not null, dt is read from there at run time (captured steps).
 // dotp (one pulse, optional): alpha_{m-1} is the sum of its nseg parts.
 hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0, double dt, const double *dt_dev,
                    int m, int batch, double *y, const double *dotp, int nseg, hipStream_t s);
 hipError_t lz_combine(const double *V, size_t vstride, const double *y, int m, int batch, int64_t ncplx, double *c,
                       double *ckpt, int64_t ckpt_rows, int64_t ckpt_row, hipStream_t s);
+// One pulse, one launch per product: alpha_{m-1} and |x_{m-1}| from that
+// launch's parts, the exponential, y_j scaled by beta0 / beta_{j-1} (for the
+// recombination over the unnormalised x_j).
+hipError_t lz_expm_fused(double *alpha, double *beta, double *beta0, const double *qin, const double *ein,
+                         const double *nin, int ntiles, int nseg, const double *fsample, double dt,
+                         const double *dt_dev, int m, double *y, hipStream_t s);
 // One pulse: c = sum_j y_j v_j as lz_combine, also x0 = c (the next step's
 // first Krylov vector, in place over v_0) and its norm parts.
 hipError_t lz_combine_wide(double *V, const double *y, int m, int64_t ncplx, double *c, double *ckpt,

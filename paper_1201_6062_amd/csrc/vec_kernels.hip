@@ -276,8 +276,13 @@ struct TileLds {
 // order, this lane's 16 loads) and the inputs in lds.uA / lds.uB: writes the
 // row partials (towards z_l, rows i) and column partials (towards z_{l+1},
 // columns j) to the partial buffers of parity npar.
-__device__ __forceinline__ void tile_products(const VecBuffers &b, TileLds &lds, const double2 (&dv)[16], int T,
-                                              int l, int i, int j, int RA, int RB, int npar) {
+// QF (Krylov products): also returns, in the row threads, this row's term of
+// the tile's part of the quadratic form, conj(u_A[a]) (D_tile u_B)[a] -- its
+// real part (length gauge) or imaginary part (velocity gauge, QF = 2); 0 in
+// every other thread.
+template <int QF = 0>
+__device__ __forceinline__ double tile_products(const VecBuffers &b, TileLds &lds, const double2 (&dv)[16], int T,
+                                                int l, int i, int j, int RA, int RB, int npar) {
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
     // Output bases held in scalar registers: the two partial stores below sit
@@ -347,8 +352,16 @@ __device__ __forceinline__ void tile_products(const VecBuffers &b, TileLds &lds,
             for (int k = 1; k < VEC_THREADS / 64; ++k) s = cadd(s, lds.rbuf[k][a]);
             double2 *rp = rowp_out + ((size_t)(l * T + i) * T + j) * VEC_TILE_MAX;
             st_global(rp + a, s);
+            if constexpr (QF == 1) {
+                const double2 ua = lds.uA[a];
+                return fma(ua.x, s.x, ua.y * s.y);
+            } else if constexpr (QF == 2) {
+                const double2 ua = lds.uA[a];
+                return fma(ua.x, s.y, -(ua.y * s.x));
+            }
         }
     }
+    return 0.0;
 }
 
 // One tile workgroup of the fused path: completes the previous product for
@@ -605,6 +618,159 @@ __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
     lds_barrier();
     if (own && (t == 0 || t == VEC_TILE_MAX)) z.normp[sm * T + (isB ? j : i)] = nred[wv] + nred[wv + 1];
     tile_products(b, lds, dv, T, l, i, j, RA, RB, 0);
+}
+
+// One launch per Krylov product (see LzFused). The structure follows
+// tile_body: prologue loads (half 0: row partials, x_{k-1}, x_{k-2}, E; half
+// 1: column partials), the previous launch's parts, the tile stream, then the
+// sums, the formation of this tile's two input segments of x_k, the tile
+// products with the tile's quadratic-form term, and the parts of x_k.
+template <int TP, int G>
+__device__ __forceinline__ void lz_tile_body(const VecBuffers &b, const LzFused &z, int T, int l, int i, int j,
+                                             int r0, int RA, int c0, int RB) {
+    const int n = b.n;
+    const int tile = (l * T + i) * T + j;
+    __shared__ TileLds lds;
+    __shared__ double red[3][VEC_THREADS / 64];
+    __shared__ double sred[4][2];  // [wave of the input threads][e-part, n-part]
+    __shared__ double qred[2];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    const int pe = t & 255, half = __builtin_amdgcn_readfirstlane(t >> 8);
+    const bool isB = pe >= VEC_TILE_MAX;
+    const int e = pe & (VEC_TILE_MAX - 1);
+    const int m = isB ? l + 1 : l, q = isB ? j : i, len = isB ? RB : RA, s0 = isB ? c0 : r0;
+    const int ec = e < len ? e : len - 1;
+    const size_t gi = (size_t)m * n + s0 + ec;
+    const int k = z.k;
+    // prologue (the partials exist for k = 0 too; their values are unused then)
+    const PartialLoads<TP> pl = load_partials<TP>(b, T, 0, half == 0, m, q, ec);
+    double2 xp = make_double2(0.0, 0.0), xp2 = xp;
+    double E0 = 0.0;
+    if (half == 0) {
+        xp = ld2(reinterpret_cast<const double2 *>(z.xprev) + gi);
+        xp2 = ld2(reinterpret_cast<const double2 *>(z.xprev2) + gi);
+        E0 = b.en[gi];
+    }
+    // parts of x_{k-1}: at most VEC_THREADS tiles and 2 VEC_THREADS segments
+    // on this path (L T^2 <= 512); loads at clamped indices
+    const int ntiles = b.lmax * T * T, nseg = (b.lmax + 1) * T;
+    const double qv = z.qin[t < ntiles ? t : ntiles - 1];
+    const double ev0 = z.ein[t < nseg ? t : nseg - 1], nv0 = z.nin[t < nseg ? t : nseg - 1];
+    const int t2 = t + VEC_THREADS;
+    const double ev1 = z.ein[t2 < nseg ? t2 : nseg - 1], nv1 = z.nin[t2 < nseg ? t2 : nseg - 1];
+    // alpha_{k-2} and beta_{k-3} (beta0 for k = 2), stored by earlier launches
+    const double a_pp = k >= 2 ? z.alpha[k - 2] : 0.0;
+    const double b_ppp = k >= 3 ? z.beta[k - 3] : (k == 2 ? *z.beta0 : 0.0);
+    const double F = *z.fsample;
+
+    const double2 *Dt = reinterpret_cast<const double2 *>(b.dip) +
+                        (size_t)tile * (VEC_TILE_MAX * VEC_TILE_MAX / 2) + wv * 16 * 64 + lane;
+    constexpr int EARLY = TP <= 4 ? 16 : (TP <= 8 ? 8 : 0);
+    double2 dv[16];
+#pragma unroll
+    for (int r = 0; r < EARLY; ++r) dv[r] = Dt[r * 64];
+    __builtin_amdgcn_sched_barrier(0);
+    // sums of the parts (every workgroup, same order)
+    double qs = t < ntiles ? qv : 0.0;
+    double es = (t < nseg ? ev0 : 0.0) + (t2 < nseg ? ev1 : 0.0);
+    double ns = (t < nseg ? nv0 : 0.0) + (t2 < nseg ? nv1 : 0.0);
+    qs = wave_sum(qs);
+    es = wave_sum(es);
+    ns = wave_sum(ns);
+    if (lane == 0) {
+        red[0][wv] = qs;
+        red[1][wv] = es;
+        red[2][wv] = ns;
+    }
+    const double2 zpart = add_partials<TP>(pl, T);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = EARLY; r < 16; ++r) dv[r] = Dt[r * 64];
+    if (half == 1) lds.zc[pe] = zpart;
+    lds_barrier();
+    double Q = red[0][0], Es = red[1][0], Ns = red[2][0];
+#pragma unroll
+    for (int w = 1; w < VEC_THREADS / 64; ++w) {
+        Q += red[0][w];
+        Es += red[1][w];
+        Ns += red[2][w];
+    }
+    // beta_{k-2} = |x_{k-1}| (beta0 for k = 1) with the breakdown rule,
+    // alpha_{k-1}, and the scales of v_{k-1} and v_{k-2}
+    double bprev = sqrt(Ns);
+    if (k >= 2 && bprev <= 1e-13 * (fabs(a_pp) + (k >= 3 ? b_ppp : 0.0))) bprev = 0.0;
+    const double s1 = bprev > 0.0 ? 1.0 / bprev : 0.0;
+    const double s2 = b_ppp > 0.0 ? 1.0 / b_ppp : 0.0;
+    const double alpha = (Es + F * Q) * (s1 * s1);
+    if (blockIdx.x == 0 && t == 0 && k >= 1) {
+        z.alpha[k - 1] = alpha;
+        if (k == 1) *z.beta0 = bprev;
+        else z.beta[k - 2] = bprev;
+    }
+    // this tile's input segments of x_k
+    double2 x = make_double2(0.0, 0.0);
+    double epart = 0.0, npart = 0.0;
+    bool owner = false;
+    if (half == 0) {
+        if (e < len) {
+            if (k == 0) {
+                x = xp;
+            } else {
+                const double2 w = couple_g<G>(zpart, lds.zc[pe]);
+                const double2 v = make_double2(xp.x * s1, xp.y * s1);
+                const double yr = fma(F, w.x * s1, E0 * v.x), yi = fma(F, w.y * s1, E0 * v.y);
+                x.x = yr - alpha * v.x;
+                x.y = yi - alpha * v.y;
+                if (k >= 2) {
+                    x.x -= bprev * (xp2.x * s2);
+                    x.y -= bprev * (xp2.y * s2);
+                }
+            }
+            const double a2 = fma(x.x, x.x, x.y * x.y);
+            npart = a2;
+            epart = E0 * a2;
+            owner = isB ? (l == b.lmax - 1 && i == 0) : (j == 0);
+        }
+        (isB ? lds.uB : lds.uA)[e] = x;
+        epart = wave_sum(epart);
+        npart = wave_sum(npart);
+        if (lane == 0) {
+            sred[wv][0] = epart;
+            sred[wv][1] = npart;
+        }
+    }
+    lds_barrier();
+    // the owner of each input segment stores its parts (threads 0 and 128:
+    // the first thread of each half's segment)
+    const bool seg_owner = isB ? (l == b.lmax - 1 && i == 0) : (j == 0);
+    if (half == 0 && (pe == 0 || pe == VEC_TILE_MAX) && seg_owner) {
+        const int sg = m * T + q, w0 = pe >> 6;
+        z.eout[sg] = sred[w0][0] + sred[w0 + 1][0];
+        z.nout[sg] = sred[w0][1] + sred[w0 + 1][1];
+    }
+    const double wq = tile_products<G == 0 ? 1 : 2>(b, lds, dv, T, l, i, j, RA, RB, 1);
+    if (owner && k >= 1) st_global(reinterpret_cast<double2 *>(z.xout) + gi, x);
+    if (wv == 2 || wv == 3) {
+        const double sq = wave_sum(wq);
+        if (lane == 0) qred[wv - 2] = sq;
+    }
+    lds_barrier();
+    if (t == 0) z.qout[tile] = 2.0 * (qred[0] + qred[1]);
+}
+
+template <int TP, int G>
+__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_lz_fused_kernel(VecBuffers b, LzFused z) {
+    const int T = TP <= 8 ? TP : b.T;
+    const int ntiles = b.lmax * T * T;
+    const int w = blockIdx.x;
+    const int xcd = w & 7, per = ntiles >> 3, extra = ntiles & 7;
+    const int tile = xcd * per + (xcd < extra ? xcd : extra) + (w >> 3);
+    const int l = tile / (T * T), rem = tile - l * T * T, i = rem / T, j = rem - i * T;
+    int r0, RA, c0, RB;
+    segment_of(b.n, T, i, &r0, &RA);
+    segment_of(b.n, T, j, &c0, &RB);
+    lz_tile_body<TP, G>(b, z, T, l, i, j, r0, RA, c0, RB);
 }
 
 // Uneven group: every RK4 stage-round of the active instances is one
@@ -936,6 +1102,30 @@ hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream
 hipError_t vec_launch_lz_products(const VecBuffers &b, const LzUpdate &z, hipStream_t s) {
     if (b.lmax == 0) return hipErrorInvalidValue;
     TDSE_TP_DISPATCH(b.T, vec_lz_products_kernel, dim3(b.lmax * b.T * b.T), dim3(VEC_THREADS), 0, s, b, z);
+    return hipGetLastError();
+}
+template <int G>
+static void (*lz_fused_kernel_for(int T))(VecBuffers, LzFused) {
+    switch (T) {
+    case 1: return vec_lz_fused_kernel<1, G>;
+    case 2: return vec_lz_fused_kernel<2, G>;
+    case 3: return vec_lz_fused_kernel<3, G>;
+    case 4: return vec_lz_fused_kernel<4, G>;
+    case 5: return vec_lz_fused_kernel<5, G>;
+    case 6: return vec_lz_fused_kernel<6, G>;
+    case 7: return vec_lz_fused_kernel<7, G>;
+    case 8: return vec_lz_fused_kernel<8, G>;
+    default: return T <= 16 ? vec_lz_fused_kernel<16, G> : nullptr;
+    }
+}
+// Launch k reads the partials of parity (k - 1) & 1 and writes parity k & 1:
+// through the parity view, always "read side 0, write side 1".
+hipError_t vec_launch_lz_fused(const VecBuffers &b, const LzFused &z, hipStream_t s) {
+    const int ntiles = b.lmax * b.T * b.T;
+    if (b.lmax == 0 || ntiles > VEC_THREADS || (b.lmax + 1) * b.T > 2 * VEC_THREADS) return hipErrorInvalidValue;
+    void (*k)(VecBuffers, LzFused) = b.gauge ? lz_fused_kernel_for<1>(b.T) : lz_fused_kernel_for<0>(b.T);
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3(ntiles), dim3(VEC_THREADS), 0, s, parity_view(b, (z.k + 1) & 1), z);
     return hipGetLastError();
 }
 hipError_t vec_launch_hmul_dot(const VecBuffers &b, const VecLaunch &l, double *dotp, const LzNorm &nz,
