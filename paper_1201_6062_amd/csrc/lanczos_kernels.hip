@@ -161,13 +161,13 @@ __global__ __launch_bounds__(64) void lz_expm_kernel(const double *alpha, const 
 // unnormalised vectors x_j. qin/ein/nin: the parts of x_{m-1}.
 __global__ __launch_bounds__(64) void lz_expm_fused_kernel(double *alpha, double *beta, double *beta0,
                                                            const double *qin, const double *ein, const double *nin,
-                                                           int ntiles, int nseg, const double *fsample,
+                                                           int nq, int nseg, const double *fsample,
                                                            const double *dt_dev, double dt_arg, int m, double2 *y) {
     const int j = threadIdx.x;
     const double dt = dt_dev ? *dt_dev : dt_arg;
     const bool in = j < m;
     double qs = 0.0, es = 0.0, ns = 0.0;
-    for (int k = j; k < ntiles; k += 64) qs += qin[k];
+    for (int k = j; k < nq; k += 64) qs += qin[k];
     for (int k = j; k < nseg; k += 64) {
         es += ein[k];
         ns += nin[k];
@@ -388,9 +388,9 @@ hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0,
     return hipGetLastError();
 }
 hipError_t lz_expm_fused(double *alpha, double *beta, double *beta0, const double *qin, const double *ein,
-                         const double *nin, int ntiles, int nseg, const double *fsample, double dt,
+                         const double *nin, int nq, int nseg, const double *fsample, double dt,
                          const double *dt_dev, int m, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(lz_expm_fused_kernel, dim3(1), dim3(64), 0, s, alpha, beta, beta0, qin, ein, nin, ntiles, nseg,
+    hipLaunchKernelGGL(lz_expm_fused_kernel, dim3(1), dim3(64), 0, s, alpha, beta, beta0, qin, ein, nin, nq, nseg,
                        fsample, dt_dev, dt, m, reinterpret_cast<double2 *>(y));
     return hipGetLastError();
 }

@@ -480,7 +480,7 @@ static hipError_t lz_enqueue_steps(tdse_plan p, const LzWork &w, int m, double d
             }
             const int pl = (m - 1) & 1;
             if (e == hipSuccess)
-                e = lz_expm_fused(w.alpha, w.beta, w.beta0, w.qp[pl], w.ep[pl], w.np[pl], p->lmax * p->T * p->T,
+                e = lz_expm_fused(w.alpha, w.beta, w.beta0, w.qp[pl], w.ep[pl], w.np[pl], 2 * p->lmax * p->T * p->T,
                                   (p->lmax + 1) * p->T, fs, dt, dt_dev, m, w.y, s);
             if (e == hipSuccess)
                 e = lz_combine_wide(w.V, w.y, m, w.ncplx, c, row ? ckpt : nullptr, row ? (k + 1) / K : 0, w.normp,
@@ -549,7 +549,7 @@ static tdse_status lz_propagate(tdse_plan p, int m, double dt, int64_t nsteps, c
     const size_t nseg = (size_t)(p->lmax + 1) * (p->T > 0 ? p->T : 1);
     const size_t ntl = (size_t)p->lmax * (p->T > 0 ? p->T : 1) * (p->T > 0 ? p->T : 1);
     const size_t need = ((size_t)(m + 2) * vstride + (size_t)B * (4 * m + 1) + 2 * nseg +
-                         (size_t)lz_wide_groups(ncplx) + 2 * (ntl + 2 * nseg)) * sizeof(double);
+                         (size_t)lz_wide_groups(ncplx) + 2 * (2 * ntl + 2 * nseg)) * sizeof(double);
     if (need > p->lz_bytes) {
         if (p->lz_mem) (void)hipFree(p->lz_mem);
         p->lz_mem = nullptr;
@@ -581,8 +581,8 @@ static tdse_status lz_propagate(tdse_plan p, int m, double dt, int64_t nsteps, c
     {
         double *pp = w.normp + nseg + lz_wide_groups(ncplx);
         for (int q = 0; q < 2; ++q) {
-            w.qp[q] = pp;
-            pp += ntl;
+            w.qp[q] = pp;  // two parts per tile
+            pp += 2 * ntl;
             w.ep[q] = pp;
             pp += nseg;
             w.np[q] = pp;

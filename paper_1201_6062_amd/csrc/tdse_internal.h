@@ -262,9 +262,10 @@ hipError_t vec_launch_lz_products(const VecBuffers &b, const LzUpdate &z, hipStr
 // norm come from the previous launch's parts, summed in the same order in
 // every workgroup (workgroup 0 stores alpha_{k-1} and beta_{k-2}, or beta0
 // for k = 1). Launch 0 takes x_0 as it is. Every launch leaves, for x_k:
-// the partials (parity k & 1), x^H D x per tile (real part, length gauge;
-// imaginary part, velocity gauge; times 2), and per segment sum E|x|^2 and
-// |x|^2 (the segment's owner tile), and the owners store x_k (k >= 1).
+// the partials (parity k & 1), x^H D x in two parts per tile (real part,
+// length gauge; imaginary part, velocity gauge; times 2), and per segment
+// sum E|x|^2 and |x|^2 (the segment's owner tile), and the owners store x_k
+// (k >= 1).
 struct LzFused {
     const double *xprev;   // k >= 1: x_{k-1}; k = 0: x_0
     const double *xprev2;  // x_{k-2} (k >= 2; any valid vector otherwise)
@@ -287,7 +288,7 @@ hipError_t lz_combine(const double *V, size_t vstride, const double *y, int m, i
 // launch's parts, the exponential, y_j scaled by beta0 / beta_{j-1} (for the
 // recombination over the unnormalised x_j).
 hipError_t lz_expm_fused(double *alpha, double *beta, double *beta0, const double *qin, const double *ein,
-                         const double *nin, int ntiles, int nseg, const double *fsample, double dt,
+                         const double *nin, int nq, int nseg, const double *fsample, double dt,
                          const double *dt_dev, int m, double *y, hipStream_t s);
 // One pulse: c = sum_j y_j v_j as lz_combine, also x0 = c (the next step's
 // first Krylov vector, in place over v_0) and its norm parts.

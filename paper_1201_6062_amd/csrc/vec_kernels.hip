@@ -633,7 +633,6 @@ __device__ __forceinline__ void lz_tile_body(const VecBuffers &b, const LzFused 
     __shared__ TileLds lds;
     __shared__ double red[3][VEC_THREADS / 64];
     __shared__ double sred[4][2];  // [wave of the input threads][e-part, n-part]
-    __shared__ double qred[2];
     const int t = threadIdx.x;
     const int lane = t & 63, wv = t >> 6;
     const int pe = t & 255, half = __builtin_amdgcn_readfirstlane(t >> 8);
@@ -652,12 +651,13 @@ __device__ __forceinline__ void lz_tile_body(const VecBuffers &b, const LzFused 
         xp2 = ld2(reinterpret_cast<const double2 *>(z.xprev2) + gi);
         E0 = b.en[gi];
     }
-    // parts of x_{k-1}: at most VEC_THREADS tiles and 2 VEC_THREADS segments
-    // on this path (L T^2 <= 512); loads at clamped indices
-    const int ntiles = b.lmax * T * T, nseg = (b.lmax + 1) * T;
-    const double qv = z.qin[t < ntiles ? t : ntiles - 1];
-    const double ev0 = z.ein[t < nseg ? t : nseg - 1], nv0 = z.nin[t < nseg ? t : nseg - 1];
+    // parts of x_{k-1}: two per tile (at most 2 VEC_THREADS on this path, L
+    // T^2 <= 512) and one per segment (at most 2 VEC_THREADS); loads at
+    // clamped indices
+    const int nq = 2 * b.lmax * T * T, nseg = (b.lmax + 1) * T;
     const int t2 = t + VEC_THREADS;
+    const double qv0 = z.qin[t < nq ? t : nq - 1], qv1 = z.qin[t2 < nq ? t2 : nq - 1];
+    const double ev0 = z.ein[t < nseg ? t : nseg - 1], nv0 = z.nin[t < nseg ? t : nseg - 1];
     const double ev1 = z.ein[t2 < nseg ? t2 : nseg - 1], nv1 = z.nin[t2 < nseg ? t2 : nseg - 1];
     // alpha_{k-2} and beta_{k-3} (beta0 for k = 2), stored by earlier launches
     const double a_pp = k >= 2 ? z.alpha[k - 2] : 0.0;
@@ -672,7 +672,7 @@ __device__ __forceinline__ void lz_tile_body(const VecBuffers &b, const LzFused 
     for (int r = 0; r < EARLY; ++r) dv[r] = Dt[r * 64];
     __builtin_amdgcn_sched_barrier(0);
     // sums of the parts (every workgroup, same order)
-    double qs = t < ntiles ? qv : 0.0;
+    double qs = (t < nq ? qv0 : 0.0) + (t2 < nq ? qv1 : 0.0);
     double es = (t < nseg ? ev0 : 0.0) + (t2 < nseg ? ev1 : 0.0);
     double ns = (t < nseg ? nv0 : 0.0) + (t2 < nseg ? nv1 : 0.0);
     qs = wave_sum(qs);
@@ -751,12 +751,11 @@ __device__ __forceinline__ void lz_tile_body(const VecBuffers &b, const LzFused 
     }
     const double wq = tile_products<G == 0 ? 1 : 2>(b, lds, dv, T, l, i, j, RA, RB, 1);
     if (owner && k >= 1) st_global(reinterpret_cast<double2 *>(z.xout) + gi, x);
+    // the two row waves' sums are two parts each (no barrier needed)
     if (wv == 2 || wv == 3) {
         const double sq = wave_sum(wq);
-        if (lane == 0) qred[wv - 2] = sq;
+        if (lane == 0) z.qout[2 * tile + (wv - 2)] = 2.0 * sq;
     }
-    lds_barrier();
-    if (t == 0) z.qout[tile] = 2.0 * (qred[0] + qred[1]);
 }
 
 template <int TP, int G>
