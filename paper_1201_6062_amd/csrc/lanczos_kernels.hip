@@ -159,22 +159,53 @@ __global__ __launch_bounds__(64) void lz_expm_kernel(const double *alpha, const 
 // from the parts its launch left, the exponential, and y_j scaled by
 // beta0 / beta_{j-1} (beta_{-1} = beta0), so that c = sum_j y_j x_j over the
 // unnormalised vectors x_j. qin/ein/nin: the parts of x_{m-1}.
-__global__ __launch_bounds__(64) void lz_expm_fused_kernel(double *alpha, double *beta, double *beta0,
+constexpr int LZ_EXPM_FUSED_THREADS = 256;
+__global__ __launch_bounds__(LZ_EXPM_FUSED_THREADS) void lz_expm_fused_kernel(double *alpha, double *beta, double *beta0,
                                                            const double *qin, const double *ein, const double *nin,
                                                            int nq, int nseg, const double *fsample,
                                                            const double *dt_dev, double dt_arg, int m, double2 *y) {
-    const int j = threadIdx.x;
+    // the parts over the whole workgroup (up to four of each kind per
+    // thread in one round of loads), then the exponential on wave 0
+    __shared__ double red[3][LZ_EXPM_FUSED_THREADS / 64];
+    const int t = threadIdx.x, j = t;
     const double dt = dt_dev ? *dt_dev : dt_arg;
     const bool in = j < m;
     double qs = 0.0, es = 0.0, ns = 0.0;
-    for (int k = j; k < nq; k += 64) qs += qin[k];
-    for (int k = j; k < nseg; k += 64) {
-        es += ein[k];
-        ns += nin[k];
+    for (int k0 = 0; k0 < nq || k0 < nseg; k0 += 4 * LZ_EXPM_FUSED_THREADS) {
+        double qv[4], ev[4], nv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = k0 + r * LZ_EXPM_FUSED_THREADS + t;
+            qv[r] = k < nq ? qin[k] : 0.0;
+            ev[r] = k < nseg ? ein[k] : 0.0;
+            nv[r] = k < nseg ? nin[k] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            qs += qv[r];
+            es += ev[r];
+            ns += nv[r];
+        }
     }
     qs = wave_sum(qs);
     es = wave_sum(es);
     ns = wave_sum(ns);
+    if ((t & 63) == 0) {
+        red[0][t >> 6] = qs;
+        red[1][t >> 6] = es;
+        red[2][t >> 6] = ns;
+    }
+    __syncthreads();
+    if (t >= 64) return;
+    qs = red[0][0];
+    es = red[1][0];
+    ns = red[2][0];
+#pragma unroll
+    for (int w = 1; w < LZ_EXPM_FUSED_THREADS / 64; ++w) {
+        qs += red[0][w];
+        es += red[1][w];
+        ns += red[2][w];
+    }
     const double F = *fsample;
     // beta_{m-2} (beta0 for m = 1) with the breakdown rule, then alpha_{m-1}
     double blast = sqrt(ns);
@@ -390,7 +421,8 @@ hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0,
 hipError_t lz_expm_fused(double *alpha, double *beta, double *beta0, const double *qin, const double *ein,
                          const double *nin, int nq, int nseg, const double *fsample, double dt,
                          const double *dt_dev, int m, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(lz_expm_fused_kernel, dim3(1), dim3(64), 0, s, alpha, beta, beta0, qin, ein, nin, nq, nseg,
+    hipLaunchKernelGGL(lz_expm_fused_kernel, dim3(1), dim3(LZ_EXPM_FUSED_THREADS), 0, s, alpha, beta, beta0, qin, ein,
+                       nin, nq, nseg,
                        fsample, dt_dev, dt, m, reinterpret_cast<double2 *>(y));
     return hipGetLastError();
 }

@@ -668,8 +668,12 @@ __device__ __forceinline__ void lz_tile_body(const VecBuffers &b, const LzFused 
                         (size_t)tile * (VEC_TILE_MAX * VEC_TILE_MAX / 2) + wv * 16 * 64 + lane;
     constexpr int EARLY = TP <= 4 ? 16 : (TP <= 8 ? 8 : 0);
     double2 dv[16];
+    // (in consumption order: the products use loads 2k and 2k + 1 together)
 #pragma unroll
-    for (int r = 0; r < EARLY; ++r) dv[r] = Dt[r * 64];
+    for (int r = 0; r < EARLY; ++r) {
+        dv[r] = Dt[r * 64];
+        __builtin_amdgcn_sched_barrier(0);
+    }
     __builtin_amdgcn_sched_barrier(0);
     // sums of the parts (every workgroup, same order)
     double qs = (t < nq ? qv0 : 0.0) + (t2 < nq ? qv1 : 0.0);

@@ -43,6 +43,20 @@ def test_lanczos_matches_oracle(lmax, n, batch, m, nsteps):
     assert rel_l2(got, ref) <= TOL
 
 
+@pytest.mark.parametrize("lmax,n", [(2, 900), (1, 2048)])
+def test_lanczos_large_blocks(lmax, n):
+    """One pulse with N = 900 (8 tiles per block dimension) and N = 2048 (16,
+    the largest): the one-launch Krylov products with their run-time tile
+    counts; 3 steps of Krylov dimension 6."""
+    h = wl.hamiltonian(lmax, n, 8)
+    dt, nsteps, m = 0.02, 3, 6
+    f = samples(1, dt, nsteps)
+    c0 = wl.random_state(np.random.default_rng(n), h.nstates, 1)
+    got = make_plan(h.energies, h.dipole, 1).propagate(f, c0, dt, "lanczos", order=m).cpu().numpy()
+    ref = oracle.lanczos(h.energies, h.dipole, m, dt, f, c0, n=n)
+    assert rel_l2(got, ref) <= TOL
+
+
 def test_lanczos_many_segments():
     """One pulse with Lmax=520, N=130 (1042 segments of at most 128 states,
     2080 tiles; 67730 states): more norm and dot parts than one workgroup
