@@ -333,40 +333,46 @@ def velocity_measure(torch, steps: int = 2048):
             "GBps": bpp / per / 1e9, "frac_of_hbm_peak": bpp / per / 1e9 / HBM_PEAK_GBS}
 
 
-def adjoint_measure(torch, steps: int = 2048):
+def adjoint_measure(torch, steps: int = 2048, method: str = "rk4", order: int = 8):
     """The adjoint workload (32 pulses of piecewise-constant samples on the
     Lmax=15 N=500 Hamiltonian, RK4 dt=0.01, checkpoints every 64 steps), first
     `steps` steps: forward with checkpoints, then the reverse sweep (segment
-    recompute + adjoint stages). FP64 matrix-core rate over all 12 stages per step."""
+    recompute + adjoint stages). FP64 matrix-core rate over all 12 stages per
+    step. method="taylor": the same samples through the Taylor series of
+    `order` (3 * order products per step: forward, recompute, adjoint)."""
     from paper_1201_6062_amd import workloads as wl
     from paper_1201_6062_amd.api import Plan
     h = wl.hamiltonian(15, 500, 0)
     pulses = wl.adjoint_pulses(32)
     spi = wl.ADJ_STEPS_PER_INTERVAL
     ek = np.stack([wl.piecewise_samples(p) for p in pulses])[:, : max(1, steps // spi)]
-    f = torch.as_tensor(wl.expand_piecewise(ek, spi), device="cuda")
+    slots = 3 if method == "rk4" else 1
+    f = torch.as_tensor(wl.expand_piecewise(ek, spi, slots), device="cuda")
     nsteps = f.shape[1]
     c0 = torch.as_tensor(wl.ground_state(15, 500, 32), device="cuda")
     dt, batch = 0.01, 32
     plan = Plan(h.energies, h.dipole, batch=batch)
     en = torch.as_tensor(plan.energies, device="cuda")
     mask = (en > 0).to(torch.float64).repeat_interleave(2)
-    cT, ck = plan.propagate(f[:, :64], c0, dt, "rk4", ckpt_every=64)  # warm-up
-    plan.adjoint(f[:, :64], c0, dt, 2.0 * cT * mask[None, :], ckpt=ck, ckpt_every=64)
+    kw = dict(method=method, order=order)
+    cT, ck = plan.propagate(f[:, :64], c0, dt, ckpt_every=64, **kw)  # warm-up
+    plan.adjoint(f[:, :64], c0, dt, 2.0 * cT * mask[None, :], ckpt=ck, ckpt_every=64, **kw)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     ev[0].record()
-    cT, ck = plan.propagate(f, c0, dt, "rk4", ckpt_every=64)
+    cT, ck = plan.propagate(f, c0, dt, ckpt_every=64, **kw)
     ev[1].record()
-    g, l0 = plan.adjoint(f, c0, dt, 2.0 * cT * mask[None, :], ckpt=ck, ckpt_every=64)
+    g, l0 = plan.adjoint(f, c0, dt, 2.0 * cT * mask[None, :], ckpt=ck, ckpt_every=64, **kw)
     ev[2].record()
     torch.cuda.synchronize()
     tf, tb = ev[0].elapsed_time(ev[1]) / 1e3, ev[1].elapsed_time(ev[2]) / 1e3
     flop_stage = 8.0 * h.lmax * h.n * h.n * batch
-    stages = 12 * nsteps  # forward, recompute and adjoint: 4 stages each per step
+    per_step = 4 if method == "rk4" else order
+    stages = 3 * per_step * nsteps  # forward, recompute and adjoint products
     tflops = flop_stage * stages / (tf + tb) / 1e12
     plan.close()
-    return {"workload": f"{batch} pulses, Lmax=15 N=500, RK4 dt=0.01, piecewise-constant field, checkpoints "
+    name = "RK4" if method == "rk4" else f"Taylor-{order}"
+    return {"workload": f"{batch} pulses, Lmax=15 N=500, {name} dt=0.01, piecewise-constant field, checkpoints "
                         f"every 64 steps, first {nsteps} of {wl.ADJ_INTERVALS * spi} steps",
             "forward_s": tf, "reverse_s": tb, "reverse_over_forward": tb / tf,
             "state_steps_per_s": h.nstates * batch * nsteps / (tf + tb),
@@ -393,7 +399,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the small-problem and group measurements")
     ap.add_argument("--only", choices=["single", "diag", "batched", "small", "small_tiles", "group", "taylor8",
-                                       "lanczos", "lsweep", "adjoint", "rkf45", "velocity"], default=None,
+                                       "lanczos", "lsweep", "adjoint", "adjoint_taylor8", "rkf45", "velocity"],
+                    default=None,
                     help="profiling runs: measure one workload and print its record alone")
     ap.add_argument("--tile", default=None, help="batched tile TMxTN (tuning experiments)")
     ap.add_argument("--method", choices=["rk4", "taylor"], default="rk4")
@@ -423,6 +430,7 @@ def main():
             "lanczos": lambda: lanczos_measure(torch),
             "lsweep": lambda: lmax_sweep(torch),
             "adjoint": lambda: adjoint_measure(torch, steps=a.truncate or 2048),
+            "adjoint_taylor8": lambda: adjoint_measure(torch, steps=a.truncate or 512, method="taylor", order=8),
             "rkf45": lambda: rkf45_measure(torch, steps=a.truncate or 50),
             "velocity": lambda: velocity_measure(torch)}
     if a.only in only:
@@ -490,6 +498,7 @@ def main():
         out["single_taylor8"] = taylor8_measure(torch)
         out["lanczos"] = lanczos_measure(torch)
         out["adjoint"] = adjoint_measure(torch)
+        out["adjoint_taylor8"] = adjoint_measure(torch, steps=512, method="taylor", order=8)
         out["rkf45"] = rkf45_measure(torch)
         out["velocity_gauge"] = velocity_measure(torch)
     if not a.no_cpu_baseline:
