@@ -7,10 +7,13 @@
 // plan's own product kernels; these kernels do the per-pulse reductions,
 // the recurrence, the small exponential and the recombination. Vectors are in
 // the caller layout [pulse][2 n] (interleaved complex). With several pulses
-// the recurrence runs in one workgroup per pulse; a single pulse spreads it
-// over many workgroups: alpha from the completion launch's per-segment dots,
-// then one update launch per product, each Krylov vector normalised inside
-// its own product's completion launch. Every reduction has a fixed order.
+// the recurrence runs in one workgroup per pulse. A single pulse on a plan of
+// the fused tile path takes one launch per product (vec_lz_fused_kernel, over
+// unnormalised vectors, with alpha and the norms summed from parts the
+// previous launch left); on a split-path plan two: alpha from the completion
+// launch's per-segment dots, the update folded into the next product launch,
+// each vector normalised inside its own product's completion launch. Every
+// reduction has a fixed order.
 #include "tdse_internal.h"
 #include "tdse_reduce.h"
 
