@@ -203,14 +203,20 @@ def taylor8_measure(torch):
             "max_rel_err_vs_oracle": err}
 
 
-def lanczos_measure(torch, m: int = 12, dt: float = 0.05, steps: int = 256):
-    """Lmax=15, N=500 short-iterative Lanczos (Krylov dimension m, midpoint samples)."""
+def lanczos_measure(torch, m: int = 12, dt: float = 0.05, steps: int = 256, batch: int = 1):
+    """Lmax=15, N=500 short-iterative Lanczos (Krylov dimension m, midpoint
+    samples); batch > 1: that many pulses of one Hamiltonian (c3's pulse
+    distribution), the batched product."""
     from paper_1201_6062_amd import workloads as wl
     from paper_1201_6062_amd.api import Plan
     h = wl.hamiltonian(15, 500, 0)
-    plan = Plan(h.energies, h.dipole)
-    f = torch.as_tensor(wl.taylor_samples(wl.Pulse(0.05, 0.5, 20.0), dt, steps, "mid")[None], device="cuda")
-    c0 = torch.as_tensor(wl.ground_state(15, 500), device="cuda")
+    plan = Plan(h.energies, h.dipole, batch=batch)
+    if batch == 1:
+        fs = wl.taylor_samples(wl.Pulse(0.05, 0.5, 20.0), dt, steps, "mid")[None]
+    else:
+        fs = np.stack([wl.taylor_samples(p, dt, steps, "mid") for p in wl.random_pulses(np.random.default_rng(1), batch)])
+    f = torch.as_tensor(fs, device="cuda")
+    c0 = torch.as_tensor(wl.ground_state(15, 500, batch), device="cuda")
     plan.propagate(f[:, :64], c0, dt, "lanczos", order=m)  # warm-up, captures the 64-step chunk graph
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -220,8 +226,9 @@ def lanczos_measure(torch, m: int = 12, dt: float = 0.05, steps: int = 256):
     torch.cuda.synchronize()
     s = e0.elapsed_time(e1) / 1e3
     plan.close()
-    return {"workload": f"Lmax=15 N=500, Lanczos m={m}, dt={dt}, first {steps} steps of the 20-cycle pulse",
-            "state_steps_per_s": h.nstates * steps / s, "us_per_step": s / steps * 1e6,
+    what = "the 20-cycle pulse" if batch == 1 else f"{batch} pulses"
+    return {"workload": f"Lmax=15 N=500, Lanczos m={m}, dt={dt}, first {steps} steps of {what}",
+            "state_steps_per_s": h.nstates * batch * steps / s, "us_per_step": s / steps * 1e6,
             "us_per_product": s / (steps * m) * 1e6}
 
 
@@ -399,7 +406,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the small-problem and group measurements")
     ap.add_argument("--only", choices=["single", "diag", "batched", "small", "small_tiles", "group", "taylor8",
-                                       "lanczos", "lsweep", "adjoint", "adjoint_taylor8", "rkf45", "velocity"],
+                                       "lanczos", "lanczos_b8", "lsweep", "adjoint", "adjoint_taylor8", "rkf45",
+                                       "velocity"],
                     default=None,
                     help="profiling runs: measure one workload and print its record alone")
     ap.add_argument("--tile", default=None, help="batched tile TMxTN (tuning experiments)")
@@ -428,6 +436,7 @@ def main():
             "group": lambda: group_measure(torch, steps=a.truncate or 400),
             "taylor8": lambda: taylor8_measure(torch),
             "lanczos": lambda: lanczos_measure(torch),
+            "lanczos_b8": lambda: lanczos_measure(torch, batch=8, steps=64),
             "lsweep": lambda: lmax_sweep(torch),
             "adjoint": lambda: adjoint_measure(torch, steps=a.truncate or 2048),
             "adjoint_taylor8": lambda: adjoint_measure(torch, steps=a.truncate or 512, method="taylor", order=8),

@@ -20,33 +20,32 @@
 namespace tdse {
 
 constexpr int LZ_THREADS = 1024;
-
-// Sum of v over the workgroup (fixed tree order). red: LZ_THREADS doubles of LDS.
-__device__ __forceinline__ double lz_block_sum(double v, double *red) {
-    const int t = threadIdx.x;
-    red[t] = v;
-    __syncthreads();
-    for (int h = LZ_THREADS / 2; h > 0; h >>= 1) {
-        if (t < h) red[t] += red[t + h];
-        __syncthreads();
-    }
-    const double s = red[0];
-    __syncthreads();
-    return s;
-}
+// Loops over a pulse's vector take LZ_BATCH elements per thread at a time,
+// every load of a batch issued before its first use (a loop that used each
+// load at once would wait for every one in turn); within a thread the
+// elements are still combined in ascending order.
+constexpr int LZ_BATCH = 4;
 
 // beta0 = |c|, v_1 = c / beta0 (zero when c == 0). One workgroup per pulse.
 __global__ __launch_bounds__(LZ_THREADS) void lz_begin_kernel(const double *c, double *v1, double *beta0,
                                                               int64_t len) {
-    __shared__ double red[LZ_THREADS];
+    __shared__ double red[LZ_THREADS / 64];
     const int b = blockIdx.x;
     const double *cb = c + (size_t)b * len;
     double s = 0.0;
-    for (int64_t e = threadIdx.x; e < len; e += LZ_THREADS) s = fma(cb[e], cb[e], s);
-    const double nrm = sqrt(lz_block_sum(s, red));
+    int64_t e = threadIdx.x;
+    for (; e + (LZ_BATCH - 1) * LZ_THREADS < len; e += LZ_BATCH * LZ_THREADS) {
+        double x[LZ_BATCH];
+#pragma unroll
+        for (int r = 0; r < LZ_BATCH; ++r) x[r] = cb[e + r * LZ_THREADS];
+#pragma unroll
+        for (int r = 0; r < LZ_BATCH; ++r) s = fma(x[r], x[r], s);
+    }
+    for (; e < len; e += LZ_THREADS) s = fma(cb[e], cb[e], s);
+    const double nrm = sqrt(block_sum<LZ_THREADS>(s, red));
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
     double *vb = v1 + (size_t)b * len;
-    for (int64_t e = threadIdx.x; e < len; e += LZ_THREADS) vb[e] = cb[e] * inv;
+    for (e = threadIdx.x; e < len; e += LZ_THREADS) vb[e] = cb[e] * inv;
     if (threadIdx.x == 0) beta0[b] = nrm;
 }
 
@@ -58,26 +57,57 @@ __global__ __launch_bounds__(LZ_THREADS) void lz_begin_kernel(const double *c, d
 __global__ __launch_bounds__(LZ_THREADS) void lz_orth_kernel(const double *vj, const double *vjm1, double *w,
                                                              double *vnext, double *alpha, double *beta, int j,
                                                              int m, int last, int64_t len) {
-    __shared__ double red[LZ_THREADS];
+    __shared__ double red[LZ_THREADS / 64];
     const int b = blockIdx.x;
     const size_t off = (size_t)b * len;
+    // (for j = 0, pb points at v_j: never read then, but a valid address)
+    const double *vb = vj + off, *pb = j > 0 ? vjm1 + off : vb;
+    double *wb = w + off;
     double s = 0.0;
-    for (int64_t e = threadIdx.x; e < len; e += LZ_THREADS) s = fma(vj[off + e], w[off + e], s);
-    const double a = lz_block_sum(s, red);
+    int64_t e = threadIdx.x;
+    for (; e + (LZ_BATCH - 1) * LZ_THREADS < len; e += LZ_BATCH * LZ_THREADS) {
+        double x[LZ_BATCH], y[LZ_BATCH];
+#pragma unroll
+        for (int r = 0; r < LZ_BATCH; ++r) {
+            x[r] = vb[e + r * LZ_THREADS];
+            y[r] = wb[e + r * LZ_THREADS];
+        }
+#pragma unroll
+        for (int r = 0; r < LZ_BATCH; ++r) s = fma(x[r], y[r], s);
+    }
+    for (; e < len; e += LZ_THREADS) s = fma(vb[e], wb[e], s);
+    const double a = block_sum<LZ_THREADS>(s, red);
     const double bprev = j > 0 ? beta[(size_t)b * m + j - 1] : 0.0;
     double s2 = 0.0;
-    for (int64_t e = threadIdx.x; e < len; e += LZ_THREADS) {
-        double x = w[off + e] - a * vj[off + e];
-        if (j > 0) x -= bprev * vjm1[off + e];
-        w[off + e] = x;
+    e = threadIdx.x;
+    for (; e + (LZ_BATCH - 1) * LZ_THREADS < len; e += LZ_BATCH * LZ_THREADS) {
+        double x[LZ_BATCH], v[LZ_BATCH], p[LZ_BATCH];
+#pragma unroll
+        for (int r = 0; r < LZ_BATCH; ++r) {
+            x[r] = wb[e + r * LZ_THREADS];
+            v[r] = vb[e + r * LZ_THREADS];
+            p[r] = j > 0 ? pb[e + r * LZ_THREADS] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < LZ_BATCH; ++r) {
+            double xr = x[r] - a * v[r];
+            if (j > 0) xr -= bprev * p[r];
+            wb[e + r * LZ_THREADS] = xr;
+            s2 = fma(xr, xr, s2);
+        }
+    }
+    for (; e < len; e += LZ_THREADS) {
+        double x = wb[e] - a * vb[e];
+        if (j > 0) x -= bprev * pb[e];
+        wb[e] = x;
         s2 = fma(x, x, s2);
     }
     if (threadIdx.x == 0) alpha[(size_t)b * m + j] = a;
     if (last) return;
-    double bj = sqrt(lz_block_sum(s2, red));
+    double bj = sqrt(block_sum<LZ_THREADS>(s2, red));
     if (bj <= 1e-13 * (fabs(a) + bprev)) bj = 0.0;
     const double inv = bj > 0.0 ? 1.0 / bj : 0.0;
-    for (int64_t e = threadIdx.x; e < len; e += LZ_THREADS) vnext[off + e] = w[off + e] * inv;
+    for (e = threadIdx.x; e < len; e += LZ_THREADS) vnext[off + e] = wb[e] * inv;
     if (threadIdx.x == 0) beta[(size_t)b * m + j] = bj;
 }
 
@@ -245,7 +275,19 @@ __global__ void lz_combine_kernel(const double *V, size_t vstride, const double2
         const int b = (int)(g / ncplx);
         const int64_t e = g - (int64_t)b * ncplx;
         double sr = 0.0, si = 0.0;
-        for (int j = 0; j < m; ++j) {
+        int j = 0;
+        for (; j + 8 <= m; j += 8) {  // loads of eight vectors before their sums
+            double2 v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = reinterpret_cast<const double2 *>(V + (size_t)(j + q) * vstride)[g];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double2 yj = y[(size_t)b * m + j + q];
+                sr = fma(yj.x, v[q].x, fma(-yj.y, v[q].y, sr));
+                si = fma(yj.x, v[q].y, fma(yj.y, v[q].x, si));
+            }
+        }
+        for (; j < m; ++j) {
             const double2 yj = y[(size_t)b * m + j];
             const double2 v = reinterpret_cast<const double2 *>(V + (size_t)j * vstride)[g];
             sr = fma(yj.x, v.x, fma(-yj.y, v.y, sr));
