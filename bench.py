@@ -506,6 +506,7 @@ def main():
         out["uneven_group"] = group_measure(torch)
         out["single_taylor8"] = taylor8_measure(torch)
         out["lanczos"] = lanczos_measure(torch)
+        out["lanczos_8_pulses"] = lanczos_measure(torch, batch=8, steps=64)
         out["adjoint"] = adjoint_measure(torch)
         out["adjoint_taylor8"] = adjoint_measure(torch, steps=512, method="taylor", order=8)
         out["rkf45"] = rkf45_measure(torch)
