@@ -84,7 +84,7 @@ __device__ __forceinline__ int panel_off(int k, int x) {
 // when la is non-null. The restrict qualifiers tell the compiler that the
 // panels being read and the ones being filled do not overlap, so it does
 // not wait for the new loads before reading the current panels.
-template <int TM, int TN, int KC>
+template <int TM, int TN, int KC, bool PIN = false>
 __device__ __forceinline__ void bat_chunk(const char *__restrict__ la, const char *__restrict__ lb,
                                           char *__restrict__ wa, char *__restrict__ wb,
                                           const double *__restrict__ pa, const double *__restrict__ pb,
@@ -122,6 +122,12 @@ __device__ __forceinline__ void bat_chunk(const char *__restrict__ la, const cha
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
         if (ks + 1 < KC / 4) frag(ks + 1, (ks + 1) & 1);
+        // PIN: keep the next fragments' reads ahead of this k-step's products
+        // (the scheduler would otherwise sink them behind the products and
+        // wait for them at once). Measured: 26.9 -> 29.0 TFLOP/s on the
+        // 32-pulse grid (two K groups), 44.1 -> 43.4 on 256 pulses, so only
+        // the two-group kernels pin.
+        if constexpr (PIN) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int i = 0; i < C::SM; ++i)
 #pragma unroll
@@ -201,14 +207,14 @@ __global__ __launch_bounds__(256 * KS) __attribute__((amdgpu_waves_per_eu(1, 2))
     char(*lb)[C::B_BYTES] = lds_b[kg];
     if (niter > 0) {
         if (kcnt > 0)
-            bat_chunk<TM, TN, KC>(nullptr, nullptr, la[0], lb[0], a_src(kbeg), b_src(kbeg), Np, ldu, lane, wv, acc);
+            bat_chunk<TM, TN, KC, KS == 2>(nullptr, nullptr, la[0], lb[0], a_src(kbeg), b_src(kbeg), Np, ldu, lane, wv, acc);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         bat_lds_barrier();
         for (int q = 0; q < niter; ++q) {
             if (q < kcnt) {
                 const int buf = q & 1;
                 const bool next = q + 1 < kcnt;
-                bat_chunk<TM, TN, KC>(la[buf], lb[buf], next ? la[buf ^ 1] : nullptr, next ? lb[buf ^ 1] : nullptr,
+                bat_chunk<TM, TN, KC, KS == 2>(la[buf], lb[buf], next ? la[buf ^ 1] : nullptr, next ? lb[buf ^ 1] : nullptr,
                                       next ? a_src(kbeg + q + 1) : nullptr, next ? b_src(kbeg + q + 1) : nullptr, Np,
                                       ldu, lane, wv, acc);
             }
