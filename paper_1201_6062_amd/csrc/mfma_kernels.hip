@@ -107,32 +107,66 @@ __device__ __forceinline__ void bat_chunk(const char *__restrict__ la, const cha
     }
     if (!la) return;
     const int wy = wv >> 1, wx = wv & 1;
-    // fragments of k-step ks+1 are read while the products of ks run
-    double af[2][C::SM], bf[2][C::SN];
-    auto frag = [&](int ks, int slot) {
-        const int kr = ks * 4 + (lane >> 4);
+    if constexpr (!PIN) {
+        // fragments of k-step ks+1 are read while the products of ks run
+        double af[2][C::SM], bf[2][C::SN];
+        auto frag = [&](int ks, int slot) {
+            const int kr = ks * 4 + (lane >> 4);
 #pragma unroll
-        for (int i = 0; i < C::SM; ++i)
-            af[slot][i] = *reinterpret_cast<const double *>(la + panel_off<TM>(kr, wy * C::WM + i * 16 + (lane & 15)));
-#pragma unroll
-        for (int j = 0; j < C::SN; ++j)
-            bf[slot][j] = *reinterpret_cast<const double *>(lb + panel_off<TN>(kr, wx * C::WN + j * 16 + (lane & 15)));
-    };
-    frag(0, 0);
-#pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks) {
-        if (ks + 1 < KC / 4) frag(ks + 1, (ks + 1) & 1);
-        // PIN: keep the next fragments' reads ahead of this k-step's products
-        // (the scheduler would otherwise sink them behind the products and
-        // wait for them at once). Measured: 26.9 -> 29.0 TFLOP/s on the
-        // 32-pulse grid (two K groups), 44.1 -> 43.4 on 256 pulses, so only
-        // the two-group kernels pin.
-        if constexpr (PIN) __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int i = 0; i < C::SM; ++i)
+            for (int i = 0; i < C::SM; ++i)
+                af[slot][i] =
+                    *reinterpret_cast<const double *>(la + panel_off<TM>(kr, wy * C::WM + i * 16 + (lane & 15)));
 #pragma unroll
             for (int j = 0; j < C::SN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks & 1][i], bf[ks & 1][j], acc[i][j], 0, 0, 0);
+                bf[slot][j] =
+                    *reinterpret_cast<const double *>(lb + panel_off<TN>(kr, wx * C::WN + j * 16 + (lane & 15)));
+        };
+        frag(0, 0);
+#pragma unroll
+        for (int ks = 0; ks < KC / 4; ++ks) {
+            if (ks + 1 < KC / 4) frag(ks + 1, (ks + 1) & 1);
+#pragma unroll
+            for (int i = 0; i < C::SM; ++i)
+#pragma unroll
+                for (int j = 0; j < C::SN; ++j)
+                    acc[i][j] =
+                        __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks & 1][i], bf[ks & 1][j], acc[i][j], 0, 0, 0);
+        }
+    } else {
+        // PIN (kernels with two K groups, the skinny grids of few pulses):
+        // the fragments of k-step ks+2 are read while the products of ks run,
+        // from a ring of three sets, and a scheduling barrier keeps the reads
+        // ahead of the products (the scheduler would otherwise sink them
+        // behind the products and wait for them at once). At 256 pulses the
+        // one-group kernels keep the compiler's schedule: the barrier cost
+        // 1.6% there.
+        constexpr int D = 2, NSLOT = 3;
+        double af[NSLOT][C::SM], bf[NSLOT][C::SN];
+        auto frag = [&](int ks, int slot) {
+            const int kr = ks * 4 + (lane >> 4);
+#pragma unroll
+            for (int i = 0; i < C::SM; ++i)
+                af[slot][i] =
+                    *reinterpret_cast<const double *>(la + panel_off<TM>(kr, wy * C::WM + i * 16 + (lane & 15)));
+#pragma unroll
+            for (int j = 0; j < C::SN; ++j)
+                bf[slot][j] =
+                    *reinterpret_cast<const double *>(lb + panel_off<TN>(kr, wx * C::WN + j * 16 + (lane & 15)));
+        };
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            if (d < KC / 4) frag(d, d);
+#pragma unroll
+        for (int ks = 0; ks < KC / 4; ++ks) {
+            if (ks + D < KC / 4) frag(ks + D, (ks + D) % NSLOT);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < C::SM; ++i)
+#pragma unroll
+                for (int j = 0; j < C::SN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks % NSLOT][i], bf[ks % NSLOT][j], acc[i][j],
+                                                                     0, 0, 0);
+        }
     }
 }
 
