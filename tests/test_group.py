@@ -4,7 +4,7 @@ import os
 
 import numpy as np
 import pytest
-import torch  # noqa: F401
+import torch
 
 import oracle
 from paper_1201_6062_amd import workloads as wl
@@ -67,6 +67,57 @@ def test_group_full_length_sampled_instances():
         gold = np.load(os.path.join(HERE, "golden", f"uneven_inst{i:02d}.npz"), allow_pickle=False)
         assert int(gold["nsteps"]) == specs[i].nsteps
         assert rel_l2(o.cpu().numpy(), gold["cT"]) <= TOL
+
+
+@pytest.fixture(scope="module")
+def uneven64():
+    """The 64-instance uneven workload: specs, Hamiltonians' plans, full-length samples, c0."""
+    specs = wl.uneven_specs(64)
+    plans, fs, cs = [], [], []
+    for s in specs:
+        h = wl.hamiltonian(s.lmax, s.n, s.seed)
+        plans.append(plan_of(h))
+        fs.append(torch.as_tensor(wl.rk4_samples(s.pulse, 0.005, s.nsteps), device="cuda"))
+        cs.append(torch.as_tensor(wl.ground_state(s.lmax, s.n)[0], device="cuda"))
+    yield specs, plans, fs, cs
+    for p in plans:
+        p.close()
+
+
+def test_group_all64_first_200_steps(uneven64):
+    """All 64 instances in one group for the first 200 steps of their pulses
+    (the schedule the benchmark times, every instance active): sampled
+    entries (every block, both ends and 12 seeded positions each), |c|^2 and
+    sum E|c|^2 against the stored oracle results."""
+    from paper_1201_6062_amd.api import Group
+    specs, plans, fs, cs = uneven64
+    gold = np.load(os.path.join(HERE, "golden", "uneven_prefix200.npz"), allow_pickle=False)
+    steps = int(gold["steps"])
+    out = Group(plans).propagate([f[:steps] for f in fs], cs, 0.005)
+    for i, (s, o) in enumerate(zip(specs, out)):
+        z = o.cpu().numpy().reshape(-1, 2)
+        idx, ref = gold[f"idx{i:02d}"], gold[f"val{i:02d}"]
+        assert rel_l2(z[idx], ref) <= TOL, i
+        assert abs((z * z).sum() - gold[f"norm2_{i:02d}"]) <= 1e-12, i
+        en = wl.energies(s.lmax, s.n)
+        e = ((z * z).sum(1) * en).sum()
+        assert abs(e - gold[f"energy_{i:02d}"]) <= 1e-11 * max(1.0, abs(e)), i
+
+
+@pytest.mark.timeout(600)
+def test_group_all64_full_length(uneven64):
+    """All 64 instances in one group, each over its whole pulse (13230 to
+    60461 steps), as one call: the smallest instance (#28, N=210), the largest
+    (#38, Lmax=31, N=923), #30 (N=986) and #16, #21, #39 against their stored
+    full-length oracle results."""
+    from paper_1201_6062_amd.api import Group
+    specs, plans, fs, cs = uneven64
+    out = Group(plans).propagate(fs, cs, 0.005)
+    torch.cuda.synchronize()
+    for i in (28, 38, 30, 16, 21, 39):
+        gold = np.load(os.path.join(HERE, "golden", f"uneven_inst{i:02d}.npz"), allow_pickle=False)
+        assert int(gold["nsteps"]) == specs[i].nsteps
+        assert rel_l2(out[i].cpu().numpy(), gold["cT"]) <= TOL, i
 
 
 def test_group_repeated_calls_reuse_graphs():

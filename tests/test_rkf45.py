@@ -44,6 +44,24 @@ def test_rkf45_matches_oracle(lmax, n, batch, nsteps, dt):
         assert np.abs(err[b] - eref[0]).max() <= 1e-6 * np.abs(eref).max()
 
 
+def test_rkf45_256_pulses_sampled():
+    """The shape the benchmark times: 256 pulses on the Lmax=15, N=500
+    Hamiltonian (the 128x64 tile grid with one K group), three steps taken from
+    the middle of the pulses (the field is strong there) from random states;
+    pulses 0, 85, 170 and 255 and their error estimates vs the oracle."""
+    h, dt, k0, nsteps, batch = wl.hamiltonian(15, 500, 0), 0.005, 20000, 3, 256
+    pulses = wl.random_pulses(np.random.default_rng(1), batch)
+    f = np.stack([wl.rkf45_samples(p, dt, k0 + nsteps)[k0:] for p in pulses])
+    assert np.abs(f).max() > 0.02  # a field well away from zero in this window
+    c0 = wl.random_state(np.random.default_rng(11), h.nstates, batch)
+    cT, err = make_plan(h.energies, h.dipole, batch).propagate_rkf45(f, c0, dt)
+    cT, err = cT.cpu().numpy(), err.cpu().numpy()
+    for b in (0, 85, 170, 255):
+        ref, eref = oracle.rkf45(h.energies, h.dipole, dt, f[b:b + 1], c0[b:b + 1])
+        assert rel_l2(cT[b:b + 1], ref) <= TOL, b
+        assert np.abs(err[b] - eref[0]).max() <= 1e-6 * np.abs(eref).max(), b
+
+
 def test_rkf45_velocity_gauge_and_checkpoints():
     h = wl.hamiltonian(2, 40, 4)
     q = wl.velocity_coupling(h.energies, h.dipole)
