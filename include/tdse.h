@@ -169,6 +169,53 @@ tdse_status tdse_propagate_rkf45(tdse_plan plan, double dt, int64_t nsteps, cons
                                  double *cT, double *err, double *ckpt, int32_t ckpt_every, void *stream);
 
 /*
+ * Step-size control on the Runge-Kutta-Fehlberg error estimate (the embedded
+ * pair of appendix B's explicit family): from c0 at t = 0 to t_final, one
+ * step at a time. For each attempted step of size h from time t the library
+ * calls field_fn(t, h, samples, ctx), which fills samples (host,
+ * [batch][6]) with the field (or vector potential) at the six stage times
+ * t + c_i h, c = (0, 1/4, 3/8, 12/13, 1, 1/2); runs one tdse_propagate_rkf45
+ * step; and accepts it when every pulse's estimate is <= tol (or h <= dt_min).
+ * The next size is max(dt_min, h min(2, max(0.2, 0.9 (tol/err)^(1/5))))
+ * (2 h when err == 0); the last step is shortened to end at t_final.
+ * c0, cT: [batch][2*nstates] device (may alias). steps: NULL or host
+ * [max_steps], receiving the accepted step sizes; *nsteps_taken (host) their
+ * count. max_steps bounds the attempted steps: TDSE_E_INVAL if t_final is not
+ * reached within them (cT then holds the state at the last accepted step).
+ * Synchronous: it reads every step's estimate back to the host. Batch-1 plans
+ * run on their batched twin. The workspace (six samples and two states per
+ * pulse) is allocated on first use and kept by the plan. Errors: TDSE_E_INVAL
+ * (null plan, field_fn or nsteps_taken, non-finite or non-positive t_final,
+ * dt0, dt_min or tol, device arguments as tdse_propagate), TDSE_E_NOMEM.
+ */
+typedef void (*tdse_field_fn)(double t, double h, double *samples, void *ctx);
+tdse_status tdse_propagate_adaptive(tdse_plan plan, double t_final, double dt0, double tol, double dt_min,
+                                    int64_t max_steps, tdse_field_fn field_fn, void *ctx, const double *c0,
+                                    double *cT, double *steps, int64_t *nsteps_taken, void *stream);
+
+/*
+ * Stability test of a step size (appendix B's step maps on the imaginary
+ * axis): one step multiplies each eigencomponent of H(F) by R(-i dt lambda),
+ * R the method's stability polynomial (the Taylor polynomial of degree 4 for
+ * RK4 and of degree p for Taylor-p; 1 + sum_k b^T A^(k-1) 1 z^k for the
+ * Fehlberg pair's fourth-order solution). With theta = dt (max|E| + |fmax|
+ * ||D||), ||D|| bounded by the largest absolute row sum of the coupling
+ * (computed at plan creation), returns TDSE_OK when |R(i s)|^2 <= 1 + 1e-14
+ * for every |s| <= theta, else TDSE_E_UNSTABLE (tdse_last_error gives the
+ * numbers). RK4: the bound is 2 sqrt(2); Taylor orders 1, 2 (mod 4) and the
+ * Fehlberg pair amplify every oscillation, so their bounds are set by the
+ * 1e-14 allowance; Lanczos is unitary (always TDSE_OK). theta and bound
+ * (host, either may be NULL) receive the two numbers. Host only; nothing is
+ * enqueued. This is the optional pre-check of a propagation: the propagation
+ * entry points do not apply it themselves (a step outside the interval is
+ * still the well-defined discrete map, which short runs and tests may want).
+ * Errors: TDSE_E_INVAL (null plan, unknown method, order out of range, dt
+ * not finite and > 0, fmax not finite).
+ */
+tdse_status tdse_check_stability(tdse_plan plan, tdse_method method, int32_t taylor_order, double dt, double fmax,
+                                 double *theta, double *bound);
+
+/*
  * Discrete adjoint of tdse_propagate, for RK4 and for the Taylor series of
  * order taylor_order (appendix B steps run backwards: the co-states of the
  * RK4 stage derivatives, or of the Taylor terms Tbar_{m-1} = lambda +

@@ -33,6 +33,8 @@ SIGNATURES = {
     "tdse_hmul": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "tdse_propagate": (_st, [_vp, _st, _i32, _d, _i64, _vp, _vp, _vp, _vp, _i32, _vp]),
     "tdse_propagate_rkf45": (_st, [_vp, _d, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "tdse_propagate_adaptive": (_st, [_vp, _d, _d, _d, _d, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i64), _vp]),
+    "tdse_check_stability": (_st, [_vp, _st, _i32, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "tdse_adjoint": (_st, [_vp, _st, _i32, _d, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "tdse_group_create": (_st, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _vp]),
     "tdse_group_propagate": (_st, [_vp, _st, _i32, _d, ctypes.POINTER(_i64), ctypes.POINTER(_vp),
@@ -40,6 +42,9 @@ SIGNATURES = {
     "tdse_group_destroy": (_st, [_vp]),
     "tdse_tune": (_st, [_i32, _i32, _i32, ctypes.c_char_p]),
 }
+
+# void (*tdse_field_fn)(double t, double h, double *samples, void *ctx)
+FIELD_FN = ctypes.CFUNCTYPE(None, _d, _d, ctypes.POINTER(_d), _vp)
 
 _lib = None
 

@@ -133,26 +133,36 @@ class Plan:
 
     def propagate_adaptive(self, field_fn, c0, t_final: float, dt0: float, tol: float,
                            dt_min: float = 1e-6, max_steps: int = 100000):
-        """Optional step-size control on top of the Runge-Kutta-Fehlberg error
-        estimate: one step at a time, field_fn(t) giving the field (or vector
-        potential) at an array of times [B, ...]; a step is accepted when every
-        pulse's estimate is <= tol, and the next dt is 0.9 dt (tol / err)^(1/5),
-        clipped to [dt/5, 2 dt]. Returns (c(t_final), accepted step sizes)."""
-        c = self._state(c0).clone()
-        t, dt, steps = 0.0, float(dt0), []
+        """tdse_propagate_adaptive: Runge-Kutta-Fehlberg steps with the
+        library's step-size control. field_fn(t) gives the field (or vector
+        potential) at an array of times; broadcast to [B, 6] per step.
+        Returns (c(t_final), accepted step sizes)."""
+        c0 = self._state(c0)
+        cT = torch.empty_like(c0)
+        steps = np.zeros(max(int(max_steps), 1), dtype=np.float64)
+        taken = ctypes.c_int64(0)
         slots = np.array(RKF45_SLOTS)
-        while t < t_final * (1.0 - 1e-14) and len(steps) < max_steps:
-            h = min(dt, t_final - t)
+        batch = self.batch
+
+        def fill(t, h, samples, _ctx):
             f = np.asarray(field_fn(t + slots * h), dtype=np.float64)
-            f = np.array(np.broadcast_to(f, (self.batch, 6))).reshape(self.batch, 1, 6)
-            cn, err = self.propagate_rkf45(f, c, h)
-            e = float(err.max().item())
-            if e <= tol or h <= dt_min:
-                c, t = cn, t + h
-                steps.append(h)
-            fac = 2.0 if e == 0.0 else min(2.0, max(0.2, 0.9 * (tol / e) ** 0.2))
-            dt = max(dt_min, h * fac)
-        return c, steps
+            np.ctypeslib.as_array(samples, shape=(batch * 6,))[:] = np.broadcast_to(f, (batch, 6)).reshape(-1)
+
+        cb = _capi.FIELD_FN(fill)
+        check(self._lib.tdse_propagate_adaptive(self._h, float(t_final), float(dt0), float(tol), float(dt_min),
+                                                int(max_steps), cb, None, _ptr(c0), _ptr(cT),
+                                                steps.ctypes.data_as(ctypes.c_void_p), ctypes.byref(taken),
+                                                _stream(self.device)))
+        return cT, list(steps[: taken.value])
+
+    def check_stability(self, method: str, dt: float, fmax: float = 0.0, order: int = 8):
+        """tdse_check_stability: (stable?, theta = dt (max|E| + |fmax| ||D||), the method's bound)."""
+        th, bd = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        st = self._lib.tdse_check_stability(self._h, METHODS[method], int(order), float(dt), float(fmax),
+                                            ctypes.byref(th), ctypes.byref(bd))
+        if st not in (_capi.TDSE_OK, _capi.TDSE_E_UNSTABLE):
+            check(st)
+        return st == _capi.TDSE_OK, th.value, bd.value
 
     def adjoint(self, field, c0, dt: float, lambda_t, ckpt=None, ckpt_every: int = 64,
                 method: str = "rk4", order: int = 8, want_lambda0: bool = True):

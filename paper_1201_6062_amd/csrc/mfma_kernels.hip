@@ -422,6 +422,287 @@ __global__ __launch_bounds__(256 * KS) __attribute__((amdgpu_waves_per_eu(1, 2))
     }
 }
 
+// ---------------------------------------------------------------------------
+// Small batches (2B <= 64 real columns): one workgroup of eight waves per
+// 32-row tile and all columns, the contraction (both neighbour blocks, K =
+// 2 Np) split into eight contiguous k ranges, one per wave. A wave streams its
+// operands from global memory straight into registers -- no LDS staging and no
+// barrier inside the k loop -- keeping DEPTH k-steps of loads in flight, and
+// runs 4 NG MFMAs per k-step on them. Every operand is k-major (D^T rows for
+// the row use of D_m, D rows for the transposed use of D_{m-1}, U rows), so
+// one 16-byte load per lane covers four k rows of 32 consecutive entries:
+// lane 16q + i takes entries 2i, 2i + 1 of row k0 + q. For A that is two
+// 16-row MFMA operands (the even and the odd rows of the tile); for U the
+// real and the imaginary column of 16 pulses. The eight partial tiles are
+// summed in LDS in wave order (a fixed order: bitwise reproducible) and the
+// epilogue -- the same completions as the kernel above, on complex entries --
+// is spread over all 512 threads, each owning whole (row, pulse) entries.
+template <int NG>
+struct SkinnyTile {
+    static constexpr int TM = 32, TN = 32 * NG, WAVES = 8;
+    static constexpr int NACC = 2 * NG * 2;          // (row parity, column group, re/im)
+    static constexpr int SLOTS = NACC * 4;           // doubles of accumulator per lane
+};
+
+template <int NG, bool ADJ, int DEPTH, int CHUNK>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void bat_skinny_kernel(BatBuffers b,
+                                                                                                    BatLaunch L) {
+    static_assert(CHUNK % DEPTH == 0, "a chunk holds whole rounds of the load ring");
+    using S = SkinnyTile<NG>;
+    const int Np = b.np, ldu = b.ldu, lmax = b.lmax;
+    const int RT = Np / S::TM, CT = ldu / S::TN;
+    const int ntiles = (lmax + 1) * RT * CT;
+    const int w = blockIdx.x;
+    const int xcd = w & 7, per = ntiles >> 3, extra = ntiles & 7;
+    const int tile = xcd * per + (xcd < extra ? xcd : extra) + (w >> 3);
+    const int m = tile / (RT * CT), rem = tile - m * RT * CT, rt = rem / CT, ct = rem - rt * CT;
+    const int r0 = rt * S::TM, c0 = ct * S::TN;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform: buffer descriptors stay scalar
+    const int q = lane >> 4, li = lane & 15;
+    const double *U = L.parity ? b.u[1] : b.u[0];
+
+    // ---- this wave's k range: with both neighbour blocks, waves 0-3 split the
+    // row use of D_m and waves 4-7 the transposed use of D_{m-1}; with one,
+    // all eight split it.
+    const bool has_up = m < lmax, has_dn = m > 0;
+    const int nks = Np / 4;
+    const bool up = (has_up && has_dn) ? wv < 4 : has_up;
+    const int nparts = (has_up && has_dn) ? 4 : 8, part = (has_up && has_dn) ? (wv & 3) : wv;
+    // k-steps [ks0, ks0 + len) of the block, by the balanced split of Sec. 4.1
+    const int len = (has_up || has_dn) ? (int)split_len(nks, nparts, part) : 0;
+    const int ks0 = (has_up || has_dn) ? (int)split_start(nks, nparts, part) : 0;
+    const size_t blk = (size_t)Np * Np;
+    const double *A = up ? b.dT + (size_t)(has_up ? m : 0) * blk : b.d + (size_t)(has_dn ? m - 1 : 0) * blk;
+    const double *Bm = U + (size_t)(up ? (has_up ? m + 1 : 0) : (has_dn ? m - 1 : 0)) * Np * ldu;
+    // Raw buffer loads: the descriptor of k-step ks starts at that step's
+    // first row and covers the rows left in this wave's range, so a load past
+    // the range (the look-ahead of the last k-steps) returns zeros without
+    // touching memory; every load is issued either way and the wait counts
+    // stay exact. Base and size are scalar, the lane offset is one register.
+    const double *A0 = A + (size_t)4 * ks0 * Np, *B0 = Bm + (size_t)4 * ks0 * ldu;
+    const int oa = (q * Np + r0 + 2 * li) * 8, ob = (q * ldu + c0 + 2 * li) * 8;  // lane byte offsets
+    auto rsrc = [&](const double *base, int ks, int ld) {
+        const int left = len - ks;
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(base) + (size_t)ks * 4 * ld, 0,
+                                                 left > 0 ? left * 4 * ld * 8 : 0, 0x00020000);
+    };
+
+    d4_t acc[2][NG][2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int g = 0; g < NG; ++g) acc[p][g][0] = acc[p][g][1] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    if (len > 0) {
+        dv2b_t ra[DEPTH], rb[DEPTH][NG];
+        auto load = [&](int slot, int ks) {
+            ra[slot] = __builtin_bit_cast(dv2b_t, __builtin_amdgcn_raw_buffer_load_b128(rsrc(A0, ks, Np), oa, 0, 0));
+            const __amdgpu_buffer_rsrc_t rb_s = rsrc(B0, ks, ldu);
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+                rb[slot][g] = __builtin_bit_cast(dv2b_t, __builtin_amdgcn_raw_buffer_load_b128(rb_s, ob + 256 * g, 0, 0));
+        };
+        auto mfmas = [&](int slot) {
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int g = 0; g < NG; ++g)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+                        acc[p][g][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[slot][p], rb[slot][g][c], acc[p][g][c],
+                                                                            0, 0, 0);
+        };
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) load(d, d);
+        // CHUNK k-steps fully unrolled per trip (the launcher picks CHUNK >=
+        // the longest k range, so a wave normally makes one trip: at a loop
+        // back edge the compiler waits for every load in flight). A range
+        // shorter than the chunk ends with products of the zeros that the
+        // loads past it returned.
+        for (int ks = 0; ks < len; ks += CHUNK) {
+#pragma unroll
+            for (int d = 0; d < CHUNK; ++d) {
+                mfmas(d % DEPTH);
+                load(d % DEPTH, ks + DEPTH + d);
+                // keep each slot's reload right behind its products (the
+                // scheduler would otherwise gather the reloads at the end)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+
+    // ---- epilogue operands of this thread's entries, requested before the
+    // reduction so their latency overlaps it. Thread (v, lane) owns the
+    // accumulator slots P = NPER v .. NPER v + NPER - 1 of every wave, P =
+    // ((g 2 + p) 4 + r): rows r0 + 2 (q + 4 r) + p, pulse c0/2 + 16 g + li.
+    constexpr int NPER = 2 * NG * 4 / 8;  // (g, p, r) slots per thread: 2 (NG = 2) or 1
+    const int B = b.batch;
+    double *Un = L.parity ? b.u[0] : b.u[1];
+    size_t gi[NPER];
+    int row[NPER], pulse[NPER];
+    dv2b_t uo[NPER], cc[NPER], aa[NPER], us[NPER];
+    double E0[NPER], F[NPER];
+#pragma unroll
+    for (int e = 0; e < NPER; ++e) {
+        const int P = NPER * wv + e, g = P >> 3, p = (P >> 2) & 1, r = P & 3;
+        row[e] = r0 + 2 * (q + 4 * r) + p;
+        pulse[e] = c0 / 2 + 16 * g + li;
+        gi[e] = ((size_t)m * Np + row[e]) * ldu + 2 * pulse[e];
+        uo[e] = *reinterpret_cast<const dv2b_t *>(U + gi[e]);
+        cc[e] = *reinterpret_cast<const dv2b_t *>(b.c + gi[e]);
+        aa[e] = (ADJ || !L.first || L.kind == CK_RK4_END || L.kind == CK_RKF) ? *reinterpret_cast<const dv2b_t *>(b.acc + gi[e])
+                                                                              : dv2b_t{0.0, 0.0};
+        us[e] = (ADJ && L.ustore) ? *reinterpret_cast<const dv2b_t *>(L.ustore + gi[e]) : dv2b_t{0.0, 0.0};
+        E0[e] = b.en[(size_t)m * Np + row[e]];
+        F[e] = pulse[e] < B ? b.field[((size_t)pulse[e] * L.nsteps + L.step) * L.slots + L.slot] : 0.0;
+    }
+
+    // ---- fixed-order sum of the eight partial tiles
+    __shared__ double red[S::WAVES][S::SLOTS][64];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) red[wv][((((g * 2 + p) * 4 + r) * 2) + c)][lane] = acc[p][g][c][r];
+    bat_lds_barrier();
+    const double dt = L.dt;
+    double gsum = 0.0;  // this thread's part of the pulse's tile partial (adjoint, RKF error)
+#pragma unroll
+    for (int e = 0; e < NPER; ++e) {
+        const int P = NPER * wv + e;
+        double cr = 0.0, ci = 0.0;
+#pragma unroll
+        for (int k = 0; k < S::WAVES; ++k) {
+            cr += red[k][2 * P][lane];
+            ci += red[k][2 * P + 1][lane];
+        }
+        // coupling product z of this entry; velocity gauge: -i times the contraction
+        const double zr = b.gauge ? ci : cr, zi = b.gauge ? -cr : ci;
+        const double ur = uo[e][0], ui = uo[e][1];
+        const bool live = pulse[e] < B && row[e] < b.n;
+        if constexpr (ADJ) {
+            // ubar = i (E0 kbar + F w); gradient part Im(w^H u) = w_re u_im - w_im u_re
+            const double ubr = -fma(F[e], zi, E0[e] * ui), ubi = fma(F[e], zr, E0[e] * ur);
+            gsum = fma(zr, us[e][1], gsum);
+            gsum = fma(-zi, us[e][0], gsum);
+            const double lr = cc[e][0], lim = cc[e][1];
+            const double cbr = (L.first ? lr : aa[e][0]) + ubr, cbi = (L.first ? lim : aa[e][1]) + ubi;
+            if (L.kind == CK_ADJ_MID) {
+                *reinterpret_cast<dv2b_t *>(b.acc + gi[e]) = dv2b_t{cbr, cbi};
+                *reinterpret_cast<dv2b_t *>(Un + gi[e]) =
+                    dv2b_t{fma(L.p_lam, lr, L.p_ub * ubr), fma(L.p_lam, lim, L.p_ub * ubi)};
+            } else {
+                *reinterpret_cast<dv2b_t *>(b.c + gi[e]) = dv2b_t{cbr, cbi};
+                *reinterpret_cast<dv2b_t *>(Un + gi[e]) = dv2b_t{L.p_lam * cbr, L.p_lam * cbi};
+            }
+        } else {
+            // y = E0 u + F z, k = -i y
+            const double yr = fma(F[e], zr, E0[e] * ur), yi = fma(F[e], zi, E0[e] * ui);
+            const double kr = yi, ki = -yr;
+            if (L.kind == CK_HMUL) {
+                if (live)
+                    *reinterpret_cast<dv2b_t *>(L.out + (size_t)pulse[e] * 2 * (lmax + 1) * b.n +
+                                                2 * ((size_t)m * b.n + row[e])) = dv2b_t{yr, yi};
+                continue;
+            }
+            if (L.ustore) *reinterpret_cast<dv2b_t *>(L.ustore + gi[e]) = uo[e];
+            double c_r = cc[e][0], c_i = cc[e][1], a_r = aa[e][0], a_i = aa[e][1], n_r, n_i;
+            switch (L.kind) {
+            case CK_RK4_MID: {
+                a_r = L.first ? L.w_acc * kr : fma(L.w_acc, kr, a_r);
+                a_i = L.first ? L.w_acc * ki : fma(L.w_acc, ki, a_i);
+                const double ad = L.a_next * dt;
+                n_r = fma(ad, kr, c_r);
+                n_i = fma(ad, ki, c_i);
+                *reinterpret_cast<dv2b_t *>(b.acc + gi[e]) = dv2b_t{a_r, a_i};
+                break;
+            }
+            case CK_RK4_END:
+                c_r = fma(dt, fma(L.w_acc, kr, a_r), c_r);
+                c_i = fma(dt, fma(L.w_acc, ki, a_i), c_i);
+                n_r = c_r;
+                n_i = c_i;
+                *reinterpret_cast<dv2b_t *>(b.c + gi[e]) = dv2b_t{c_r, c_i};
+                break;
+            case CK_TAY_MID: {
+                const double tr = L.a_next * dt * kr, ti = L.a_next * dt * ki;
+                a_r = (L.first ? c_r : a_r) + tr;
+                a_i = (L.first ? c_i : a_i) + ti;
+                n_r = tr;
+                n_i = ti;
+                *reinterpret_cast<dv2b_t *>(b.acc + gi[e]) = dv2b_t{a_r, a_i};
+                break;
+            }
+            case CK_RKF: {
+                const int st = L.slot;
+                const size_t kstride = (size_t)(lmax + 1) * Np * ldu;
+                double sr = 0.0, si = 0.0, er = 0.0, ei = 0.0;
+                for (int qq = 0; qq < st; ++qq) {
+                    const dv2b_t kq = *reinterpret_cast<const dv2b_t *>(b.kst + (size_t)qq * kstride + gi[e]);
+                    const double wgt = st < 5 ? RKF_A[st + 1][qq] : RKF_B4[qq];
+                    sr = fma(wgt, kq[0], sr);
+                    si = fma(wgt, kq[1], si);
+                    er = fma(RKF_E[qq], kq[0], er);
+                    ei = fma(RKF_E[qq], kq[1], ei);
+                }
+                if (st < 5) {
+                    *reinterpret_cast<dv2b_t *>(b.kst + (size_t)st * kstride + gi[e]) = dv2b_t{kr, ki};
+                    n_r = fma(dt, fma(RKF_A[st + 1][st], kr, sr), c_r);
+                    n_i = fma(dt, fma(RKF_A[st + 1][st], ki, si), c_i);
+                } else {
+                    c_r = fma(dt, fma(RKF_B4[5], kr, sr), c_r);
+                    c_i = fma(dt, fma(RKF_B4[5], ki, si), c_i);
+                    const double xr = dt * fma(RKF_E[5], kr, er), xi = dt * fma(RKF_E[5], ki, ei);
+                    gsum = fma(xr, xr, gsum);
+                    gsum = fma(xi, xi, gsum);
+                    n_r = c_r;
+                    n_i = c_i;
+                    *reinterpret_cast<dv2b_t *>(b.c + gi[e]) = dv2b_t{c_r, c_i};
+                }
+                break;
+            }
+            default: {  // CK_TAY_END
+                const double tr = L.a_next * dt * kr, ti = L.a_next * dt * ki;
+                c_r = (L.first ? c_r : a_r) + tr;
+                c_i = (L.first ? c_i : a_i) + ti;
+                n_r = c_r;
+                n_i = c_i;
+                *reinterpret_cast<dv2b_t *>(b.c + gi[e]) = dv2b_t{c_r, c_i};
+                break;
+            }
+            }
+            *reinterpret_cast<dv2b_t *>(Un + gi[e]) = dv2b_t{n_r, n_i};
+            const bool ends = L.kind == CK_RK4_END || L.kind == CK_TAY_END || (L.kind == CK_RKF && L.slot == 5);
+            if (L.ckpt && ends && live)
+                *reinterpret_cast<dv2b_t *>(L.ckpt + ((size_t)pulse[e] * L.ckpt_rows + L.ckpt_row) * 2 *
+                                                         (size_t)(lmax + 1) * b.n +
+                                            2 * ((size_t)m * b.n + row[e])) = dv2b_t{c_r, c_i};
+        }
+    }
+    if (ADJ || (L.kind == CK_RKF && L.slot == 5 && L.gpart != nullptr)) {
+        // per-pulse sum over the tile's 32 rows: the thread's own entries, the
+        // four row groups q of the wave, then (in LDS, in wave order) the waves
+        // holding the same column group
+        gsum += __shfl_xor(gsum, 16);
+        gsum += __shfl_xor(gsum, 32);
+        __shared__ double gred[S::WAVES][16];
+        if (lane < 16) gred[wv][lane] = gsum;
+        bat_lds_barrier();
+        constexpr int WPG = S::WAVES / NG;  // waves per column group
+        if (t < S::TN / 2) {
+            const int g = t >> 4, j = t & 15, pl = c0 / 2 + t;
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < WPG; ++k) s += gred[g * WPG + k][j];
+            if (pl < B) L.gpart[(size_t)(m * RT + rt) * B + pl] = s;
+        }
+    }
+}
+
 // caller layout [B][2 n] <-> internal [lmax+1][Np][ldu]
 __global__ void bat_pack_kernel(BatBuffers b, const double *c0, int taylor_acc) {
     const size_t total = (size_t)(b.lmax + 1) * b.np * b.ldu;
@@ -529,6 +810,22 @@ template <bool ADJ>
 static hipError_t bat_launch(const BatBuffers &b, const BatLaunch &l, hipStream_t s) {
     const int ntiles = (b.lmax + 1) * (b.np / b.tm) * (b.ldu / b.tn);
     const dim3 g(ntiles), blk(256), blk2(512);
+    if (b.ks == 8) {  // small-batch kernel: 32-row tiles, 32 or 64 columns
+        if (b.tm != 32 || (b.tn != 32 && b.tn != 64)) return hipErrorInvalidValue;
+        // the longest k range of a wave: a quarter of a block's k-steps when
+        // a tile has both neighbour blocks, an eighth when it has one
+        const int nks = b.np / 4, maxlen = b.lmax >= 2 ? (nks + 3) / 4 : (nks + 7) / 8;
+        const int chunk = maxlen <= 8 ? 8 : maxlen <= 16 ? 16 : maxlen <= 32 ? 32 : 64;
+#define TDSE_SKINNY(NG_, CH_)                                                                      \
+    if (b.tn == 32 * NG_ && chunk == CH_) {                                                        \
+        hipLaunchKernelGGL((bat_skinny_kernel<NG_, ADJ, 8, CH_>), g, blk2, 0, s, b, l);          \
+        return hipGetLastError();                                                                  \
+    }
+        TDSE_SKINNY(2, 8) TDSE_SKINNY(2, 16) TDSE_SKINNY(2, 32) TDSE_SKINNY(2, 64)
+        TDSE_SKINNY(1, 8) TDSE_SKINNY(1, 16) TDSE_SKINNY(1, 32) TDSE_SKINNY(1, 64)
+#undef TDSE_SKINNY
+        return hipErrorInvalidValue;
+    }
 #define TDSE_BAT(TM_, TN_, KC_)                                                                \
     if (b.tm == TM_ && b.tn == TN_ && b.kc == KC_ && b.ks == 1) {                              \
         hipLaunchKernelGGL((bat_stage_kernel<TM_, TN_, KC_, ADJ, 1>), g, blk, 0, s, b, l);   \

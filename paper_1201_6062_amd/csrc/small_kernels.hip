@@ -192,6 +192,32 @@ __global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
 
 bool small_eligible(int lmax, int n) { return n <= 64 && (lmax + 1) * n <= 256; }
 
+// Absolute row sums of the symmetric coupling matrix: for state (m, a) the
+// row a of D_m (towards block m+1) and the column a of D_{m-1} (towards block
+// m-1); neighbouring threads take neighbouring a, so both walks read
+// consecutive addresses across the wave.
+__global__ void coupling_rowsum_kernel(const double *dip, int lmax, int n, double *rs) {
+    const size_t ns = (size_t)(lmax + 1) * n;
+    for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < ns; g += (size_t)gridDim.x * blockDim.x) {
+        const int m = (int)(g / n), a = (int)(g % n);
+        double s = 0.0;
+        if (m < lmax) {
+            const double *row = dip + ((size_t)m * n + a) * n;
+            for (int b = 0; b < n; ++b) s += fabs(row[b]);
+        }
+        if (m > 0) {
+            const double *col = dip + (size_t)(m - 1) * n * n + a;
+            for (int b = 0; b < n; ++b) s += fabs(col[(size_t)b * n]);
+        }
+        rs[g] = s;
+    }
+}
+
+hipError_t coupling_rowsum(const double *dip, int lmax, int n, double *rs, hipStream_t s) {
+    hipLaunchKernelGGL(coupling_rowsum_kernel, dim3(256), dim3(256), 0, s, dip, lmax, n, rs);
+    return hipGetLastError();
+}
+
 hipError_t small_propagate(const double *en, const double *dip, int gauge, int lmax, int n, int method, int order, double dt,
                            int64_t nsteps, const double *field, const double *c0, double *cT, double *ckpt,
                            int64_t ckpt_every, hipStream_t s) {

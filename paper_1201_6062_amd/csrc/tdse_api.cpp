@@ -10,6 +10,7 @@
 #include <string>
 
 #include "tdse_internal.h"
+#include "tdse_stability.h"
 #include "tdse_validate.h"
 
 namespace tdse {
@@ -45,6 +46,35 @@ static tdse_status check_dev(const void *p, const char *name) {
     return TDSE_OK;
 }
 
+tdse_status check_device_ptr(const void *p, const char *name) { return check_dev(p, name); }
+
+// max |E| and the largest absolute row sum of the coupling (an upper bound of
+// its spectral norm), from device copies of the energies and of the row-major
+// blocks (dip may be NULL when lmax == 0). Synchronises s.
+static tdse_status coupling_bounds(tdse_plan p, const double *en, const double *dip, hipStream_t s) {
+    const size_t ns = (size_t)(p->lmax + 1) * p->n;
+    std::vector<double> hen(ns), hrs(ns, 0.0);
+    double *rs = nullptr;
+    hipError_t e = hipSuccess;
+    if (p->lmax > 0) {
+        e = hipMalloc(&rs, ns * sizeof(double));
+        if (e == hipSuccess) e = coupling_rowsum(dip, p->lmax, p->n, rs, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hrs.data(), rs, ns * sizeof(double), hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(hen.data(), en, ns * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (rs) (void)hipFree(rs);
+    if (e != hipSuccess) return hip_fail(e, "spectrum bounds of the plan");
+    double emax = 0.0, dmax = 0.0;
+    for (size_t g = 0; g < ns; ++g) {
+        emax = fabs(hen[g]) > emax ? fabs(hen[g]) : emax;
+        dmax = hrs[g] > dmax ? hrs[g] : dmax;
+    }
+    p->emax = emax;
+    p->dnorm = dmax;
+    return TDSE_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Launch schedule of one step: the completion each launch performs on the
 // previous launch's product (see vec_kernels.hip).
@@ -69,7 +99,7 @@ static Completion final_completion(tdse_method m, int order) {
     return v[0];
 }
 
-static hipError_t enqueue_steps(tdse_plan p, tdse_method m, int order, int64_t nsteps_chunk,
+static hipError_t enqueue_steps(tdse_plan p, const VecBuffers &vb, tdse_method m, int order, int64_t nsteps_chunk,
                                 int32_t &parity, hipStream_t s) {
     std::vector<Completion> sl;
     step_launches(m, order, sl);
@@ -82,12 +112,12 @@ static hipError_t enqueue_steps(tdse_plan p, tdse_method m, int order, int64_t n
             L.slots = m == TDSE_RK4 ? 3 : 1;
             hipError_t e;
             if (p->lmax == 0) {
-                e = vec_launch_combine(p->vb, L, s);
+                e = vec_launch_combine(vb, L, s);
             } else if (p->split) {
-                e = vec_launch_combine(p->vb, L, s);
-                if (e == hipSuccess) e = vec_launch_products(p->vb, L, s);
+                e = vec_launch_combine(vb, L, s);
+                if (e == hipSuccess) e = vec_launch_products(vb, L, s);
             } else {
-                e = vec_launch_tiles(p->vb, L, s);
+                e = vec_launch_tiles(vb, L, s);
             }
             if (e != hipSuccess) return e;
             parity ^= 1;
@@ -110,7 +140,7 @@ static tdse_status get_chunk_graph(tdse_plan p, tdse_method m, int order, hipGra
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     int32_t par = 0;
-    if (e == hipSuccess) e = enqueue_steps(p, m, order, CHUNK_STEPS, par, cs);
+    if (e == hipSuccess) e = enqueue_steps(p, p->vb, m, order, CHUNK_STEPS, par, cs);
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e == hipSuccess) e = e2;
     hipGraphExec_t ge = nullptr;
@@ -131,9 +161,15 @@ static bool graphs_enabled() {
     return !(v && v[0] == '1');
 }
 
-static tdse_status vec_propagate(tdse_plan p, tdse_method m, int order, double dt, int64_t nsteps,
-                                 const double *field, const double *c0, double *cT, double *ckpt,
-                                 int32_t K, hipStream_t s) {
+}  // namespace tdse
+
+// Single-vector propagation on the buffers vb (the plan's own, or the fixed
+// scratch array of tdse_propagate_noalloc); use_graphs: whole 64-step chunks
+// replay the plan's captured graph (only for the plan's own buffers, which
+// the graph was captured with).
+tdse_status tdse::vec_propagate_on(tdse_plan p, const VecBuffers &vb, bool use_graphs, tdse_method m, int order,
+                                   double dt, int64_t nsteps, const double *field, const double *c0, double *cT,
+                                   double *ckpt, int32_t K, hipStream_t s) {
     if (p->small) {
         TDSE_HIP(small_propagate(p->en, p->dip, p->gauge, p->lmax, p->n, (int)m, order, dt, nsteps, field, c0, cT, ckpt,
                                  ckpt ? K : 1, s));
@@ -147,24 +183,24 @@ static tdse_status vec_propagate(tdse_plan p, tdse_method m, int order, double d
     d.ckpt_every = ckpt ? K : 1;
     d.dt = dt;
     d.slots = m == TDSE_RK4 ? 3 : 1;
-    TDSE_HIP(set_desc(p->vb.desc, d, s));
+    TDSE_HIP(set_desc(vb.desc, d, s));
     int32_t parity = 0;
-    TDSE_HIP(vec_launch_start(p->vb, parity, c0, m, s));
+    TDSE_HIP(vec_launch_start(vb, parity, c0, m, s));
     hipGraphExec_t ge = nullptr;
-    if (graphs_enabled() && nsteps >= CHUNK_STEPS) {
+    if (use_graphs && graphs_enabled() && nsteps >= CHUNK_STEPS) {
         tdse_status st = get_chunk_graph(p, m, order, &ge);
         if (st != TDSE_OK) return st;
     }
     int64_t base = 0;
-    TDSE_HIP(chunk_begin(p->vb.desc, 0, s));
+    TDSE_HIP(chunk_begin(vb.desc, 0, s));
     for (int64_t done = 0; done < nsteps; done += CHUNK_STEPS) {
         base = done;
-        if (done > 0) TDSE_HIP(chunk_begin(p->vb.desc, done, s));
+        if (done > 0) TDSE_HIP(chunk_begin(vb.desc, done, s));
         const int64_t len = nsteps - done < CHUNK_STEPS ? nsteps - done : CHUNK_STEPS;
         if (ge && len == CHUNK_STEPS) {
             TDSE_HIP(hipGraphLaunch(ge, s));  // even launch count: parity unchanged
         } else {
-            TDSE_HIP(enqueue_steps(p, m, order, len, parity, s));
+            TDSE_HIP(enqueue_steps(p, vb, m, order, len, parity, s));
         }
     }
     VecLaunch L{};
@@ -174,18 +210,50 @@ static tdse_status vec_propagate(tdse_plan p, tdse_method m, int order, double d
     L.slots = m == TDSE_RK4 ? 3 : 1;
     L.finish = 1;
     L.out = cT;
-    TDSE_HIP(vec_launch_combine(p->vb, L, s));
+    TDSE_HIP(vec_launch_combine(vb, L, s));
     return TDSE_OK;
+}
+
+namespace tdse {
+
+static tdse_status vec_propagate(tdse_plan p, tdse_method m, int order, double dt, int64_t nsteps,
+                                 const double *field, const double *c0, double *cT, double *ckpt,
+                                 int32_t K, hipStream_t s) {
+    return vec_propagate_on(p, p->vb, true, m, order, dt, nsteps, field, c0, cT, ckpt, K, s);
+}
+
+size_t vec_scratch_bytes(int lmax, int n, int T) {
+    const size_t ns = (size_t)(lmax + 1) * n;
+    const size_t npart = (size_t)lmax * T * T * VEC_TILE_MAX;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return 6 * al(ns * sizeof(double2)) + 4 * al(npart * sizeof(double2)) + al(sizeof(CallDesc));
+}
+
+// Point the per-call buffers of vb (states of both parities, partials of both
+// parities, the call descriptor) into one region of vec_scratch_bytes bytes.
+void vec_bind_scratch(VecBuffers &vb, char *base, int lmax, int n, int T) {
+    const size_t ns = (size_t)(lmax + 1) * n;
+    const size_t npart = (size_t)lmax * T * T * VEC_TILE_MAX;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t st_bytes = al(ns * sizeof(double2)), part_bytes = al(npart * sizeof(double2));
+    size_t off = 0;
+    for (int par = 0; par < 2; ++par)
+        for (int v = 0; v < 3; ++v) {
+            vb.side[par].st[v] = reinterpret_cast<double2 *>(base + off);
+            off += st_bytes;
+        }
+    for (int par = 0; par < 2; ++par) {
+        vb.side[par].rowp = reinterpret_cast<double2 *>(base + off);
+        off += part_bytes;
+        vb.side[par].colp = reinterpret_cast<double2 *>(base + off);
+        off += part_bytes;
+    }
+    vb.desc = reinterpret_cast<CallDesc *>(base + off);
 }
 
 // Lay the plan's scratch out in one allocation.
 static tdse_status vec_alloc(tdse_plan p) {
-    const size_t ns = (size_t)(p->lmax + 1) * p->n;
-    const size_t npart = (size_t)p->lmax * p->T * p->T * VEC_TILE_MAX;
-    const size_t st_bytes = ns * sizeof(double2);
-    const size_t part_bytes = npart * sizeof(double2);
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    size_t total = 6 * al(st_bytes) + 4 * al(part_bytes) + al(sizeof(CallDesc));
+    const size_t total = vec_scratch_bytes(p->lmax, p->n, p->T);
     char *base = nullptr;
     if (hipMalloc(&base, total) != hipSuccess) {
         (void)hipGetLastError();
@@ -193,19 +261,7 @@ static tdse_status vec_alloc(tdse_plan p) {
     }
     p->scratch = reinterpret_cast<double *>(base);
     p->scratch_bytes = total;
-    size_t off = 0;
-    for (int par = 0; par < 2; ++par)
-        for (int v = 0; v < 3; ++v) {
-            p->vb.side[par].st[v] = reinterpret_cast<double2 *>(base + off);
-            off += al(st_bytes);
-        }
-    for (int par = 0; par < 2; ++par) {
-        p->vb.side[par].rowp = reinterpret_cast<double2 *>(base + off);
-        off += al(part_bytes);
-        p->vb.side[par].colp = reinterpret_cast<double2 *>(base + off);
-        off += al(part_bytes);
-    }
-    p->vb.desc = reinterpret_cast<CallDesc *>(base + off);
+    vec_bind_scratch(p->vb, base, p->lmax, p->n, p->T);
     p->vb.en = p->en;
     p->vb.dip = p->dip;
     p->vb.lmax = p->lmax;
@@ -219,13 +275,18 @@ static tdse_status vec_alloc(tdse_plan p) {
 // ---------------------------------------------------------------------------
 // Batched path.
 
-// Tile shape for a batched plan: TN from the padded column count, TM the
-// largest of 128/64/32 that still gives >= 256 workgroups (one per CU).
-// TDSE_TILE="TMxTN" overrides (the autotuner writes the same choice).
+// Tile shape for a batched plan.
+//  * 2B <= 64 real columns (up to 32 pulses): the small-batch kernel (K
+//    split over eight waves, operands straight into registers; ks = 8),
+//    32-row tiles over all columns.
+//  * otherwise TN from the padded column count and TM the largest of
+//    128/64/32 that still gives >= 512 workgroups (two per CU); grids short
+//    of that take K chunks of 32 and two K groups per workgroup.
+// A tuned (cache) or forced ($TDSE_TILE="TMxTNxKC[xKS]") choice overrides;
+// $TDSE_KGROUPS=1/2 overrides the K groups of the LDS kernels, and
+// $TDSE_SKINNY=0 turns the small-batch kernel off.
 static void bat_pick_tile(int lmax, int n, int batch, const TileChoice *force, int *tm, int *tn, int *kc,
                           int *ks) {
-    // Default: 128 x 64 tiles where the grid still fills the chip (two
-    // workgroups per CU measured fastest at Lmax=15, N=500, 256 pulses).
     const int ldu = ((2 * batch + 31) / 32) * 32;
     *tn = ldu % 64 == 0 ? 64 : 32;
     *tm = 32;
@@ -242,19 +303,27 @@ static void bat_pick_tile(int lmax, int n, int batch, const TileChoice *force, i
     if (*tn != 64) *kc = 16;  // compiled K-chunk-32 shapes have TN = 64 or 128
     // such grids also get two K groups (eight waves) per workgroup
     *ks = *kc == 32 || (*tm == 32 && *tn == 32) ? 2 : 1;
-    TileChoice tc{0, 0, 0, 0};
+    const char *sk = getenv("TDSE_SKINNY");
+    if (2 * batch <= 64 && !(sk && sk[0] == '0')) {
+        *tm = 32;
+        *tn = 2 * batch <= 32 ? 32 : 64;
+        *kc = 16;
+        *ks = 8;
+    }
+    TileChoice tc{0, 0, 0, 0, 0};
     if (force) tc = *force;
     else tune_lookup(lmax, n, batch, &tc);
-    if (tc.tm > 0 || tc.tn > 0 || tc.kc > 0) *ks = 1;  // a forced or tuned shape: one K group
+    if (tc.tm > 0 || tc.tn > 0 || tc.kc > 0) *ks = tc.ks > 0 ? tc.ks : 1;  // a forced or tuned shape
     if (tc.tm > 0) *tm = tc.tm;
     if (tc.tn > 0) *tn = tc.tn;
     if (tc.kc > 0) *kc = tc.kc;
-    // two K groups exist for 32x64x32 and 32x32x16; $TDSE_KGROUPS=1/2 overrides
     if (const char *kg = getenv("TDSE_KGROUPS")) {
-        if (kg[0] == '1') *ks = 1;
-        if (kg[0] == '2') *ks = 2;
+        if (*ks != 8 && kg[0] == '1') *ks = 1;
+        if (*ks != 8 && kg[0] == '2') *ks = 2;
     }
-    if (!((*tm == 32 && *tn == 64 && *kc == 32) || (*tm == 32 && *tn == 32 && *kc == 16))) *ks = 1;
+    // two K groups exist for 32x64x32 and 32x32x16; the small-batch kernel for 32-row tiles of 32 or 64 columns
+    if (*ks == 8 && !(*tm == 32 && (*tn == 32 || *tn == 64) && 2 * batch <= *tn)) *ks = 1;
+    if (*ks == 2 && !((*tm == 32 && *tn == 64 && *kc == 32) || (*tm == 32 && *tn == 32 && *kc == 16))) *ks = 1;
 }
 
 static tdse_status bat_create(tdse_plan p, const double *energies, const double *dipole,
@@ -294,10 +363,11 @@ static tdse_status bat_create(tdse_plan p, const double *energies, const double 
     if (e == hipSuccess) e = hipMemsetAsync(b.u[0], 0, 4 * usz * sizeof(double), s);
     if (e == hipSuccess) e = bat_layout(stage_d, stage_en, b, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    tdse_status st = e == hipSuccess ? coupling_bounds(p, stage_en, stage_d, s) : TDSE_OK;
     if (stage_en) (void)hipFree(stage_en);
     if (stage_d) (void)hipFree(stage_d);
     if (e != hipSuccess) return hip_fail(e, "batched plan setup");
-    return TDSE_OK;
+    return st;
 }
 
 static void bat_schedule(tdse_method m, int order, std::vector<BatLaunch> &out) {
@@ -664,6 +734,7 @@ static tdse_status adj_workspace(tdse_plan p, int32_t K, int nprod, bool need_ck
     const size_t bytes = (n_fwd + n_us + n_gp + n_ck) * sizeof(double);
     if (bytes > p->adj_bytes) {
         if (p->adj_mem) (void)hipFree(p->adj_mem);
+    if (p->ada_mem) (void)hipFree(p->ada_mem);
         p->adj_mem = nullptr;
         p->adj_bytes = 0;
         if (hipMalloc(&p->adj_mem, bytes) != hipSuccess) {
@@ -885,7 +956,7 @@ tdse_status create_plan(tdse_plan *out, const double *energies, const double *di
     p->ld = VEC_TILE_MAX;
     p->T = (n + VEC_TILE_MAX - 1) / VEC_TILE_MAX;
     {
-        TileChoice tc{0, 0, 0, 0};
+        TileChoice tc{0, 0, 0, 0, 0};
         if (force) tc = *force;
         else tune_lookup(lmax, n, 1, &tc);
         if (tc.T >= p->T && tc.T <= n) p->T = tc.T;
@@ -923,10 +994,16 @@ tdse_status create_plan(tdse_plan *out, const double *energies, const double *di
         e = hipMemcpyAsync(stage, dipole, dip_elems * sizeof(double), hipMemcpyDefault, s);
     if (e == hipSuccess && lmax > 0) e = vec_layout(stage, p->dip, lmax, n, p->T, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    st = e == hipSuccess ? coupling_bounds(p, p->en, stage, s) : TDSE_OK;
     if (stage) (void)hipFree(stage);
     if (e != hipSuccess) {
         tdse_destroy(p);
         return hip_fail(e, "copy of the Hamiltonian into the plan");
+    }
+    if (st != TDSE_OK) {
+        std::string msg = g_last_error;
+        tdse_destroy(p);
+        return fail(st, msg);
     }
     st = vec_alloc(p);
     if (st != TDSE_OK) {
@@ -1065,6 +1142,88 @@ tdse_status tdse_propagate_rkf45(tdse_plan p, double dt, int64_t nsteps, const d
     return rkf_propagate(p, dt, nsteps, field, c0, cT, err, ckpt, ckpt_every, reinterpret_cast<hipStream_t>(stream));
 }
 
+tdse_status tdse_check_stability(tdse_plan p, tdse_method method, int32_t order, double dt, double fmax,
+                                 double *theta, double *bound) {
+    clear_error();
+    std::string why;
+    tdse_status st = validate_propagate(p != nullptr, (int)method, method == TDSE_RK4 || method == TDSE_RKF45 ? 1 : order,
+                                        dt, 0, false, 0, &why);
+    if (st != TDSE_OK) return fail(st, why);
+    if (!isfinite(fmax)) return fail(TDSE_E_INVAL, "fmax must be finite");
+    double th = 0.0, bd = 0.0;
+    st = check_stability(method, order, dt, p->emax, fmax, p->dnorm, &th, &bd);
+    if (theta) *theta = th;
+    if (bound) *bound = bd;
+    if (st != TDSE_OK) {
+        char buf[240];
+        snprintf(buf, sizeof buf,
+                 "unstable step: dt (max|E| + |F| ||D||) = %.6g exceeds the method's imaginary-axis bound %.6g "
+                 "(max|E| = %.6g, ||D|| <= %.6g)",
+                 th, bd, p->emax, p->dnorm);
+        return fail(TDSE_E_UNSTABLE, buf);
+    }
+    return TDSE_OK;
+}
+
+tdse_status tdse_propagate_adaptive(tdse_plan p, double t_final, double dt0, double tol, double dt_min,
+                                    int64_t max_steps, tdse_field_fn field_fn, void *ctx, const double *c0,
+                                    double *cT, double *steps, int64_t *nsteps_taken, void *stream) {
+    clear_error();
+    if (!p) return fail(TDSE_E_INVAL, "plan is NULL");
+    if (!field_fn) return fail(TDSE_E_INVAL, "field_fn is NULL");
+    if (!nsteps_taken) return fail(TDSE_E_INVAL, "nsteps_taken is NULL");
+    if (!(t_final >= 0.0) || !isfinite(t_final)) return fail(TDSE_E_INVAL, "t_final must be finite and >= 0");
+    if (!(dt0 > 0.0) || !isfinite(dt0)) return fail(TDSE_E_INVAL, "dt0 must be finite and > 0");
+    if (!(dt_min > 0.0) || !isfinite(dt_min)) return fail(TDSE_E_INVAL, "dt_min must be finite and > 0");
+    if (!(tol > 0.0) || !isfinite(tol)) return fail(TDSE_E_INVAL, "tol must be finite and > 0");
+    if (max_steps < 0) return fail(TDSE_E_INVAL, "max_steps must be >= 0");
+    tdse_status st;
+    if ((st = check_dev(c0, "c0")) || (st = check_dev(cT, "cT"))) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int B = p->batch;
+    const size_t len = (size_t)B * 2 * (p->lmax + 1) * p->n;
+    const size_t need = ((size_t)B * 6 + 2 * len + (size_t)B) * sizeof(double);
+    if (need > p->ada_bytes) {
+        if (p->ada_mem) (void)hipFree(p->ada_mem);
+        p->ada_mem = nullptr;
+        p->ada_bytes = 0;
+        if (hipMalloc(&p->ada_mem, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(TDSE_E_NOMEM, "hipMalloc of the adaptive-step workspace failed");
+        }
+        p->ada_bytes = need;
+    }
+    double *dfield = p->ada_mem, *cur = dfield + (size_t)B * 6, *nxt = cur + len, *derr = nxt + len;
+    std::vector<double> hfield((size_t)B * 6), herr(B);
+    TDSE_HIP(hipMemcpyAsync(cur, c0, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double t = 0.0, dt = dt0;
+    int64_t taken = 0, tried = 0;
+    while (t < t_final * (1.0 - 1e-14) && tried < max_steps) {
+        const double h = dt < t_final - t ? dt : t_final - t;
+        field_fn(t, h, hfield.data(), ctx);
+        TDSE_HIP(hipMemcpyAsync(dfield, hfield.data(), hfield.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        TDSE_HIP_ST(rkf_propagate(p, h, 1, dfield, cur, nxt, derr, nullptr, 1, s));
+        TDSE_HIP(hipMemcpyAsync(herr.data(), derr, B * sizeof(double), hipMemcpyDeviceToHost, s));
+        TDSE_HIP(hipStreamSynchronize(s));
+        double e = 0.0;
+        for (int b = 0; b < B; ++b) e = herr[b] > e ? herr[b] : e;
+        ++tried;
+        if (e <= tol || h <= dt_min) {
+            std::swap(cur, nxt);
+            t += h;
+            if (steps) steps[taken] = h;
+            ++taken;
+        }
+        const double fac = e == 0.0 ? 2.0 : std::min(2.0, std::max(0.2, 0.9 * pow(tol / e, 0.2)));
+        dt = std::max(dt_min, h * fac);
+    }
+    TDSE_HIP(hipMemcpyAsync(cT, cur, len * sizeof(double), hipMemcpyDeviceToDevice, s));
+    TDSE_HIP(hipStreamSynchronize(s));
+    *nsteps_taken = taken;
+    if (t < t_final * (1.0 - 1e-14)) return fail(TDSE_E_INVAL, "max_steps reached before t_final");
+    return TDSE_OK;
+}
+
 // Captured group chunks hold the work-list addresses: drop them before the
 // lists move.
 static void drop_group_graphs(tdse_group g) {
@@ -1086,7 +1245,10 @@ tdse_status tdse_group_create(tdse_group *out, int32_t count, const tdse_plan *p
         const tdse_plan p = plans[k];
         if (!p) return fail(TDSE_E_INVAL, "plans[" + std::to_string(k) + "] is NULL");
         if (p->batch != 1) return fail(TDSE_E_INVAL, "group members must be batch-1 plans");
-        if (p->T > 8) return fail(TDSE_E_UNSUPPORTED, "group members need n <= 1024 (at most 8 tiles per block)");
+        if (p->T > 8)
+            return fail(TDSE_E_UNSUPPORTED, "group members need at most 8 tiles per block dimension (n <= 1024 at "
+                                            "the default tile count; plans[" + std::to_string(k) + "] has " +
+                                                std::to_string(p->T) + ")");
         if (p->device != plans[0]->device) return fail(TDSE_E_INVAL, "group members must share one device");
     }
     tdse_group g = new (std::nothrow) tdse_group_s();

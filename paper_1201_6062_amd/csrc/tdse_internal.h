@@ -130,6 +130,9 @@ struct GroupInst {
 };
 // Single-workgroup propagation of small problems ((lmax+1) n <= 256, n <= 64).
 bool small_eligible(int lmax, int n);
+// rs[(m, a)] = absolute row sum of the symmetric coupling matrix (row-major
+// blocks dip [lmax][n][n], device), [(lmax+1) n] device.
+hipError_t coupling_rowsum(const double *dip, int lmax, int n, double *rs, hipStream_t s);
 hipError_t small_propagate(const double *en, const double *dip, int gauge, int lmax, int n, int method, int order, double dt,
                            int64_t nsteps, const double *field, const double *c0, double *cT, double *ckpt,
                            int64_t ckpt_every, hipStream_t s);
@@ -147,6 +150,19 @@ hipError_t group_launch_round(const GroupSeg *segs, int nsegs, const GroupTile *
 hipError_t group_set_desc(GroupDesc *desc, int64_t base_round, double dt, hipStream_t s);
 
 hipError_t vec_launch_tiles(const VecBuffers &b, const VecLaunch &l, hipStream_t s);
+// Bytes of per-call buffers of a single-vector plan (states and partials of
+// both parities, the call descriptor) and their placement in one region.
+size_t vec_scratch_bytes(int lmax, int n, int T);
+void vec_bind_scratch(VecBuffers &vb, char *base, int lmax, int n, int T);
+// Single-vector RK4 / Taylor propagation of plan p on the per-call buffers of
+// vb; use_graphs: replay the plan's captured chunk graph (vb must then be the
+// plan's own buffers).
+tdse_status vec_propagate_on(tdse_plan p, const VecBuffers &vb, bool use_graphs, tdse_method m, int order, double dt,
+                             int64_t nsteps, const double *field, const double *c0, double *cT, double *ckpt,
+                             int32_t K, hipStream_t s);
+// NULL, alignment and device-memory check of an argument (TDSE_E_INVAL).
+tdse_status check_device_ptr(const void *p, const char *name);
+
 hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream_t s);
 // Split path: products only, inputs completed by a preceding vec_launch_combine.
 hipError_t vec_launch_products(const VecBuffers &b, const VecLaunch &l, hipStream_t s);
@@ -168,7 +184,7 @@ struct BatBuffers {
     double *kst;           // Runge-Kutta-Fehlberg: stage derivatives k_1..k_5, [5][(lmax+1)][np][ldu]
     const double *field;   // caller [batch][nsteps][S]
     int32_t lmax, n, np, ldu, batch, tm, tn, kc;
-    int32_t ks;            // K groups per workgroup (1, or 2: one per neighbour block)
+    int32_t ks;            // K groups per workgroup (1, or 2: one per neighbour block; 8: the small-batch kernel)
     int32_t gauge;         // TDSE_LENGTH or TDSE_VELOCITY (d holds -Q_l in the velocity gauge)
 };
 
@@ -302,6 +318,7 @@ struct TileChoice {
     int32_t T;        // single-vector path: tiles per block dimension (0 = default)
     int32_t tm, tn;   // batched path: output tile (0 = default)
     int32_t kc;       // batched path: contraction chunk staged per LDS buffer (0 = default)
+    int32_t ks;       // batched path: K groups per workgroup (1, 2; 8 = the small-batch kernel; 0 = default)
 };
 
 // Reads $TDSE_TUNE_CACHE (written by tdse_tune) and $TDSE_TILE; leaves the
@@ -334,6 +351,12 @@ struct tdse_group_s {
 
 struct tdse_plan_s {
     int32_t lmax = 0, n = 0, batch = 1;
+    // spectrum bounds for the stability test: max |E| and the largest absolute
+    // row sum of the coupling (>= its spectral norm)
+    double emax = 0.0, dnorm = 0.0;
+    // tdse_propagate_adaptive workspace (first use): field samples, two states, errors
+    double *ada_mem = nullptr;
+    size_t ada_bytes = 0;
     int32_t gauge = 0;           // tdse_gauge of the coupling blocks
     int device = 0;
     // device copies of the Hamiltonian

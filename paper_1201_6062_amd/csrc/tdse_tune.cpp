@@ -4,9 +4,14 @@
 //
 // Cache format (one entry per line, written and read by this file only):
 //   {"arch": "gfx950", "entries": {
-//   "L15_N500_B1": {"T": 4, "tm": 0, "tn": 0, "kc": 0, "us_per_step": 29.8},
-//   "L15_N500_B256": {"T": 0, "tm": 128, "tn": 64, "kc": 32, "us_per_step": 441.0}
+//   "L15_N500_B1": {"T": 4, "tm": 0, "tn": 0, "kc": 0, "ks": 0, "us_per_step": 29.8},
+//   "L15_N512b_B256": {"T": 0, "tm": 128, "tn": 64, "kc": 32, "ks": 1, "us_per_step": 441.0}
 //   }}
+// Every tuned shape is recorded twice: under its exact (lmax, n, batch) and
+// under its bucket (lmax, n rounded up to a multiple of 64, batch; key suffix
+// "b"), which serves shapes of the same bucket that were not tuned themselves
+// (their kernels take the same tile grid up to the last partial tile). A
+// lookup takes the exact entry first, then the bucket's.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -38,6 +43,12 @@ static std::string key_of(int lmax, int n, int batch) {
     return k;
 }
 
+static std::string bucket_key_of(int lmax, int n, int batch) {
+    char k[64];
+    snprintf(k, sizeof k, "L%d_N%db_B%d", lmax, ((n + 63) / 64) * 64, batch);
+    return k;
+}
+
 struct CacheEntry {
     TileChoice tc;
     double us;
@@ -56,8 +67,8 @@ static bool read_cache(const char *path, std::string *arch, std::map<std::string
         }
         char key[64];
         CacheEntry ce{};
-        if (sscanf(line, " \"%63[^\"]\": {\"T\": %d, \"tm\": %d, \"tn\": %d, \"kc\": %d, \"us_per_step\": %lf",
-                   key, &ce.tc.T, &ce.tc.tm, &ce.tc.tn, &ce.tc.kc, &ce.us) == 6)
+        if (sscanf(line, " \"%63[^\"]\": {\"T\": %d, \"tm\": %d, \"tn\": %d, \"kc\": %d, \"ks\": %d, \"us_per_step\": %lf",
+                   key, &ce.tc.T, &ce.tc.tm, &ce.tc.tn, &ce.tc.kc, &ce.tc.ks, &ce.us) == 7)
             (*ent)[key] = ce;
     }
     fclose(f);
@@ -72,9 +83,9 @@ static bool write_cache(const char *path, const std::string &arch,
     fprintf(f, "{\"arch\": \"%s\", \"entries\": {\n", arch.c_str());
     size_t i = 0;
     for (const auto &kv : ent) {
-        fprintf(f, "\"%s\": {\"T\": %d, \"tm\": %d, \"tn\": %d, \"kc\": %d, \"us_per_step\": %.3f}%s\n",
-                kv.first.c_str(), kv.second.tc.T, kv.second.tc.tm, kv.second.tc.tn, kv.second.tc.kc, kv.second.us,
-                ++i < ent.size() ? "," : "");
+        fprintf(f, "\"%s\": {\"T\": %d, \"tm\": %d, \"tn\": %d, \"kc\": %d, \"ks\": %d, \"us_per_step\": %.3f}%s\n",
+                kv.first.c_str(), kv.second.tc.T, kv.second.tc.tm, kv.second.tc.tn, kv.second.tc.kc, kv.second.tc.ks,
+                kv.second.us, ++i < ent.size() ? "," : "");
     }
     fprintf(f, "}}\n");
     fclose(f);
@@ -87,12 +98,13 @@ void tune_lookup(int lmax, int n, int batch, TileChoice *tc) {
         int a = 0, b = 0;
         if (sscanf(force, "T=%d", &a) == 1 && batch == 1) tc->T = a;
         else if (batch > 1) {
-            int k = 0;
-            int got = sscanf(force, "%dx%dx%d", &a, &b, &k);
+            int k = 0, g = 0;
+            int got = sscanf(force, "%dx%dx%dx%d", &a, &b, &k, &g);
             if (got >= 2) {
                 tc->tm = a;
                 tc->tn = b;
-                tc->kc = got == 3 ? k : 16;
+                tc->kc = got >= 3 ? k : 16;
+                tc->ks = got == 4 ? g : 1;
             }
         }
         return;
@@ -103,12 +115,14 @@ void tune_lookup(int lmax, int n, int batch, TileChoice *tc) {
     std::map<std::string, CacheEntry> ent;
     if (!read_cache(path, &arch, &ent) || arch != arch_name()) return;
     auto it = ent.find(key_of(lmax, n, batch));
+    if (it == ent.end()) it = ent.find(bucket_key_of(lmax, n, batch));
     if (it == ent.end()) return;
     if (batch == 1 && it->second.tc.T > 0) tc->T = it->second.tc.T;
     if (batch > 1 && it->second.tc.tm > 0) {
         tc->tm = it->second.tc.tm;
         tc->tn = it->second.tc.tn;
         tc->kc = it->second.tc.kc > 0 ? it->second.tc.kc : 16;
+        tc->ks = it->second.tc.ks > 0 ? it->second.tc.ks : 1;
     }
 }
 
@@ -182,15 +196,23 @@ extern "C" tdse_status tdse_tune(int32_t lmax, int32_t n, int32_t batch, const c
 
     std::vector<TileChoice> cands;
     if (batch == 1) {
-        const int t0 = (n + VEC_TILE_MAX - 1) / VEC_TILE_MAX;
-        for (int T = t0; T <= t0 + 3 && T <= 16 && T <= n; ++T) cands.push_back({T, 0, 0, 0});
+        // tile counts T0 .. T0 + 3, at most 8 where T0 allows it (plans of
+        // more than 8 tiles per block dimension cannot join an uneven group)
+        const int t0 = (n + VEC_TILE_MAX - 1) / VEC_TILE_MAX, tmax = t0 <= 8 ? 8 : 16;
+        for (int T = t0; T <= t0 + 3 && T <= tmax && T <= n; ++T) cands.push_back({T, 0, 0, 0, 0});
     } else {
+        // the LDS kernels' 11 tile shapes with one K group, the two shapes
+        // compiled with two K groups, and for 2B <= 64 the small-batch kernel
         const int shapes[11][3] = {{128, 128, 16}, {128, 64, 16}, {64, 128, 16}, {64, 64, 16}, {64, 32, 16},
                                    {32, 64, 16},   {32, 32, 16},  {128, 64, 32}, {64, 128, 32}, {64, 64, 32},
                                    {32, 64, 32}};
-        for (auto &sh : shapes) cands.push_back({0, sh[0], sh[1], sh[2]});
+        for (auto &sh : shapes) cands.push_back({0, sh[0], sh[1], sh[2], 1});
+        cands.push_back({0, 32, 64, 32, 2});
+        cands.push_back({0, 32, 32, 16, 2});
+        if (2 * batch <= 32) cands.push_back({0, 32, 32, 16, 8});
+        if (2 * batch <= 64) cands.push_back({0, 32, 64, 16, 8});
     }
-    CacheEntry best{{0, 0, 0, 0}, 1e300};
+    CacheEntry best{{0, 0, 0, 0, 0}, 1e300};
     for (const TileChoice &tc : cands) {
         if (st != TDSE_OK) break;
         double us = 0.0;
@@ -211,11 +233,12 @@ extern "C" tdse_status tdse_tune(int32_t lmax, int32_t n, int32_t batch, const c
         std::map<std::string, CacheEntry> ent;
         if (read_cache(path, &old_arch, &ent) && old_arch != arch) ent.clear();
         ent[key_of(lmax, n, batch)] = best;
+        ent[bucket_key_of(lmax, n, batch)] = best;
         if (!write_cache(path, arch, ent)) return fail(TDSE_E_INVAL, std::string("cannot write ") + path);
     }
     char msg[128];
-    snprintf(msg, sizeof msg, "best T=%d tm=%d tn=%d: %.3f us per step", best.tc.T, best.tc.tm, best.tc.tn,
-             best.us);
+    snprintf(msg, sizeof msg, "best T=%d tm=%d tn=%d kc=%d ks=%d: %.3f us per step", best.tc.T, best.tc.tm,
+             best.tc.tn, best.tc.kc, best.tc.ks, best.us);
     set_error(msg);  // informational text for the caller; status is TDSE_OK
     return TDSE_OK;
 }

@@ -5,7 +5,10 @@
 #include <math.h>
 #include <stdio.h>
 
+#include <complex>
+
 #include "tdse_split.h"
+#include "tdse_stability.h"
 #include "tdse_tile.h"
 #include "tdse_validate.h"
 
@@ -71,6 +74,75 @@ int main() {
     CHECK(validate_propagate(true, 0, 0, 0.1, 0, false, 0, &why) == TDSE_OK);
     CHECK(validate_propagate(true, 0, 0, 0.1, 5, true, 0, &why) == TDSE_E_INVAL);
     CHECK(validate_propagate(true, 0, 0, 0.1, 5, true, 1, &why) == TDSE_OK);
+    // Stability polynomials against the step maps themselves: one step of
+    // dy/dt = -i lam y run stage by stage (RK4 tableau; Fehlberg's tableau with
+    // its fourth-order weights; the Taylor recursion) equals R(-i dt lam).
+    {
+        typedef std::complex<double> cd;
+        for (double th : {0.1, 0.7, 1.9, 2.5, 3.1}) {
+            const cd z(0.0, -th);  // dt * (-i lam), lam = th / dt
+            double r[33];
+            // RK4
+            cd k1 = z, k2 = z * (1.0 + 0.5 * k1), k3 = z * (1.0 + 0.5 * k2), k4 = z * (1.0 + k3);
+            cd y = 1.0 + (k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0;
+            int deg = stability_poly(TDSE_RK4, 0, r);
+            CHECK(fabs(std::norm(y) - amplification2(r, deg, th)) < 1e-13);
+            // Taylor-p
+            for (int p = 1; p <= 12; ++p) {
+                cd t = 1.0, acc = 1.0;
+                for (int m = 1; m <= p; ++m) {
+                    t *= z / (double)m;
+                    acc += t;
+                }
+                deg = stability_poly(TDSE_TAYLOR, p, r);
+                CHECK(fabs(std::norm(acc) - amplification2(r, deg, th)) < 1e-12);
+            }
+            // Fehlberg, fourth-order solution
+            cd k[6];
+            for (int i = 0; i < 6; ++i) {
+                cd u = 1.0;
+                for (int j = 0; j < i; ++j) u += FEHLBERG_A[i][j] * k[j];
+                k[i] = z * u;
+            }
+            cd yf = 1.0;
+            for (int i = 0; i < 6; ++i) yf += FEHLBERG_B4[i] * k[i];
+            deg = stability_poly(TDSE_RKF45, 0, r);
+            CHECK(fabs(std::norm(yf) - amplification2(r, deg, th)) < 1e-13);
+        }
+        double r[33];
+        stability_poly(TDSE_RKF45, 0, r);
+        // fourth order: the exponential's coefficients up to z^4
+        CHECK(fabs(r[1] - 1.0) < 1e-15 && fabs(r[2] - 0.5) < 1e-15 && fabs(r[3] - 1.0 / 6.0) < 1e-15 &&
+              fabs(r[4] - 1.0 / 24.0) < 1e-15);
+        // bounds: classic values on the imaginary axis
+        CHECK(fabs(stability_bound(TDSE_RK4, 0) - 2.0 * sqrt(2.0)) < 1e-6);
+        CHECK(fabs(stability_bound(TDSE_TAYLOR, 4) - 2.0 * sqrt(2.0)) < 1e-6);
+        CHECK(fabs(stability_bound(TDSE_TAYLOR, 3) - sqrt(3.0)) < 1e-6);
+        CHECK(stability_bound(TDSE_TAYLOR, 1) < 2e-7);  // explicit Euler amplifies at once
+        CHECK(stability_bound(TDSE_TAYLOR, 8) > stability_bound(TDSE_RK4, 0));
+        // Fehlberg's fourth-order solution: |R|^2 - 1 = theta^6 (1/52 - 1/72) + ...
+        CHECK(fabs(r[5] - 1.0 / 104.0) < 1e-15 && fabs(r[6]) < 1e-15);
+        CHECK(fabs(stability_bound(TDSE_RKF45, 0) - pow(1e-14 / (1.0 / 52 - 1.0 / 72), 1.0 / 6)) < 1e-4);
+        for (int p = 1; p <= 16; ++p)
+            CHECK(has_stability_interval(TDSE_TAYLOR, p) == (p % 4 == 0 || p % 4 == 3));
+        CHECK(has_stability_interval(TDSE_RK4, 0) && !has_stability_interval(TDSE_RKF45, 0));
+        CHECK(isinf(stability_bound(TDSE_LANCZOS, 8)));
+        // the bound is the first crossing of 1 + STAB_TOL
+        for (int m : {TDSE_RK4}) {
+            const double b = stability_bound(m, 0);
+            const int deg = stability_poly(m, 0, r);
+            for (double s = 0.0; s <= b; s += b / 997.0) CHECK(amplification2(r, deg, s) <= 1.0 + STAB_TOL);
+            CHECK(amplification2(r, deg, b * (1.0 + 1e-6)) > 1.0 + STAB_TOL);
+        }
+        double th = 0.0, bd = 0.0;
+        // c5-like: dt 0.01, max|E| 29.6, field 0.1, row-sum bound 133
+        CHECK(check_stability(TDSE_RK4, 0, 0.01, 29.6, 0.1, 133.0, &th, &bd) == TDSE_OK);
+        CHECK(fabs(th - 0.01 * (29.6 + 13.3)) < 1e-12 && fabs(bd - 2.0 * sqrt(2.0)) < 1e-6);
+        CHECK(check_stability(TDSE_RK4, 0, 0.1, 29.6, 0.0, 133.0, &th, &bd) == TDSE_E_UNSTABLE);
+        CHECK(check_stability(TDSE_RK4, 0, 0.05, 29.6, 0.1, 133.0, &th, &bd) == TDSE_OK);
+        CHECK(check_stability(TDSE_RK4, 0, 0.05, 29.6, -0.4, 133.0, &th, &bd) == TDSE_E_UNSTABLE);
+        CHECK(check_stability(TDSE_LANCZOS, 12, 10.0, 29.6, 1.0, 133.0, &th, &bd) == TDSE_OK);
+    }
     printf("%s (%d failures)\n", fails ? "FAILED" : "ok", fails);
     return fails ? 1 : 0;
 }

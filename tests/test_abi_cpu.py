@@ -89,6 +89,20 @@ def test_propagate_rejects_invalid_arguments(lib):
         assert frag in _err(lib), (frag, _err(lib))
 
 
+def test_stability_and_adaptive_argument_errors(lib):
+    import ctypes as ct
+    th, bd = ct.c_double(0.0), ct.c_double(0.0)
+    assert lib.tdse_check_stability(None, 0, 0, 0.1, 0.0, ct.byref(th), ct.byref(bd)) == 1
+    assert "plan is NULL" in _err(lib)
+    fake = ct.c_void_p(16)  # rejected before the handle is used
+    assert lib.tdse_check_stability(fake, 9, 0, 0.1, 0.0, None, None) == 1
+    assert lib.tdse_check_stability(fake, 0, 0, -1.0, 0.0, None, None) == 1
+    n = ct.c_int64(0)
+    assert lib.tdse_propagate_adaptive(None, 1.0, 0.1, 1e-8, 1e-6, 10, None, None, None, None, None,
+                                       ct.byref(n), None) == 1
+    assert "plan is NULL" in _err(lib)
+
+
 def test_adjoint_and_group_argument_errors(lib):
     assert lib.tdse_adjoint(None, 0, 0, 0.1, 10, None, None, None, 64, None, None, None, None) == 1
     assert "plan is NULL" in _err(lib)

@@ -17,7 +17,12 @@ from paper_1201_6062_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 TOL = 1e-10
-TILES = ["128x128", "128x64", "64x128", "64x64", "64x32", "32x64", "32x32"]
+# (forced tile TMxTNxKCxKS, batch): every compiled shape of the LDS kernels,
+# with one and two K groups, and both column widths of the small-batch kernel
+TILES = [("128x128", 20), ("128x64", 20), ("64x128", 20), ("64x64", 20), ("64x32", 20), ("32x64", 20),
+         ("32x32", 20), ("128x64x32", 20), ("64x128x32", 20), ("64x64x32", 20), ("32x64x32", 20),
+         ("32x64x32x2", 20), ("32x32x16x2", 20), ("32x64x16x8", 20), ("32x64x16x8", 9), ("32x32x16x8", 16),
+         ("32x32x16x8", 5)]
 
 
 def rel_l2(a, b):
@@ -53,8 +58,11 @@ def test_batched_hmul(lmax, n, batch):
 
 @pytest.mark.parametrize("lmax,n,batch,nsteps", [(1, 1, 2, 40), (2, 3, 2, 50), (3, 50, 5, 40),
                                                  (2, 130, 17, 20), (0, 6, 3, 30), (15, 500, 32, 6),
-                                                 (1, 2048, 3, 6)])
+                                                 (1, 2048, 3, 6), (2, 1100, 3, 4), (4, 1000, 16, 3)])
 def test_batched_rk4(lmax, n, batch, nsteps):
+    """Up to 32 pulses run the small-batch kernel: its k-range chunks of 8
+    (n = 50), 16 (130), 32 (500) and 64 k-steps (1000, 2048), and two trips
+    of 64 (Lmax = 2, n = 1100: 70 k-steps per wave)."""
     h = wl.hamiltonian(lmax, n, 4)
     dt = 0.01
     f = pulses_field(batch, dt, nsteps, 7)
@@ -77,11 +85,11 @@ def test_batched_taylor(order):
     assert rel_l2(got, ref) <= TOL
 
 
-@pytest.mark.parametrize("tile", TILES)
-def test_every_tile_shape(tile, monkeypatch):
+@pytest.mark.parametrize("tile,batch", TILES)
+def test_every_tile_shape(tile, batch, monkeypatch):
     monkeypatch.setenv("TDSE_TILE", tile)
     h = wl.hamiltonian(3, 70, 6)
-    dt, nsteps, batch = 0.01, 12, 20
+    dt, nsteps = 0.01, 12
     f = pulses_field(batch, dt, nsteps, 13)
     c0 = wl.random_state(np.random.default_rng(5), h.nstates, batch)
     plan = make_plan(h, batch)

@@ -7,15 +7,18 @@ import json
 
 import numpy as np
 import pytest
-import torch  # noqa: F401
+import torch  # noqa: F401  (loads the HIP runtime before the library)
 
 import oracle
 from paper_1201_6062_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
-SHAPES_BATCHED = {(128, 128, 16), (128, 64, 16), (64, 128, 16), (64, 64, 16), (64, 32, 16), (32, 64, 16),
-                  (32, 32, 16), (128, 64, 32), (64, 128, 32), (64, 64, 32), (32, 64, 32)}
+# (tm, tn, kc, K groups): the LDS kernels with one and two K groups, and the
+# small-batch kernel (K groups 8) for 2B <= 64
+SHAPES_BATCHED = {(128, 128, 16, 1), (128, 64, 16, 1), (64, 128, 16, 1), (64, 64, 16, 1), (64, 32, 16, 1),
+                  (32, 64, 16, 1), (32, 32, 16, 1), (128, 64, 32, 1), (64, 128, 32, 1), (64, 64, 32, 1),
+                  (32, 64, 32, 1), (32, 64, 32, 2), (32, 32, 16, 2), (32, 32, 16, 8), (32, 64, 16, 8)}
 
 
 def rel_l2(a, b):
@@ -32,11 +35,13 @@ def test_tune_writes_cache_and_plans_use_it(lmax, n, batch, tmp_path, monkeypatc
     data = json.loads(cache.read_text())
     assert data["arch"].startswith("gfx")
     entry = data["entries"][f"L{lmax}_N{n}_B{batch}"]
+    # the same choice under the shape's bucket (n rounded up to a multiple of 64)
+    assert data["entries"][f"L{lmax}_N{(n + 63) // 64 * 64}b_B{batch}"] == entry
     if batch == 1:
         t0 = (n + 127) // 128
-        assert t0 <= entry["T"] <= t0 + 3 and entry["tm"] == 0
+        assert t0 <= entry["T"] <= min(t0 + 3, 8) and entry["tm"] == 0
     else:
-        assert (entry["tm"], entry["tn"], entry["kc"]) in SHAPES_BATCHED and entry["T"] == 0
+        assert (entry["tm"], entry["tn"], entry["kc"], entry["ks"]) in SHAPES_BATCHED and entry["T"] == 0
     assert entry["us_per_step"] > 0
     # a second shape is added to the same cache, the first one kept
     tune(1, 40, 2, str(cache))
@@ -44,14 +49,16 @@ def test_tune_writes_cache_and_plans_use_it(lmax, n, batch, tmp_path, monkeypatc
     assert f"L{lmax}_N{n}_B{batch}" in data2["entries"] and "L1_N40_B2" in data2["entries"]
 
     monkeypatch.setenv("TDSE_TUNE_CACHE", str(cache))
-    h = wl.hamiltonian(lmax, n, 9)
-    dt, nsteps = 0.01, 40
-    ps = wl.random_pulses(np.random.default_rng(4), batch, ncyc=2.0)
-    f = np.stack([wl.rk4_samples(wl.Pulse(p.e0 * 5, p.omega, p.ncyc), dt, nsteps) for p in ps])
-    c0 = wl.random_state(np.random.default_rng(5), h.nstates, batch)
-    got = Plan(h.energies, h.dipole, batch=batch).propagate(f, c0, dt, "rk4").cpu().numpy()
-    ref = oracle.rk4(h.energies, h.dipole, dt, f, c0, n=n)
-    assert rel_l2(got, ref) <= TOL
+    # the tuned shape itself, and an untuned one of the same bucket (served by the bucket entry)
+    for nn in (n, n + 7):
+        h = wl.hamiltonian(lmax, nn, 9)
+        dt, nsteps = 0.01, 40
+        ps = wl.random_pulses(np.random.default_rng(4), batch, ncyc=2.0)
+        f = np.stack([wl.rk4_samples(wl.Pulse(p.e0 * 5, p.omega, p.ncyc), dt, nsteps) for p in ps])
+        c0 = wl.random_state(np.random.default_rng(5), h.nstates, batch)
+        got = Plan(h.energies, h.dipole, batch=batch).propagate(f, c0, dt, "rk4").cpu().numpy()
+        ref = oracle.rk4(h.energies, h.dipole, dt, f, c0, n=nn)
+        assert rel_l2(got, ref) <= TOL, nn
 
 
 def test_tune_cache_of_another_architecture_is_ignored(tmp_path, monkeypatch):
