@@ -154,6 +154,29 @@ tdse_status tdse_propagate(tdse_plan plan, tdse_method method, int32_t taylor_or
                            double *ckpt, int32_t ckpt_every, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the RK4 /
+ * Taylor-p propagation of tdse_propagate on a batch-1 plan, with the same
+ * arguments and the same result (the same kernels in the same order), that
+ * allocates nothing. Its per-call scratch -- state vectors and product
+ * partials of both launch parities and the call descriptor -- lives in one
+ * fixed 16 MiB device array of the library (one per device, held until the
+ * process ends) instead of the plan's own buffers, and it enqueues every
+ * launch directly instead of replaying a captured graph.
+ * Limits: batch-1 plans only, RK4 and Taylor only (TDSE_E_UNSUPPORTED
+ * otherwise); problems whose scratch exceeds 16 MiB (96 (lmax+1) n bytes
+ * plus 8 lmax ceil(n/128)^2 KiB, e.g. Lmax = 15, N = 1000) are rejected with
+ * TDSE_E_UNSUPPORTED; the plan's device must be current (TDSE_E_INVAL).
+ * Concurrency: every call on one device shares the array, so calls that
+ * overlap on one device (on other streams or threads) race on it; calls
+ * ordered on one stream are safe (each call re-initialises what it reads).
+ * Other errors as tdse_propagate.
+ */
+tdse_status tdse_propagate_noalloc(tdse_plan plan, tdse_method method, int32_t taylor_order, double dt,
+                                   int64_t nsteps, const double *field, const double *c0, double *cT,
+                                   double *ckpt, int32_t ckpt_every, void *stream);
+
+/*
  * Runge-Kutta-Fehlberg 4(5) propagation (the embedded pair of appendix B's
  * explicit Runge-Kutta family): six stages per step at t_k + c_i dt,
  * c = (0, 1/4, 3/8, 12/13, 1, 1/2), field [batch][nsteps][6] device samples

@@ -32,6 +32,7 @@ SIGNATURES = {
     "tdse_plan_shape": (_st, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "tdse_hmul": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "tdse_propagate": (_st, [_vp, _st, _i32, _d, _i64, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "tdse_propagate_noalloc": (_st, [_vp, _st, _i32, _d, _i64, _vp, _vp, _vp, _vp, _i32, _vp]),
     "tdse_propagate_rkf45": (_st, [_vp, _d, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "tdse_propagate_adaptive": (_st, [_vp, _d, _d, _d, _d, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i64), _vp]),
     "tdse_check_stability": (_st, [_vp, _st, _i32, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d)]),

@@ -113,6 +113,21 @@ class Plan:
                                        _stream(self.device)))
         return (cT, ck) if ckpt_every > 0 else cT
 
+    def propagate_noalloc(self, field, c0, dt: float, method: str = "rk4", order: int = 8, ckpt=None,
+                          ckpt_every: int = 0, out=None):
+        """tdse_propagate_noalloc: as propagate (batch-1 plans, RK4 or Taylor),
+        with the library's fixed scratch array; allocates nothing on the device
+        beyond what the caller passes (out and ckpt must be given for that)."""
+        m = METHODS[method]
+        f = _dev_f64(field, self.device)
+        nsteps = f.numel() // (self.batch * slots_of(method))
+        c0 = self._state(c0)
+        cT = out if out is not None else torch.empty_like(c0)
+        check(self._lib.tdse_propagate_noalloc(self._h, m, int(order), float(dt), nsteps, _ptr(f), _ptr(c0),
+                                               _ptr(cT), _ptr(ckpt), int(ckpt_every) if ckpt is not None else 0,
+                                               _stream(self.device)))
+        return cT
+
     def propagate_rkf45(self, field, c0, dt: float, ckpt_every: int = 0, out=None):
         """Runge-Kutta-Fehlberg 4(5) over field [B, nsteps, 6] (samples at the six
         stage times); returns (cT, err [B, nsteps]) and the checkpoints if asked."""
