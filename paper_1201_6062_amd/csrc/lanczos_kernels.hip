@@ -7,7 +7,8 @@
 // plan's own product kernels; these kernels do the per-pulse reductions,
 // the recurrence, the small exponential and the recombination. Vectors are in
 // the caller layout [pulse][2 n] (interleaved complex). With several pulses
-// the recurrence runs in one workgroup per pulse. A single pulse on a plan of
+// the recurrence runs over many workgroups per pulse, alpha from parts the
+// batched product leaves. A single pulse on a plan of
 // the fused tile path takes one launch per product (vec_lz_fused_kernel, over
 // unnormalised vectors, with alpha and the norms summed from parts the
 // previous launch left); on a split-path plan two: alpha from the completion
@@ -19,96 +20,121 @@
 
 namespace tdse {
 
-constexpr int LZ_THREADS = 1024;
 // Loops over a pulse's vector take LZ_BATCH elements per thread at a time,
 // every load of a batch issued before its first use (a loop that used each
 // load at once would wait for every one in turn); within a thread the
 // elements are still combined in ascending order.
 constexpr int LZ_BATCH = 4;
 
-// beta0 = |c|, v_1 = c / beta0 (zero when c == 0). One workgroup per pulse.
-__global__ __launch_bounds__(LZ_THREADS) void lz_begin_kernel(const double *c, double *v1, double *beta0,
-                                                              int64_t len) {
-    __shared__ double red[LZ_THREADS / 64];
-    const int b = blockIdx.x;
-    const double *cb = c + (size_t)b * len;
-    double s = 0.0;
-    int64_t e = threadIdx.x;
-    for (; e + (LZ_BATCH - 1) * LZ_THREADS < len; e += LZ_BATCH * LZ_THREADS) {
-        double x[LZ_BATCH];
+// ---- Several pulses: the products run batched on the matrix cores; the
+// recurrence runs over many workgroups, grid (chunks, pulses), each workgroup
+// one chunk of LZB_CHUNK doubles of one pulse's vector. alpha_j comes from the
+// per-(row tile, pulse) parts of Re <v_j, H v_j> that the product's epilogue
+// leaves; norms from per-chunk parts. Every workgroup of a pulse sums the
+// same parts in the same order, so all of them hold the same value.
+constexpr int LZB_THREADS = 256;
+constexpr int LZB_CHUNK = LZB_THREADS * LZ_BATCH;
+
+int lzb_chunks(int64_t len) { return (int)((len + LZB_CHUNK - 1) / LZB_CHUNK); }
+
+// normp[b * G + g]: chunk g's part of |x_b|^2 (x in the caller layout [B][len]).
+__global__ __launch_bounds__(LZB_THREADS) void lzb_norm_parts_kernel(const double *x, int64_t len, double *normp) {
+    __shared__ double red[LZB_THREADS / 64];
+    const int g = blockIdx.x, b = blockIdx.y, G = gridDim.x;
+    const double *xb = x + (size_t)b * len;
+    const int64_t e0 = (int64_t)g * LZB_CHUNK + threadIdx.x;
+    double v[LZ_BATCH];
 #pragma unroll
-        for (int r = 0; r < LZ_BATCH; ++r) x[r] = cb[e + r * LZ_THREADS];
-#pragma unroll
-        for (int r = 0; r < LZ_BATCH; ++r) s = fma(x[r], x[r], s);
+    for (int r = 0; r < LZ_BATCH; ++r) {
+        const int64_t e = e0 + r * LZB_THREADS;
+        v[r] = e < len ? xb[e] : 0.0;
     }
-    for (; e < len; e += LZ_THREADS) s = fma(cb[e], cb[e], s);
-    const double nrm = sqrt(block_sum<LZ_THREADS>(s, red));
-    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    double *vb = v1 + (size_t)b * len;
-    for (e = threadIdx.x; e < len; e += LZ_THREADS) vb[e] = cb[e] * inv;
-    if (threadIdx.x == 0) beta0[b] = nrm;
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < LZ_BATCH; ++r) s = fma(v[r], v[r], s);
+    s = block_sum<LZB_THREADS>(s, red);
+    if (threadIdx.x == 0) normp[(size_t)b * G + g] = s;
 }
 
-// One Lanczos recurrence step j (0-based) for every pulse: w = H v_j on
-// entry; alpha_j = Re <v_j, w>; w -= alpha_j v_j + beta_{j-1} v_{j-1};
-// unless last: beta_j = |w| and v_{j+1} = w / beta_j. A breakdown (beta_j <=
-// 1e-13 (|alpha_j| + beta_{j-1})) sets beta_j = 0 and v_{j+1} = 0, so the
-// remaining steps add nothing.
-__global__ __launch_bounds__(LZ_THREADS) void lz_orth_kernel(const double *vj, const double *vjm1, double *w,
-                                                             double *vnext, double *alpha, double *beta, int j,
-                                                             int m, int last, int64_t len) {
-    __shared__ double red[LZ_THREADS / 64];
-    const int b = blockIdx.x;
-    const size_t off = (size_t)b * len;
-    // (for j = 0, pb points at v_j: never read then, but a valid address)
-    const double *vb = vj + off, *pb = j > 0 ? vjm1 + off : vb;
-    double *wb = w + off;
-    double s = 0.0;
-    int64_t e = threadIdx.x;
-    for (; e + (LZ_BATCH - 1) * LZ_THREADS < len; e += LZ_BATCH * LZ_THREADS) {
-        double x[LZ_BATCH], y[LZ_BATCH];
-#pragma unroll
-        for (int r = 0; r < LZ_BATCH; ++r) {
-            x[r] = vb[e + r * LZ_THREADS];
-            y[r] = wb[e + r * LZ_THREADS];
-        }
-#pragma unroll
-        for (int r = 0; r < LZ_BATCH; ++r) s = fma(x[r], y[r], s);
-    }
-    for (; e < len; e += LZ_THREADS) s = fma(vb[e], wb[e], s);
-    const double a = block_sum<LZ_THREADS>(s, red);
-    const double bprev = j > 0 ? beta[(size_t)b * m + j - 1] : 0.0;
-    double s2 = 0.0;
-    e = threadIdx.x;
-    for (; e + (LZ_BATCH - 1) * LZ_THREADS < len; e += LZ_BATCH * LZ_THREADS) {
-        double x[LZ_BATCH], v[LZ_BATCH], p[LZ_BATCH];
-#pragma unroll
-        for (int r = 0; r < LZ_BATCH; ++r) {
-            x[r] = wb[e + r * LZ_THREADS];
-            v[r] = vb[e + r * LZ_THREADS];
-            p[r] = j > 0 ? pb[e + r * LZ_THREADS] : 0.0;
-        }
-#pragma unroll
-        for (int r = 0; r < LZ_BATCH; ++r) {
-            double xr = x[r] - a * v[r];
-            if (j > 0) xr -= bprev * p[r];
-            wb[e + r * LZ_THREADS] = xr;
-            s2 = fma(xr, xr, s2);
-        }
-    }
-    for (; e < len; e += LZ_THREADS) {
-        double x = wb[e] - a * vb[e];
-        if (j > 0) x -= bprev * pb[e];
-        wb[e] = x;
-        s2 = fma(x, x, s2);
-    }
-    if (threadIdx.x == 0) alpha[(size_t)b * m + j] = a;
+// alpha_j = sum over row tiles of the product's parts (dotp [rowtiles][B]);
+// unless last: w -= alpha_j v_j + beta_{j-1} v_{j-1} over this chunk and its
+// part of |w|^2. Workgroup (0, b) stores alpha_j.
+__global__ __launch_bounds__(LZB_THREADS) void lzb_update_kernel(const double *dotp, int rowtiles, const double *vj,
+                                                                 const double *vjm1, double *w, double *alpha,
+                                                                 const double *beta, double *normp, int j, int m,
+                                                                 int last, int64_t len) {
+    __shared__ double red[LZB_THREADS / 64];
+    const int g = blockIdx.x, b = blockIdx.y, G = gridDim.x, B = gridDim.y;
+    double pa = 0.0;
+    for (int rt = threadIdx.x; rt < rowtiles; rt += LZB_THREADS) pa += dotp[(size_t)rt * B + b];
+    const double a = block_sum<LZB_THREADS>(pa, red);
+    if (g == 0 && threadIdx.x == 0) alpha[(size_t)b * m + j] = a;
     if (last) return;
-    double bj = sqrt(block_sum<LZ_THREADS>(s2, red));
-    if (bj <= 1e-13 * (fabs(a) + bprev)) bj = 0.0;
-    const double inv = bj > 0.0 ? 1.0 / bj : 0.0;
-    for (e = threadIdx.x; e < len; e += LZ_THREADS) vnext[off + e] = wb[e] * inv;
-    if (threadIdx.x == 0) beta[(size_t)b * m + j] = bj;
+    const double bprev = j > 0 ? beta[(size_t)b * m + j - 1] : 0.0;
+    const size_t off = (size_t)b * len;
+    const int64_t e0 = (int64_t)g * LZB_CHUNK + threadIdx.x;
+    double x[LZ_BATCH], v[LZ_BATCH], pv[LZ_BATCH];
+#pragma unroll
+    for (int r = 0; r < LZ_BATCH; ++r) {
+        const int64_t e = e0 + r * LZB_THREADS;
+        const bool in = e < len;
+        x[r] = in ? w[off + e] : 0.0;
+        v[r] = in ? vj[off + e] : 0.0;
+        pv[r] = in && j > 0 ? vjm1[off + e] : 0.0;
+    }
+    double s2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < LZ_BATCH; ++r) {
+        const int64_t e = e0 + r * LZB_THREADS;
+        double xr = x[r] - a * v[r];
+        if (j > 0) xr -= bprev * pv[r];
+        if (e < len) w[off + e] = xr;
+        s2 = fma(xr, xr, s2);
+    }
+    s2 = block_sum<LZB_THREADS>(s2, red);
+    if (threadIdx.x == 0) normp[(size_t)b * G + g] = s2;
+}
+
+// v = x / |x| per pulse, |x| from the per-chunk parts: j < 0 (the start of a
+// step, x = c): beta0[b] = |c|; j >= 0: beta_j = |w| with the breakdown rule
+// (beta_j <= 1e-13 (|alpha_j| + beta_{j-1}) counts as zero, and v = 0). v is
+// written in the caller layout (vout) and into the batched plan's product
+// input (u, layout [lmax+1][np][ldu], column 2b / 2b+1 = re / im of pulse b),
+// which the next product reads.
+__global__ __launch_bounds__(LZB_THREADS) void lzb_normalize_kernel(const double *x, const double *normp,
+                                                                    double *vout, double *u, int lmax, int n, int np,
+                                                                    int ldu, int j, int m, const double *alpha,
+                                                                    double *beta, double *beta0, int64_t len) {
+    __shared__ double red[LZB_THREADS / 64];
+    const int g = blockIdx.x, b = blockIdx.y, G = gridDim.x;
+    double nb = sqrt(block_sum_array<LZB_THREADS>(normp + (size_t)b * G, G, red));
+    if (j >= 0) {
+        const double bprev = j > 0 ? beta[(size_t)b * m + j - 1] : 0.0;
+        if (nb <= 1e-13 * (fabs(alpha[(size_t)b * m + j]) + bprev)) nb = 0.0;
+    }
+    if (g == 0 && threadIdx.x == 0) {
+        if (j < 0) beta0[b] = nb;
+        else beta[(size_t)b * m + j] = nb;
+    }
+    const double inv = nb > 0.0 ? 1.0 / nb : 0.0;
+    const size_t off = (size_t)b * len;
+    const int64_t e0 = (int64_t)g * LZB_CHUNK + threadIdx.x;
+    double xv[LZ_BATCH];
+#pragma unroll
+    for (int r = 0; r < LZ_BATCH; ++r) {
+        const int64_t e = e0 + r * LZB_THREADS;
+        xv[r] = e < len ? x[off + e] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < LZ_BATCH; ++r) {
+        const int64_t e = e0 + r * LZB_THREADS;
+        if (e >= len) continue;
+        const double v = xv[r] * inv;
+        vout[off + e] = v;
+        const int64_t st = e >> 1;  // state index m n + row
+        const int blk = (int)(st / n), row = (int)(st - (int64_t)blk * n);
+        u[((size_t)blk * np + row) * ldu + 2 * b + (e & 1)] = v;
+    }
 }
 
 // Value of the previous (lane - 1) and next (lane + 1) lane, zero at the ends
@@ -447,14 +473,21 @@ hipError_t lz_combine_wide(double *V, const double *y, int m, int64_t ncplx, dou
     return hipGetLastError();
 }
 
-hipError_t lz_begin(const double *c, double *v1, double *beta0, int batch, int64_t len, hipStream_t s) {
-    hipLaunchKernelGGL(lz_begin_kernel, dim3(batch), dim3(LZ_THREADS), 0, s, c, v1, beta0, len);
+hipError_t lzb_norm_parts(const double *x, int batch, int64_t len, double *normp, hipStream_t s) {
+    hipLaunchKernelGGL(lzb_norm_parts_kernel, dim3(lzb_chunks(len), batch), dim3(LZB_THREADS), 0, s, x, len, normp);
     return hipGetLastError();
 }
-hipError_t lz_orth(const double *vj, const double *vjm1, double *w, double *vnext, double *alpha, double *beta,
-                   int j, int m, int last, int batch, int64_t len, hipStream_t s) {
-    hipLaunchKernelGGL(lz_orth_kernel, dim3(batch), dim3(LZ_THREADS), 0, s, vj, vjm1, w, vnext, alpha, beta, j, m,
-                       last, len);
+hipError_t lzb_update(const double *dotp, int rowtiles, const double *vj, const double *vjm1, double *w,
+                      double *alpha, const double *beta, double *normp, int j, int m, int last, int batch,
+                      int64_t len, hipStream_t s) {
+    hipLaunchKernelGGL(lzb_update_kernel, dim3(lzb_chunks(len), batch), dim3(LZB_THREADS), 0, s, dotp, rowtiles, vj,
+                       vjm1, w, alpha, beta, normp, j, m, last, len);
+    return hipGetLastError();
+}
+hipError_t lzb_normalize(const BatBuffers &bb, const double *x, const double *normp, double *vout, int j, int m,
+                         const double *alpha, double *beta, double *beta0, int64_t len, hipStream_t s) {
+    hipLaunchKernelGGL(lzb_normalize_kernel, dim3(lzb_chunks(len), bb.batch), dim3(LZB_THREADS), 0, s, x, normp, vout,
+                       bb.u[0], bb.lmax, bb.n, bb.np, bb.ldu, j, m, alpha, beta, beta0, len);
     return hipGetLastError();
 }
 hipError_t lz_expm(const double *alpha, const double *beta, const double *beta0, double dt, const double *dt_dev,

@@ -330,10 +330,11 @@ __global__ __launch_bounds__(256 * KS) __attribute__((amdgpu_waves_per_eu(1, 2))
                     const double yre = is_im ? fma(F, zp, E0 * up) : fma(F, z, E0 * uo);
                     const double yim = is_im ? fma(F, z, E0 * uo) : fma(F, zp, E0 * up);
                     const double k = is_im ? -yre : yim;
-                    if (L.kind == CK_HMUL) {  // single product y = H u (tdse_hmul)
+                    if (L.kind == CK_HMUL) {  // single product y = H u (tdse_hmul; Krylov products)
                         if (pulse < B && row < b.n)
                             L.out[(size_t)pulse * 2 * (lmax + 1) * b.n + 2 * ((size_t)m * b.n + row) +
                                   (is_im ? 1 : 0)] = is_im ? yim : yre;
+                        gsum[j] = fma(uo, is_im ? yim : yre, gsum[j]);  // this column's part of Re <u, y>
                         continue;
                     }
                     if (L.ustore) L.ustore[gi] = uo;  // forward recompute for the adjoint
@@ -400,9 +401,10 @@ __global__ __launch_bounds__(256 * KS) __attribute__((amdgpu_waves_per_eu(1, 2))
             }
         }
     }
-    if (ADJ || (L.kind == CK_RKF && L.slot == 5 && L.gpart != nullptr)) {
+    if (ADJ || (((L.kind == CK_RKF && L.slot == 5) || L.kind == CK_HMUL) && L.gpart != nullptr)) {
         // Per-pulse partial of this row tile (adjoint: the field gradient;
-        // Runge-Kutta-Fehlberg: the squared error estimate): rows of one lane
+        // Runge-Kutta-Fehlberg: the squared error estimate; single product:
+        // Re <u, H u>, the Krylov recurrence's alpha): rows of one lane
         // (i, r), then the four 16-lane row groups, then the real/imaginary
         // column pair, then the two row halves of the tile.
         __shared__ double gred[2][TN];
@@ -607,6 +609,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 if (live)
                     *reinterpret_cast<dv2b_t *>(L.out + (size_t)pulse[e] * 2 * (lmax + 1) * b.n +
                                                 2 * ((size_t)m * b.n + row[e])) = dv2b_t{yr, yi};
+                gsum = fma(ur, yr, gsum);  // this entry's part of Re <u, y>
+                gsum = fma(ui, yi, gsum);
                 continue;
             }
             if (L.ustore) *reinterpret_cast<dv2b_t *>(L.ustore + gi[e]) = uo[e];
@@ -683,7 +687,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                                             2 * ((size_t)m * b.n + row[e])) = dv2b_t{c_r, c_i};
         }
     }
-    if (ADJ || (L.kind == CK_RKF && L.slot == 5 && L.gpart != nullptr)) {
+    if (ADJ || (((L.kind == CK_RKF && L.slot == 5) || L.kind == CK_HMUL) && L.gpart != nullptr)) {
         // per-pulse sum over the tile's 32 rows: the thread's own entries, the
         // four row groups q of the wave, then (in LDS, in wave order) the waves
         // holding the same column group

@@ -509,6 +509,7 @@ static hipError_t lz_product(tdse_plan p, const double *field, int64_t nsteps, i
 struct LzWork {
     double *V, *W, *alpha, *beta, *beta0, *y, *C;
     double *dotp, *normp;  // one pulse: per-segment dots, per-workgroup norms
+    double *bdot, *bnorm;  // several pulses: per-(row tile, pulse) alpha parts, per-(pulse, chunk) norm parts
     double *qp[2], *ep[2], *np[2];  // one pulse, one launch per product: parts by parity
     size_t vstride;
     int64_t len, ncplx;
@@ -591,16 +592,32 @@ static hipError_t lz_enqueue_steps(tdse_plan p, const LzWork &w, int m, double d
                                     s);
             continue;
         }
-        // one workgroup per pulse
-        e = lz_begin(c, w.V, w.beta0, B, w.len, s);
+        // several pulses: batched products on the matrix cores (each leaving
+        // per-row-tile parts of alpha), the recurrence over many workgroups
+        BatBuffers bb = p->bb;
+        bb.field = field;
+        const int rowtiles = (bb.lmax + 1) * (bb.np / bb.tm);
+        e = lzb_norm_parts(c, B, w.len, w.bnorm, s);
+        if (e == hipSuccess) e = lzb_normalize(bb, c, w.bnorm, w.V, -1, m, w.alpha, w.beta, w.beta0, w.len, s);
         for (int j = 0; j < m && e == hipSuccess; ++j) {
             const double *vj = w.V + (size_t)j * w.vstride;
             const bool last = j + 1 == m;
-            double *vnext = last ? nullptr : w.V + (size_t)(j + 1) * w.vstride;
-            e = lz_product(p, field, nsteps, k, base, vj, w.W, nullptr, nullptr, true, s);
+            BatLaunch L{};
+            L.kind = CK_HMUL;
+            L.parity = 0;  // the product input is u[0], written by lzb_normalize
+            L.dt = 1.0;
+            L.step = k;
+            L.nsteps = nsteps;
+            L.slots = 1;
+            L.out = w.W;
+            L.gpart = w.bdot;
+            e = bat_launch_stage(bb, L, s);
             if (e == hipSuccess)
-                e = lz_orth(vj, j > 0 ? vj - w.vstride : nullptr, w.W, vnext, w.alpha, w.beta, j, m, last ? 1 : 0,
-                            B, w.len, s);
+                e = lzb_update(w.bdot, rowtiles, vj, j > 0 ? vj - w.vstride : nullptr, w.W, w.alpha, w.beta,
+                               w.bnorm, j, m, last ? 1 : 0, B, w.len, s);
+            if (e == hipSuccess && !last)
+                e = lzb_normalize(bb, w.W, w.bnorm, w.V + (size_t)(j + 1) * w.vstride, j, m, w.alpha, w.beta,
+                                  w.beta0, w.len, s);
         }
         if (e == hipSuccess) e = lz_expm(w.alpha, w.beta, w.beta0, dt, dt_dev, m, B, w.y, nullptr, 0, s);
         if (e == hipSuccess)
@@ -618,8 +635,10 @@ static tdse_status lz_propagate(tdse_plan p, int m, double dt, int64_t nsteps, c
     // steps a state vector of the plan's own (a graph cannot follow cT)
     const size_t nseg = (size_t)(p->lmax + 1) * (p->T > 0 ? p->T : 1);
     const size_t ntl = (size_t)p->lmax * (p->T > 0 ? p->T : 1) * (p->T > 0 ? p->T : 1);
+    const size_t nbdot = B > 1 ? (size_t)(p->lmax + 1) * (p->bb.np / p->bb.tm) * B : 0;
+    const size_t nbnorm = B > 1 ? (size_t)lzb_chunks(len) * B : 0;
     const size_t need = ((size_t)(m + 2) * vstride + (size_t)B * (4 * m + 1) + 2 * nseg +
-                         (size_t)lz_wide_groups(ncplx) + 2 * (2 * ntl + 2 * nseg)) * sizeof(double);
+                         (size_t)lz_wide_groups(ncplx) + 2 * (2 * ntl + 2 * nseg) + nbdot + nbnorm) * sizeof(double);
     if (need > p->lz_bytes) {
         if (p->lz_mem) (void)hipFree(p->lz_mem);
         p->lz_mem = nullptr;
@@ -658,6 +677,9 @@ static tdse_status lz_propagate(tdse_plan p, int m, double dt, int64_t nsteps, c
             w.np[q] = pp;
             pp += nseg;
         }
+        w.bdot = pp;
+        pp += nbdot;
+        w.bnorm = pp;
     }
     w.vstride = vstride;
     w.len = len;

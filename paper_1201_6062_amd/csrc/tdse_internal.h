@@ -199,7 +199,8 @@ struct BatLaunch {
     // forward recompute: copy this stage's input u to ustore (internal layout)
     // adjoint: ustore holds the forward input of the stage being reversed
     double *ustore;
-    double *gpart;         // adjoint: per row-tile gradient partials [row tiles][batch]
+    double *gpart;         // per row-tile partials [row tiles][batch]: adjoint field gradient, RKF45
+                           // squared error, or (single product, if set) Re <u, H u>
     double p_lam, p_ub;    // adjoint: next input = p_lam * lambda + p_ub * ubar
 };
 
@@ -222,9 +223,18 @@ hipError_t bat_launch_stage(const BatBuffers &b, const BatLaunch &l, hipStream_t
 
 // ---------------------------------------------------------------------------
 // Short-iterative Lanczos (caller-layout vectors [batch][len], len = 2 nstates).
-hipError_t lz_begin(const double *c, double *v1, double *beta0, int batch, int64_t len, hipStream_t s);
-hipError_t lz_orth(const double *vj, const double *vjm1, double *w, double *vnext, double *alpha, double *beta,
-                   int j, int m, int last, int batch, int64_t len, hipStream_t s);
+// Several pulses (batched plans): the recurrence over many workgroups, grid
+// (lzb_chunks(len), batch). normp: [batch][chunks] norm parts; dotp: the
+// product's per-(row tile, pulse) parts of Re <v_j, H v_j>, [rowtiles][batch].
+int lzb_chunks(int64_t len);
+hipError_t lzb_norm_parts(const double *x, int batch, int64_t len, double *normp, hipStream_t s);
+hipError_t lzb_update(const double *dotp, int rowtiles, const double *vj, const double *vjm1, double *w,
+                      double *alpha, const double *beta, double *normp, int j, int m, int last, int batch,
+                      int64_t len, hipStream_t s);
+// v = x / |x| into vout (caller layout) and into the plan's product input u[0]
+// (j < 0: beta0 = |x|; j >= 0: beta_j with the breakdown rule)
+hipError_t lzb_normalize(const BatBuffers &bb, const double *x, const double *normp, double *vout, int j, int m,
+                         const double *alpha, double *beta, double *beta0, int64_t len, hipStream_t s);
 // One pulse over many workgroups. The Krylov vectors are formed unnormalised
 // (x_0 = c, x_{j+1} = H v_j - alpha_j v_j - beta_{j-1} v_{j-1}), each launch
 // that forms one leaving per-workgroup parts of |x|^2 in normp; the product
