@@ -31,8 +31,8 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 matrix / vector
 
 METRIC = "state-steps/s (matvec % HBM peak; batched % FP64 MFMA) at 1e-10 vs oracle"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vec_tiles_L15_N500.json")
-# sources that determine the tile kernel's memory traffic
-TILE_KERNEL_SOURCES = ["vec_kernels.hip", "tdse_internal.h", "tdse_split.h"]
+# sources that determine the tile kernel's code (and so its traffic and trace)
+TILE_KERNEL_SOURCES = ["vec_kernels.hip", "tdse_vec.h", "tdse_split.h", "tdse_tile.h", "tdse_reduce.h"]
 
 
 def tile_kernel_hash() -> str:
