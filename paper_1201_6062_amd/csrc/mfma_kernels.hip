@@ -279,106 +279,137 @@ __global__ __launch_bounds__(256 * KS) __attribute__((amdgpu_waves_per_eu(1, 2))
         }
     }
 
-    // ---- epilogue
+    // ---- epilogue. It runs one row subtile i at a time: first every load of
+    // that subtile's SN x 4 entries (state, stage input, energies, stored
+    // stage derivatives), then the arithmetic and the stores. Loads placed
+    // after the previous entry's stores would each wait for their own round
+    // trip (the compiler cannot move a load above a store it cannot prove
+    // disjoint), one latency per entry instead of one per subtile.
     const int B = b.batch;
     const int64_t step = L.step;
     const double dt = L.dt;
     double *Un = par ? b.u[0] : b.u[1];
     double gsum[C::SN];
+    double Fj[C::SN];
 #pragma unroll
-    for (int j = 0; j < C::SN; ++j) gsum[j] = 0.0;
+    for (int j = 0; j < C::SN; ++j) {
+        gsum[j] = 0.0;
+        const int col = c0 + wx * C::WN + j * 16 + (lane & 15);
+        Fj[j] = (col >> 1) < B ? b.field[((size_t)(col >> 1) * L.nsteps + step) * L.slots + L.slot] : 0.0;
+    }
+    const bool rkf = L.kind == CK_RKF;
+    const int st = L.slot;
+    const size_t kstride = (size_t)(lmax + 1) * Np * ldu;
     // (with two K groups, group 0 completes the stage; group 1 only passes
     // the barriers below)
 #pragma unroll
     for (int i = 0; i < (kg == 0 ? C::SM : 0); ++i) {
 #pragma unroll
         for (int j = 0; j < C::SN; ++j) {
-            const int col = c0 + wx * C::WN + j * 16 + (lane & 15);
-            const bool is_im = col & 1;
-            const int pulse = col >> 1;
-            double F = 0.0;
-            if (pulse < B) F = b.field[((size_t)pulse * L.nsteps + step) * L.slots + L.slot];
+            // the loads of this (i, j) group's four entries, then their arithmetic
+            size_t gi[4];
+            double uo[4], cv[4], av[4], us[4], E0[4], kq[4][5];
+            const int colg = c0 + wx * C::WN + j * 16 + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = r0 + wy * C::WM + i * 16 + (lane >> 4) + 4 * r;
-                const size_t gi = ((size_t)m * Np + row) * ldu + col;
-                const double E0 = b.en[(size_t)m * Np + row];
+                E0[r] = b.en[(size_t)m * Np + row];
+                gi[r] = ((size_t)m * Np + row) * ldu + colg;
+                uo[r] = U[gi[r]];
+                cv[r] = b.c[gi[r]];
+                av[r] = b.acc[gi[r]];
+                us[r] = ADJ ? L.ustore[gi[r]] : 0.0;
+            }
+            if (!ADJ && rkf) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q)
+                    if (q < st) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) kq[r][q] = b.kst[(size_t)q * kstride + gi[r]];
+                    }
+            }
+            const bool is_im = colg & 1;
+            const int pulse = colg >> 1;
+            const double F = Fj[j];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + wy * C::WM + i * 16 + (lane >> 4) + 4 * r;
+                const size_t g = gi[r];
                 // coupling product of this column (z) and of its real/imaginary
                 // partner (zp); velocity gauge: -i times the contraction
                 const double zc = acc[i][j][r], zcp = bat_xor1(zc);
                 const double z = b.gauge ? (is_im ? -zcp : zcp) : zc;
                 const double zp = b.gauge ? (is_im ? zc : -zc) : zcp;
-                const double uo = U[gi], up = bat_xor1(uo);
+                const double u0 = uo[r], up = bat_xor1(u0);
                 if constexpr (ADJ) {
                     // ubar = i (E0 kbar + F w): re = -(E0 kbar_im + F w_im), im = E0 kbar_re + F w_re
-                    const double ub = (is_im ? 1.0 : -1.0) * fma(F, zp, E0 * up);
-                    const double us = L.ustore[gi], usp = bat_xor1(us);
+                    const double ub = (is_im ? 1.0 : -1.0) * fma(F, zp, E0[r] * up);
+                    const double usp = bat_xor1(us[r]);
                     // Im(w^H u) = sum (w_re u_im - w_im u_re)
                     gsum[j] += (is_im ? -z : z) * usp;
-                    const double lam = b.c[gi];
-                    const double cb = (L.first ? lam : b.acc[gi]) + ub;
+                    const double lam = cv[r];
+                    const double cb = (L.first ? lam : av[r]) + ub;
                     if (L.kind == CK_ADJ_MID) {
-                        b.acc[gi] = cb;
-                        Un[gi] = fma(L.p_lam, lam, L.p_ub * ub);
+                        b.acc[g] = cb;
+                        Un[g] = fma(L.p_lam, lam, L.p_ub * ub);
                     } else {  // CK_ADJ_LAST: cb is the co-state of c at the step's start
-                        b.c[gi] = cb;
-                        Un[gi] = L.p_lam * cb;
+                        b.c[g] = cb;
+                        Un[g] = L.p_lam * cb;
                     }
                 } else {
                     // own component of y = E0 u + F z and of k = -i y:
                     // k_re = y_im, k_im = -y_re
-                    const double yre = is_im ? fma(F, zp, E0 * up) : fma(F, z, E0 * uo);
-                    const double yim = is_im ? fma(F, z, E0 * uo) : fma(F, zp, E0 * up);
+                    const double yre = is_im ? fma(F, zp, E0[r] * up) : fma(F, z, E0[r] * u0);
+                    const double yim = is_im ? fma(F, z, E0[r] * u0) : fma(F, zp, E0[r] * up);
                     const double k = is_im ? -yre : yim;
                     if (L.kind == CK_HMUL) {  // single product y = H u (tdse_hmul; Krylov products)
                         if (pulse < B && row < b.n)
                             L.out[(size_t)pulse * 2 * (lmax + 1) * b.n + 2 * ((size_t)m * b.n + row) +
                                   (is_im ? 1 : 0)] = is_im ? yim : yre;
-                        gsum[j] = fma(uo, is_im ? yim : yre, gsum[j]);  // this column's part of Re <u, y>
+                        gsum[j] = fma(u0, is_im ? yim : yre, gsum[j]);  // this column's part of Re <u, y>
                         continue;
                     }
-                    if (L.ustore) L.ustore[gi] = uo;  // forward recompute for the adjoint
-                    double c = b.c[gi];
-                    double a = b.acc[gi];
+                    if (L.ustore) L.ustore[g] = u0;  // forward recompute for the adjoint
+                    double c = cv[r];
+                    double a = av[r];
                     double unext;
                     switch (L.kind) {
                     case CK_RK4_MID:
                         a = L.first ? L.w_acc * k : fma(L.w_acc, k, a);
                         unext = fma(L.a_next * dt, k, c);
-                        b.acc[gi] = a;
+                        b.acc[g] = a;
                         break;
                     case CK_RK4_END:
                         c = fma(dt, fma(L.w_acc, k, a), c);
                         unext = c;
-                        b.c[gi] = c;
+                        b.c[g] = c;
                         break;
                     case CK_TAY_MID: {
                         const double tm = L.a_next * dt * k;
                         a = (L.first ? c : a) + tm;
                         unext = tm;
-                        b.acc[gi] = a;
+                        b.acc[g] = a;
                         break;
                     }
                     case CK_RKF: {
                         // stage st: keep k_st, then the next stage input, or after
                         // the sixth stage the fourth-order step and its error
-                        const int st = L.slot;
-                        const size_t ks = (size_t)(lmax + 1) * Np * ldu;
                         double sacc = 0.0, serr = 0.0;
-                        for (int q = 0; q < st; ++q) {
-                            const double kq = b.kst[(size_t)q * ks + gi];
-                            sacc = fma(st < 5 ? RKF_A[st + 1][q] : RKF_B4[q], kq, sacc);
-                            serr = fma(RKF_E[q], kq, serr);
-                        }
+#pragma unroll
+                        for (int q = 0; q < 5; ++q)
+                            if (q < st) {
+                                sacc = fma(st < 5 ? RKF_A[st + 1][q] : RKF_B4[q], kq[r][q], sacc);
+                                serr = fma(RKF_E[q], kq[r][q], serr);
+                            }
                         if (st < 5) {
-                            b.kst[(size_t)st * ks + gi] = k;
+                            b.kst[(size_t)st * kstride + g] = k;
                             unext = fma(dt, fma(RKF_A[st + 1][st], k, sacc), c);
                         } else {
                             c = fma(dt, fma(RKF_B4[5], k, sacc), c);
                             const double e = dt * fma(RKF_E[5], k, serr);
                             gsum[j] = fma(e, e, gsum[j]);
                             unext = c;
-                            b.c[gi] = c;
+                            b.c[g] = c;
                         }
                         break;
                     }
@@ -386,11 +417,11 @@ __global__ __launch_bounds__(256 * KS) __attribute__((amdgpu_waves_per_eu(1, 2))
                         const double tm = L.a_next * dt * k;
                         c = (L.first ? c : a) + tm;
                         unext = c;
-                        b.c[gi] = c;
+                        b.c[g] = c;
                         break;
                     }
                     }
-                    Un[gi] = unext;
+                    Un[g] = unext;
                     const bool ends = L.kind == CK_RK4_END || L.kind == CK_TAY_END || (L.kind == CK_RKF && L.slot == 5);
                     if (L.ckpt && ends && pulse < B && row < b.n) {
                         // caller layout [B][rows][2 n]
@@ -645,14 +676,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 const int st = L.slot;
                 const size_t kstride = (size_t)(lmax + 1) * Np * ldu;
                 double sr = 0.0, si = 0.0, er = 0.0, ei = 0.0;
-                for (int qq = 0; qq < st; ++qq) {
-                    const dv2b_t kq = *reinterpret_cast<const dv2b_t *>(b.kst + (size_t)qq * kstride + gi[e]);
-                    const double wgt = st < 5 ? RKF_A[st + 1][qq] : RKF_B4[qq];
-                    sr = fma(wgt, kq[0], sr);
-                    si = fma(wgt, kq[1], si);
-                    er = fma(RKF_E[qq], kq[0], er);
-                    ei = fma(RKF_E[qq], kq[1], ei);
-                }
+                // the stored stage derivatives, all requested before the first is used
+                dv2b_t kq[5];
+#pragma unroll
+                for (int qq = 0; qq < 5; ++qq)
+                    if (qq < st) kq[qq] = *reinterpret_cast<const dv2b_t *>(b.kst + (size_t)qq * kstride + gi[e]);
+#pragma unroll
+                for (int qq = 0; qq < 5; ++qq)
+                    if (qq < st) {
+                        const double wgt = st < 5 ? RKF_A[st + 1][qq] : RKF_B4[qq];
+                        sr = fma(wgt, kq[qq][0], sr);
+                        si = fma(wgt, kq[qq][1], si);
+                        er = fma(RKF_E[qq], kq[qq][0], er);
+                        ei = fma(RKF_E[qq], kq[qq][1], ei);
+                    }
                 if (st < 5) {
                     *reinterpret_cast<dv2b_t *>(b.kst + (size_t)st * kstride + gi[e]) = dv2b_t{kr, ki};
                     n_r = fma(dt, fma(RKF_A[st + 1][st], kr, sr), c_r);
