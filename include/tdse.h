@@ -251,6 +251,14 @@ tdse_status tdse_check_stability(tdse_plan plan, tdse_method method, int32_t tay
  * dt and ckpt_every (device), or NULL: then the library recomputes them into
  * plan-owned memory first. Forward states between checkpoints are recomputed
  * segment by segment, so memory stays at one segment of stage inputs.
+ * Memory: the workspace (one segment of stage inputs, ckpt_every x products
+ * per step state vectors, and the internal checkpoints when ckpt is NULL) is
+ * allocated on first use and kept by the plan, grown when a later call needs
+ * more (TDSE_E_NOMEM if it cannot be). A batch-1 plan runs the adjoint on a
+ * batched twin of itself, built on the first call: a second copy of the
+ * Hamiltonian in the matrix-core layout (2 lmax Np^2 doubles, Np = n rounded
+ * up to the tile height; about 31 MB at Lmax = 15, N = 500), kept by the plan
+ * and shared with tdse_propagate_rkf45.
  */
 tdse_status tdse_adjoint(tdse_plan plan, tdse_method method, int32_t taylor_order, double dt,
                          int64_t nsteps, const double *field, const double *c0,

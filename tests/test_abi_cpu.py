@@ -110,12 +110,17 @@ def test_adjoint_and_group_argument_errors(lib):
     assert lib.tdse_group_destroy(None) == 0
 
 
-def test_host_logic_native(tmp_path):
-    """Argument rules, the Sec. 4.1 work split and the tile order, compiled host-only with g++."""
+@pytest.mark.parametrize("sanitize", [False, True])
+def test_host_logic_native(tmp_path, sanitize):
+    """Argument rules, the Sec. 4.1 work split, the tile order and the
+    stability bounds, compiled host-only with g++; once plain and once under
+    AddressSanitizer and UndefinedBehaviorSanitizer."""
     import subprocess
     csrc = os.path.join(ROOT, "paper_1201_6062_amd", "csrc")
     exe = str(tmp_path / "host_logic")
-    subprocess.check_call(["g++", "-std=c++17", "-O1", "-I", csrc, "-I", os.path.join(ROOT, "include"),
+    flags = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"] \
+        if sanitize else []
+    subprocess.check_call(["g++", "-std=c++17", "-O1", *flags, "-I", csrc, "-I", os.path.join(ROOT, "include"),
                            os.path.join(ROOT, "tests", "native", "host_logic.cpp"), "-o", exe])
     r = subprocess.run([exe], capture_output=True, text=True)
-    assert r.returncode == 0, r.stdout
+    assert r.returncode == 0, r.stdout + r.stderr

@@ -4,7 +4,9 @@ differences, the dot-product identity, and through torch.autograd.
 Gradients are compared to the oracle's discrete adjoint at 1e-10 relative
 to the largest gradient entry; finite differences (h = 1e-6, the Y(E+h) and
 Y(E-h) runs batched as separate pulses) at 1e-6 relative to the largest
-sampled finite-difference gradient.
+sampled finite-difference gradient, and entry by entry at 1e-6 relative (for
+entries above 1e-3 of the largest; at full size, plus the central
+difference's rounding floor of about 1e-14 Y / h).
 """
 import os
 
@@ -124,6 +126,9 @@ def test_adjoint_vs_central_fd_batched_perturbations():
     fd = (y[0::2] - y[1::2]) / (2 * hstep)
     ga = np.array([g.flat[i] for i in idx])
     assert np.abs(ga - fd).max() <= 1e-6 * np.abs(fd).max(), (ga, fd)
+    # and entry by entry, for every sampled entry above 1e-3 of the largest
+    big = np.abs(fd) >= 1e-3 * np.abs(fd).max()
+    assert np.all(np.abs(ga - fd)[big] <= 1e-6 * np.abs(fd)[big]), (ga, fd)
 
 
 def test_adjoint_full_size_piecewise():
@@ -161,6 +166,10 @@ def test_adjoint_full_size_piecewise():
     fd = (y[0::2] - y[1::2]) / (2 * hstep)
     ga = gk[0, idx]
     assert np.abs(ga - fd).max() <= 1e-6 * np.abs(fd).max(), (ga, fd)
+    # and entry by entry: 1e-6 relative plus the central difference's rounding
+    # floor, about 1e-14 Y / h (Y = this pulse's yield, 2.1e-3)
+    floor = 1e-14 * float(y.mean()) / hstep
+    assert np.all(np.abs(ga - fd) <= 1e-6 * np.abs(fd) + floor), (ga, fd, floor)
 
 
 # ---- Taylor-p adjoint

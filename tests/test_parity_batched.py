@@ -138,7 +138,7 @@ def test_batched_full_size_short():
 
 
 def test_batched_full_length_sampled_pulses():
-    """256 pulses over the whole common T (62832 RK4 steps) in the benchmark's
+    """256 pulses over the whole common T (62149 RK4 steps) in the benchmark's
     launch configuration; 4 pulses vs the stored full-length oracle results,
     every pulse checked for a finite state whose norm stayed near 1 (RK4 at
     dt*max|E| = 0.15 loses at most a little population per step)."""
