@@ -469,6 +469,65 @@ def adjoint_measure(torch, steps: int = 2048, method: str = "rk4", order: int = 
             "flop_per_stage": flop_stage, "tflops": tflops, "frac_of_fp64_peak": tflops / FP64_PEAK_TFLOPS}
 
 
+def tuned_measure(torch, group_steps: int = 400):
+    """The autotuner on the adjoint workload's shape (Lmax=15, N=500, 32
+    pulses: a forward RK4 stage) and on the 64 uneven instances (each shape
+    tuned alone, then the group run on its tuned tile counts), each against
+    the library's default tiles."""
+    import tempfile
+    from paper_1201_6062_amd import workloads as wl
+    from paper_1201_6062_amd.api import Plan, tune
+    out = {}
+    with tempfile.TemporaryDirectory() as td:
+        cache = os.path.join(td, "tune.json")
+        t = time.perf_counter()
+        msg = tune(15, 500, 32, cache)
+        tune_s = time.perf_counter() - t
+        h = wl.hamiltonian(15, 500, 0)
+        pulses = wl.adjoint_pulses(32)
+        f = torch.as_tensor(np.stack([wl.rk4_samples(p, 0.01, 256) for p in pulses]), device="cuda")
+        c0 = torch.as_tensor(wl.ground_state(15, 500, 32), device="cuda")
+
+        def stage_us():
+            plan = Plan(h.energies, h.dipole, batch=32)
+            plan.propagate(f[:, :8], c0, 0.01, "rk4")
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.propagate(f, c0, 0.01, "rk4")
+            e1.record()
+            torch.cuda.synchronize()
+            plan.close()
+            return e0.elapsed_time(e1) * 1e3 / (4 * f.shape[1])
+        default_us = stage_us()
+        os.environ["TDSE_TUNE_CACHE"] = cache
+        try:
+            tuned_us = stage_us()
+        finally:
+            del os.environ["TDSE_TUNE_CACHE"]
+        out["adjoint_shape_B32"] = {"tuner": msg, "tune_s": tune_s, "default_us_per_stage": default_us,
+                                    "tuned_us_per_stage": tuned_us, "tuned_over_default_speed": default_us / tuned_us}
+        t = time.perf_counter()
+        for sp in wl.uneven_specs(64):
+            tune(sp.lmax, sp.n, 1, cache)
+        tune_s = time.perf_counter() - t
+        with open(cache) as fh:
+            ent = json.load(fh)["entries"]
+        moved = sum(1 for sp in wl.uneven_specs(64)
+                    if ent[f"L{sp.lmax}_N{sp.n}_B1"]["T"] != (sp.n + 127) // 128)
+        default = group_measure(torch, steps=group_steps)
+        os.environ["TDSE_TUNE_CACHE"] = cache
+        try:
+            tuned = group_measure(torch, steps=group_steps)
+        finally:
+            del os.environ["TDSE_TUNE_CACHE"]
+        out["uneven_group"] = {"tune_s": tune_s, "instances_off_default_tiles": moved,
+                               "default_frac_of_hbm_peak": default["frac_of_hbm_peak"],
+                               "tuned_frac_of_hbm_peak": tuned["frac_of_hbm_peak"],
+                               "tuned_over_default_speed": tuned["GBps"] / default["GBps"]}
+    return out
+
+
 def calibrate_copy(torch, mb: int = 1024, reps: int = 5):
     """Plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
     x = torch.ones(mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
@@ -490,7 +549,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the small-problem and group measurements")
     ap.add_argument("--only", choices=["single", "diag", "batched", "small", "small_tiles", "group", "taylor8",
                                        "lanczos", "lanczos_b8", "lsweep", "adjoint", "adjoint_taylor8", "rkf45",
-                                       "velocity"],
+                                       "velocity", "tuned"],
                     default=None,
                     help="profiling runs: measure one workload and print its record alone")
     ap.add_argument("--tile", default=None, help="batched tile TMxTN (tuning experiments)")
@@ -540,7 +599,8 @@ def main():
             "adjoint": lambda: adjoint_measure(torch, steps=a.truncate or 2048),
             "adjoint_taylor8": lambda: adjoint_measure(torch, steps=a.truncate or 512, method="taylor", order=8),
             "rkf45": lambda: rkf45_measure(torch, steps=a.truncate or 50),
-            "velocity": lambda: velocity_measure(torch)}
+            "velocity": lambda: velocity_measure(torch),
+            "tuned": lambda: tuned_measure(torch)}
     if a.only in only:
         print(json.dumps(only[a.only]()))
         return
@@ -628,6 +688,7 @@ def main():
         out["adjoint_taylor8"] = adjoint_measure(torch, steps=512, method="taylor", order=8)
         out["rkf45"] = rkf45_measure(torch)
         out["velocity_gauge"] = velocity_measure(torch)
+        out["autotuner"] = tuned_measure(torch)
     out["roofline"]["hbm_streaming"] = hs or None
     if cpu is not None:
         out["cpu_baseline"] = cpu
