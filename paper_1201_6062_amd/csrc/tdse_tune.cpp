@@ -194,7 +194,12 @@ extern "C" tdse_status tdse_tune(int32_t lmax, int32_t n, int32_t batch, const c
     if (e == hipSuccess) e = hipMemcpy(dc0, c0.data(), c0.size() * 8, hipMemcpyHostToDevice);
     tdse_status st = e == hipSuccess ? TDSE_OK : hip_fail(e, "tuner buffers");
 
-    std::vector<TileChoice> cands;
+    // The library's own choice (all zeros) is timed first; a candidate
+    // replaces it only when at least TUNE_MARGIN faster, so run-to-run noise
+    // does not move a shape off its default (the tuner times a lone plan,
+    // and a near tie there can go either way inside an uneven group).
+    constexpr double TUNE_MARGIN = 0.03;
+    std::vector<TileChoice> cands{{0, 0, 0, 0, 0}};
     if (batch == 1) {
         // tile counts T0 .. T0 + 3, at most 8 where T0 allows it (plans of
         // more than 8 tiles per block dimension cannot join an uneven group)
@@ -213,13 +218,17 @@ extern "C" tdse_status tdse_tune(int32_t lmax, int32_t n, int32_t batch, const c
         if (2 * batch <= 64) cands.push_back({0, 32, 64, 16, 8});
     }
     CacheEntry best{{0, 0, 0, 0, 0}, 1e300};
-    for (const TileChoice &tc : cands) {
+    double default_us = 1e300;
+    for (size_t c = 0; c < cands.size(); ++c) {
+        const TileChoice &tc = cands[c];
         if (st != TDSE_OK) break;
         double us = 0.0;
         tdse_status r = time_choice(lmax, n, batch, tc, den, ddip, dfield, dc0, dcT, nsteps, s, &us);
+        if (r == TDSE_OK && c == 0) default_us = us;
         if (r == TDSE_OK && us < best.us) best = {tc, us};
         if (r == TDSE_E_HIP) st = r;
     }
+    if (default_us < 1e300 && best.us > (1.0 - TUNE_MARGIN) * default_us) best = {cands[0], default_us};
     (void)hipFree(den);
     (void)hipFree(ddip);
     (void)hipFree(dfield);

@@ -1,6 +1,7 @@
 """The tile autotuner (tdse_tune): it times the candidate tile shapes of a
 problem on the device, records the fastest in a JSON cache keyed by shape and
-GPU architecture, and plans created with $TDSE_TUNE_CACHE pointing at that
+GPU architecture (the library's own choice unless another shape is at least
+3% faster), and plans created with $TDSE_TUNE_CACHE pointing at that
 cache use the recorded shape. The tuned plans must still match the oracle
 (relative L2 of c(T) <= 1e-10)."""
 import json
@@ -37,11 +38,14 @@ def test_tune_writes_cache_and_plans_use_it(lmax, n, batch, tmp_path, monkeypatc
     entry = data["entries"][f"L{lmax}_N{n}_B{batch}"]
     # the same choice under the shape's bucket (n rounded up to a multiple of 64)
     assert data["entries"][f"L{lmax}_N{(n + 63) // 64 * 64}b_B{batch}"] == entry
+    # all zeros: the library's own choice, kept unless a candidate beats it by 3%
     if batch == 1:
         t0 = (n + 127) // 128
-        assert t0 <= entry["T"] <= min(t0 + 3, 8) and entry["tm"] == 0
+        assert entry["T"] == 0 or t0 <= entry["T"] <= min(t0 + 3, 8)
+        assert entry["tm"] == 0
     else:
-        assert (entry["tm"], entry["tn"], entry["kc"], entry["ks"]) in SHAPES_BATCHED and entry["T"] == 0
+        shape = (entry["tm"], entry["tn"], entry["kc"], entry["ks"])
+        assert (shape == (0, 0, 0, 0) or shape in SHAPES_BATCHED) and entry["T"] == 0
     assert entry["us_per_step"] > 0
     # a second shape is added to the same cache, the first one kept
     tune(1, 40, 2, str(cache))
