@@ -114,6 +114,7 @@ static hipError_t enqueue_steps(tdse_plan p, const VecBuffers &vb, tdse_method m
             if (p->lmax == 0) {
                 e = vec_launch_combine(vb, L, s);
             } else if (p->split) {
+                L.np = patch_np(p->T);  // partials of the preceding patch products launch (zeros at the start)
                 e = vec_launch_combine(vb, L, s);
                 if (e == hipSuccess) e = vec_launch_products(vb, L, s);
             } else {
@@ -209,6 +210,7 @@ tdse_status tdse::vec_propagate_on(tdse_plan p, const VecBuffers &vb, bool use_g
     L.parity = parity;
     L.slots = m == TDSE_RK4 ? 3 : 1;
     L.finish = 1;
+    L.np = p->split && p->lmax > 0 ? patch_np(p->T) : 0;
     L.out = cT;
     TDSE_HIP(vec_launch_combine(vb, L, s));
     return TDSE_OK;
@@ -498,6 +500,7 @@ static hipError_t lz_product(tdse_plan p, const double *field, int64_t nsteps, i
     H.parity = 0;
     H.slots = 1;
     H.off = (int32_t)(k - base);
+    H.np = p->lmax > 0 && products ? patch_np(p->T) : 0;  // patch products, or one partial per tile
     H.out = y;
     return nz ? vec_launch_hmul_dot(vb, H, dotp, *nz, s) : vec_launch_combine(vb, H, s);
 }
@@ -981,7 +984,7 @@ tdse_status create_plan(tdse_plan *out, const double *energies, const double *di
         TileChoice tc{0, 0, 0, 0, 0};
         if (force) tc = *force;
         else tune_lookup(lmax, n, 1, &tc);
-        if (tc.T >= p->T && tc.T <= n) p->T = tc.T;
+        if (tc.T >= p->T && tc.T <= (n + 15) / 16) p->T = tc.T;  // segments of whole 16-row units
         // a forced tile count selects the tiled kernels even for small problems
         p->small = tc.T == 0 && small_eligible(lmax, n);
     }
@@ -1321,9 +1324,10 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
         gi.field = fields[order_idx[q]];
         gi.nsteps = nsteps[order_idx[q]];
         g->insts.push_back(gi);
+        const int npd = patch_np(p->T);  // patches per block dimension
         for (int l = 0; l < p->lmax; ++l)
-            for (int i = 0; i < p->T; ++i)
-                for (int j = 0; j < p->T; ++j) g->tiles.push_back({(int32_t)q, (int16_t)l, (int8_t)i, (int8_t)j});
+            for (int i = 0; i < npd; ++i)
+                for (int j = 0; j < npd; ++j) g->tiles.push_back({(int32_t)q, (int16_t)l, (int8_t)i, (int8_t)j});
         for (int mm = 0; mm <= p->lmax; ++mm)
             for (int qq = 0; qq < p->T; ++qq) g->segs.push_back({(int32_t)q, (int16_t)mm, (int16_t)qq});
         prefix.push_back((int64_t)g->tiles.size());
@@ -1432,6 +1436,7 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
         L.parity = 0;
         L.finish = 1;
         L.slots = 3;
+        L.np = patch_np(p->T);  // the group's products rounds are patch launches
         L.out = cT[k];
         TDSE_HIP(vec_launch_combine(p->vb, L, s));
     }

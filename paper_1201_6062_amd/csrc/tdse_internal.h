@@ -37,8 +37,8 @@ tdse_status hip_fail(hipError_t e, const char *what);
 // Uneven group (several batch-1 plans advanced together).
 struct GroupTile {
     int32_t inst;           // instance (index into the GroupInst array)
-    int16_t l;              // block of the tile
-    int8_t i, j;            // row / column segment
+    int16_t l;              // block of the patch
+    int8_t i, j;            // patch row / column within the block (patch_np(T) each way)
 };
 struct GroupSeg {
     int32_t inst;           // instance (index into the GroupInst array)
@@ -66,7 +66,7 @@ struct GroupDesc {
 };
 constexpr int GROUP_CHUNK_ROUNDS = 64;  // rounds per captured graph (16 steps)
 // One RK4 stage-round (desc->base_round + off) of a group: completion over the
-// segment list, then the tile products over the tile list.
+// segment list, then the patch products over the patch list.
 hipError_t group_launch_round(const GroupSeg *segs, int nsegs, const GroupTile *tiles, int ntiles,
                               const GroupInst *insts, const GroupDesc *desc, int32_t off, hipStream_t s);
 hipError_t group_set_desc(GroupDesc *desc, int64_t base_round, double dt, hipStream_t s);

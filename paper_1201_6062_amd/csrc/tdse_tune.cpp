@@ -204,7 +204,7 @@ extern "C" tdse_status tdse_tune(int32_t lmax, int32_t n, int32_t batch, const c
         // tile counts T0 .. T0 + 3, at most 8 where T0 allows it (plans of
         // more than 8 tiles per block dimension cannot join an uneven group)
         const int t0 = (n + VEC_TILE_MAX - 1) / VEC_TILE_MAX, tmax = t0 <= 8 ? 8 : 16;
-        for (int T = t0; T <= t0 + 3 && T <= tmax && T <= n; ++T) cands.push_back({T, 0, 0, 0, 0});
+        for (int T = t0; T <= t0 + 3 && T <= tmax && T <= (n + 15) / 16; ++T) cands.push_back({T, 0, 0, 0, 0});
     } else {
         // the LDS kernels' 11 tile shapes with one K group, the two shapes
         // compiled with two K groups, and for 2B <= 64 the small-batch kernel

@@ -60,12 +60,19 @@ struct CallDesc {
 constexpr int VEC_TILE_MAX = 128;   // max rows/cols of one dipole tile
 constexpr int VEC_THREADS = 512;    // 8 waves per tile workgroup
 
+// Products launches that stream the dipole from HBM take patches of at most
+// PATCH_MAX x PATCH_MAX tiles of one block per workgroup, leaving
+// patch_np(T) row partials per row segment and column partials per column
+// segment (one per patch across), where one workgroup per tile leaves T.
+constexpr int PATCH_MAX = 4;
+__host__ __device__ constexpr int patch_np(int T) { return (T + PATCH_MAX - 1) / PATCH_MAX; }
+
 
 // Buffers of one parity (a launch reads one parity and writes the other).
 struct VecSide {
     double2 *st[3];        // c, acc, u, each [(lmax+1)*n]
-    double2 *rowp;         // [lmax][T][T][VEC_TILE_MAX]
-    double2 *colp;         // [lmax][T(out seg j)][T(contrib i)][VEC_TILE_MAX]
+    double2 *rowp;         // [lmax][T(seg i)][np(contrib)][VEC_TILE_MAX], np <= T
+    double2 *colp;         // [lmax][T(out seg j)][np(contrib)][VEC_TILE_MAX]
 };
 
 // Field order: lmax, n, en, dip and side[0] fill the first 64 bytes, the
@@ -86,6 +93,8 @@ struct VecLaunch {
     int32_t parity;  // launch parity: read st/partials[parity], write [parity^1]
     int32_t finish;  // 1: write c' to the caller's cT (finish launch)
     int32_t slots;   // field samples per step (3 RK4, 1 Taylor)
+    int32_t np;      // completions: partials per segment and direction (0: T, one per tile)
+    int32_t pad_;
     double *out;     // caller cT for the finish launch
 };
 

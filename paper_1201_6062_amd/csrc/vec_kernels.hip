@@ -60,6 +60,10 @@ __device__ __forceinline__ void st_global(double2 *p, double2 v) {
     dv2_t w = {v.x, v.y};
     *(gdv2_t *)(p) = w;
 }
+__device__ __forceinline__ double2 ld_global(const double2 *p) {
+    const dv2_t v = *(const gdv2_t *)(p);
+    return make_double2(v.x, v.y);
+}
 
 // Tile loads that may be skipped (all-padding parts of a tile), as raw buffer
 // loads over the one tile: a skipped load gets an offset past the buffer's
@@ -168,10 +172,12 @@ __device__ __forceinline__ double field_of(const CallDesc *d, const VecLaunch &L
 }
 
 // Sum of the partials of one kind for state entry e of segment (m, q):
-// rows=true: row partials of tiles (m, q, 0..T-1); rows=false: column
-// partials of tiles (m-1, 0..T-1, q), in ascending tile order. The TP >= T
-// loads are unconditional (indices clamped into the buffer) and invalid terms
-// are dropped afterwards, so the loads issue back to back.
+// rows=true: the np row partials of segment (m, q) (tiles (m, q, 0..T-1) when
+// np == T, one per tile; one per patch column of block m for patch
+// products); rows=false: the np column partials of segment (m, q) from block
+// m-1, in ascending order. The TP >= np loads are unconditional (indices
+// clamped into the buffer) and invalid terms are dropped afterwards, so the
+// loads issue back to back.
 template <int TP>
 struct PartialLoads {
     double2 v[TP];
@@ -179,36 +185,36 @@ struct PartialLoads {
 };
 
 template <int TP>
-__device__ __forceinline__ PartialLoads<TP> load_partials(const VecBuffers &b, int T, int par, bool rows, int m,
-                                                          int q, int e) {
+__device__ __forceinline__ PartialLoads<TP> load_partials(const VecBuffers &b, int T, int np, int par, bool rows,
+                                                          int m, int q, int e) {
     PartialLoads<TP> p;
     p.valid = rows ? (m < b.lmax) : (m > 0);
     const int hi = b.lmax > 0 ? b.lmax - 1 : 0;
     int mb = rows ? m : m - 1;
     mb = mb < 0 ? 0 : (mb > hi ? hi : mb);
     double2 *pr = rowp_ptr(b, par), *pc = colp_ptr(b, par);
-    const double2 *base = (rows ? pr : pc) + ((size_t)(mb * T + q) * T) * VEC_TILE_MAX + e;
+    const double2 *base = (rows ? pr : pc) + ((size_t)(mb * T + q) * np) * VEC_TILE_MAX + e;
 #pragma unroll
-    for (int k = 0; k < TP; ++k) p.v[k] = ld2(base + (size_t)(k < T ? k : T - 1) * VEC_TILE_MAX);
+    for (int k = 0; k < TP; ++k) p.v[k] = ld2(base + (size_t)(k < np ? k : np - 1) * VEC_TILE_MAX);
     return p;
 }
 
-// Fixed-order sum of the loaded partials (contributions k = 0 .. T-1).
+// Fixed-order sum of the loaded partials (contributions k = 0 .. np-1).
 template <int TP>
-__device__ __forceinline__ double2 add_partials(const PartialLoads<TP> &p, int T) {
+__device__ __forceinline__ double2 add_partials(const PartialLoads<TP> &p, int np) {
     double zx = 0.0, zy = 0.0;
 #pragma unroll
     for (int k = 0; k < TP; ++k) {
-        zx += k < T ? p.v[k].x : 0.0;
-        zy += k < T ? p.v[k].y : 0.0;
+        zx += k < np ? p.v[k].x : 0.0;
+        zy += k < np ? p.v[k].y : 0.0;
     }
     return p.valid ? make_double2(zx, zy) : make_double2(0.0, 0.0);
 }
 
 template <int TP>
-__device__ __forceinline__ double2 sum_partials(const VecBuffers &b, int T, int par, bool rows, int m,
+__device__ __forceinline__ double2 sum_partials(const VecBuffers &b, int T, int np, int par, bool rows, int m,
                                                 int q, int e) {
-    return add_partials<TP>(load_partials<TP>(b, T, par, rows, m, q, e), T);
+    return add_partials<TP>(load_partials<TP>(b, T, np, par, rows, m, q, e), np);
 }
 
 // Where (if anywhere) a launch's completion writes a checkpoint. Both
@@ -389,7 +395,7 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
     const int m = isB ? l + 1 : l, q = isB ? j : i, len = isB ? RB : RA, s0 = isB ? c0 : r0;
     const int ec = e < len ? e : len - 1;
     const size_t gi = (size_t)m * n + s0 + ec;
-    const PartialLoads<TP> pl = load_partials<TP>(b, T, par, half == 0, m, q, ec);
+    const PartialLoads<TP> pl = load_partials<TP>(b, T, T, par, half == 0, m, q, ec);
     // The state is read by the completing half only.
     double2 c_in = make_double2(0.0, 0.0), acc_in = c_in, u_in = c_in;
     double E0 = 0.0;
@@ -451,49 +457,14 @@ __device__ __forceinline__ void tile_body(const VecBuffers &b, const VecLaunch &
     if (owner) store_state(b, L, ct, gi, c, acc, u);
 }
 
-// One tile workgroup of the split path: the stage inputs were completed by
-// the preceding combine launch (state buffers of parity par ^ 1), so the
-// workgroup only loads its two input segments and its tile.
-__device__ __forceinline__ void products_body(const VecBuffers &b, int par, int T, int l, int i, int j, int r0,
-                                              int RA, int c0, int RB) {
-    __shared__ TileLds lds;
-    const int t = threadIdx.x;
-    const int lane = t & 63, wv = t >> 6;
-    const int tile = (l * T + i) * T + j;
-    const double2 *Dt = reinterpret_cast<const double2 *>(b.dip) +
-                        (size_t)tile * (VEC_TILE_MAX * VEC_TILE_MAX / 2) + wv * 16 * 64 + lane;
-    // input segments first: waiting for them leaves the tile loads in flight,
-    // and the products consume tile rows in load order as they arrive
-    const bool isB = t >= VEC_TILE_MAX;
-    const int e = t & (VEC_TILE_MAX - 1), len = isB ? RB : RA;
-    double2 u = make_double2(0.0, 0.0);
-    if (t < 2 * VEC_TILE_MAX) {
-        const size_t gi = (size_t)(isB ? l + 1 : l) * b.n + (isB ? c0 : r0) + (e < len ? e : len - 1);
-        u = ld2(st_ptr(b, par ^ 1, 2) + gi);
-    }
-    // Parts of the tile that are all padding are not fetched (their stored
-    // values are zeros): the 16-row groups at or past RA (load pairs 2k, 2k+1
-    // hold rows qq + 16k) and each lane's column pairs at or past RB. With
-    // segments well short of 128 (small N, or N just past a multiple of 128)
-    // this saves up to a quarter of the tile stream.
-    const int cb = wv * 16 + 4 * (lane >> 4);
-    double2 dv[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const bool need = 16 * (r >> 1) < RA && cb + 2 * (r & 1) < RB;
-        dv[r] = need ? Dt[r * 64] : make_double2(0.0, 0.0);
-    }
-    if (t < 2 * VEC_TILE_MAX) (isB ? lds.uB : lds.uA)[e] = e < len ? u : make_double2(0.0, 0.0);
-    lds_barrier();
-    tile_products(b, lds, dv, T, l, i, j, RA, RB, par ^ 1);
-}
-
-// Start and length of segment q of n split over T (Sec. 4.1), without a
-// dependent load: T is a compile-time constant where TP == T.
+// Start and length of segment q of n split over T (seg_start / seg_len: the
+// Sec. 4.1 split over 16-row units), without a dependent load: T is a
+// compile-time constant where TP == T.
 __device__ __forceinline__ void segment_of(int n, int T, int q, int *start, int *len) {
-    const int div = n / T, rem = n - div * T;
-    *start = q * div + (q < rem ? q : rem);
-    *len = div + (q < rem ? 1 : 0);
+    const int U = (n + 15) >> 4, div = U / T, rem = U - div * T;
+    const int s = q * div + (q < rem ? q : rem), end = 16 * (s + div + (q < rem ? 1 : 0));
+    *start = 16 * s;
+    *len = (end < n ? end : n) - 16 * s;
 }
 
 // G: compile-time gauge (0 length, 1 velocity) of the fused kernel.
@@ -516,19 +487,287 @@ __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
     tile_body<TP, G>(b, L0, T, l, i, j, r0, RA, c0, RB);
 }
 
-// Products-only launch of the split path (after a vec_combine launch).
-template <int TP>
-__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_products_kernel(VecBuffers b, VecLaunch L) {
-    const int T = TP <= 8 ? TP : b.T;
-    const int ntiles = b.lmax * T * T;
-    const int w = blockIdx.x;
-    const int xcd = w & 7, per = ntiles >> 3, extra = ntiles & 7;
-    const int tile = xcd * per + (xcd < extra ? xcd : extra) + (w >> 3);
-    const int l = tile / (T * T), rem = tile - l * T * T, i = rem / T, j = rem - i * T;
-    int r0, RA, c0, RB;
-    segment_of(b.n, T, i, &r0, &RA);
-    segment_of(b.n, T, j, &c0, &RB);
-    products_body(b, L.parity, T, l, i, j, r0, RA, c0, RB);
+// ---------------------------------------------------------------------------
+// Patch products: the products launch of the split path and of uneven
+// groups, where the dipole streams from HBM. A workgroup takes a patch of
+// PI x PJ tiles (at most PATCH_MAX each way; the Sec. 4.1 split of a block's
+// T tile rows and columns over patch_np(T) patches each way) of one block
+// D_l: tile rows ti0 .. ti0+PI-1, tile columns tj0 .. tj0+PJ-1. Each wave
+// streams its 16 KB slice of every tile of the patch (wave w: columns 16w ..
+// 16w+15, the tile_pos order of the fused kernel) straight into LDS with
+// buffer loads that carry the LDS bit: PATCH_LOOK loads of 1 KB in flight
+// per wave through a ring of PATCH_RING slots, so no registers are tied up by
+// data in flight and the stream runs on across tile boundaries. Parts of a
+// tile that are all padding are not fetched (out-of-range offsets).
+//   Row partials (towards z_l) accumulate over the patch's PJ tiles of a
+//   tile row in registers and are summed over the 8 waves in LDS once per
+//   tile row; column partials (towards z_{l+1}) accumulate over the patch's
+//   PI tile rows in registers and are summed over the 16 row classes of a
+//   wave by lane shuffles once per patch.
+// A patch leaves one row partial per row segment and one column partial per
+// column segment, so a segment collects patch_np(T) of each (T when every
+// tile is a workgroup of its own), and the workgroup turns over once per
+// patch rather than once per tile. The LDS (152 KB) admits one workgroup
+// per CU: 8 waves, 64 KB in flight per CU.
+constexpr int PATCH_RING = 16;  // 1 KB slots per wave: one tile slice, so load r of a tile uses slot r
+constexpr int PATCH_LOOK = 8;   // loads in flight per wave
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+struct PatchLds {
+    char ring[VEC_THREADS / 64][PATCH_RING][1024];  // [wave][slot]
+    double2 uA[PATCH_MAX][VEC_TILE_MAX];            // inputs of the row segments (l, ti0 + ii)
+    double2 rbuf[VEC_THREADS / 64][VEC_TILE_MAX];   // [wave][row]: one tile row's row sums
+};
+
+// What a patch workgroup reads and writes, copied into scalar registers at
+// kernel entry (a group's instance buffers live in device memory, and every
+// explicit wait below is a compiler memory barrier that would otherwise have
+// them re-read, each re-read waiting for the whole stream).
+struct PatchArgs {
+    const double *dip;     // tiles of the plan
+    const double2 *u;      // product inputs: the stage inputs completed by the preceding combine launch
+    double2 *rowp, *colp;  // partials written (np per segment and direction)
+    int n, T;
+};
+
+__device__ __forceinline__ PatchArgs patch_args(const VecBuffers &b, int par) {
+    PatchArgs a{b.dip, st_ptr(b, par ^ 1, 2), rowp_ptr(b, par ^ 1), colp_ptr(b, par ^ 1), b.n, b.T};
+    pin_sgpr(a.dip);
+    pin_sgpr(a.u);
+    pin_sgpr(a.rowp);
+    pin_sgpr(a.colp);
+    pin_sgpr(a.n);
+    pin_sgpr(a.T);
+    return a;
+}
+
+// Stream state of one tile of a patch: a buffer descriptor over the tile (no
+// records past the patch's last tile, so loads beyond it fetch nothing) and
+// the tile's valid rows and columns.
+struct PatchTile {
+    __amdgpu_buffer_rsrc_t rs;
+    int ra, rb;
+};
+
+__device__ __forceinline__ PatchTile patch_tile(const PatchArgs &A, int l, int ti0, int tj0, int PI, int ii, int jj) {
+    const int T = A.T;
+    const bool live = ii < PI;
+    const int i = ti0 + (live ? ii : 0), j = tj0 + jj;
+    int r0, ra, c0, rb;
+    segment_of(A.n, T, i, &r0, &ra);
+    segment_of(A.n, T, j, &c0, &rb);
+    PatchTile pt;
+    pt.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(A.dip) + (size_t)((l * T + i) * T + j) * (TILE_BYTES / 8),
+                                              0, live ? TILE_BYTES : 0, 0x00020000);
+    pt.ra = live ? ra : 0;
+    pt.rb = live ? rb : 0;
+    return pt;
+}
+
+// Load r of this wave's slice of a tile into ring slot r: lane (h, q) of wave
+// w fetches the double2 at 64 (16 w + r) + 16 h + q, i.e. rows q + 16 (r/2),
+// columns 16 w + 4 h + 2 (r % 2) + {0, 1}; row groups at or past ra and
+// column pairs at or past rb are not fetched.
+__device__ __forceinline__ void patch_issue(const PatchTile &pt, int r, char *ring, int lane_off, int cb) {
+    const bool need = 16 * (r >> 1) < pt.ra && cb + 2 * (r & 1) < pt.rb;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(pt.rs, (lds_void_t *)(ring + r * 1024), 16,
+                                             need ? lane_off + r * 1024 : TILE_SKIP, 0, 0, 0);
+}
+
+// Workgroup barrier for LDS written with ds instructions only: the ring's
+// loads stay in flight (a barrier with a memory fence would wait for them).
+__device__ __forceinline__ void patch_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// LDS accesses of the patch kernel, through byte pointers: the compiler then
+// does not tie them to the ring's in-flight loads (it would wait for every
+// one of them before any access to the workgroup's LDS). The ring is read
+// only after an explicit wait for the loads that fill it; the other arrays
+// are written with ds instructions only.
+__device__ __forceinline__ double2 lds_ld2(const char *p) {
+    const dv2_t v = *reinterpret_cast<const dv2_t *>(p);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void lds_st2(char *p, double2 v) { *reinterpret_cast<dv2_t *>(p) = dv2_t{v.x, v.y}; }
+
+// Patch (pr, pc) of block l: reads the inputs A.u, writes the partials in
+// the np-per-segment layout.
+__device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, int pr, int pc) {
+    __shared__ PatchLds lds;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int h = lane >> 4, qq = lane & 15, cb = wv * 16 + 4 * h;
+    const int T = A.T;
+    const int ti0 = (int)split_start(T, np, pr), PI = (int)split_len(T, np, pr);
+    const int tj0 = (int)split_start(T, np, pc), PJ = (int)split_len(T, np, pc);
+    const int n = A.n;
+    const double2 *u = A.u;
+    double2 *rowp_out = A.rowp, *colp_out = A.colp;
+    char *ring = lds.ring[wv][0];
+    char *rbuf = reinterpret_cast<char *>(&lds.rbuf[0][0]), *uab = reinterpret_cast<char *>(&lds.uA[0][0]);
+    const int lane_off = wv * 16 * 1024 + lane * 16;
+
+    // ---- inputs: the column-side entries this lane multiplies (columns
+    // cb .. cb+3 of each tile column) into registers, the row-side segments
+    // into LDS; zero past each segment.
+    double2 ub[PATCH_MAX][4];
+#pragma unroll
+    for (int jj = 0; jj < PATCH_MAX; ++jj) {
+        int c0, rb;
+        segment_of(n, T, tj0 + (jj < PJ ? jj : 0), &c0, &rb);
+        const size_t g = (size_t)(l + 1) * n + c0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const bool ok = jj < PJ && cb + c < rb;
+            const double2 v = ld_global(u + g + (ok ? cb + c : 0));
+            ub[jj][c] = ok ? v : make_double2(0.0, 0.0);
+        }
+    }
+    double2 ua_in;
+    {
+        const int ii = t >> 7, e = t & (VEC_TILE_MAX - 1);
+        int r0, ra;
+        segment_of(n, T, ti0 + (ii < PI ? ii : 0), &r0, &ra);
+        const bool ok = ii < PI && e < ra;
+        const double2 v = ld_global(u + (size_t)l * n + r0 + (ok ? e : 0));
+        ua_in = ok ? v : make_double2(0.0, 0.0);
+    }
+    // The ring starts zeroed: slots a skipped load leaves alone then hold
+    // zeros or an earlier tile's (finite) values, which only meet zero inputs
+    // or feed partials that are not stored.
+#pragma unroll
+    for (int r = 0; r < PATCH_RING; ++r) *reinterpret_cast<dv2_t *>(ring + r * 1024 + lane * 16) = dv2_t{0.0, 0.0};
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+
+    // ---- the stream: loads 0 .. PATCH_LOOK-1 of the first tile
+    PatchTile cur = patch_tile(A, l, ti0, tj0, PI, 0, 0);
+#pragma unroll
+    for (int r = 0; r < PATCH_LOOK; ++r) patch_issue(cur, r, ring, lane_off, cb);
+    lds_st2(uab + t * 16, ua_in);  // uA[t / 128][t % 128]
+    patch_barrier();
+    // the data of loads 0 and 1 (each step below reads the next pair ahead)
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(PATCH_LOOK - 2) : "memory");
+    double2 d0 = lds_ld2(ring + lane * 16), d1 = lds_ld2(ring + 1024 + lane * 16);
+
+    double2 col[PATCH_MAX][4];
+#pragma unroll
+    for (int jj = 0; jj < PATCH_MAX; ++jj)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) col[jj][c] = make_double2(0.0, 0.0);
+    const int rcls = 2 * (h & 1) + 4 * (h >> 1);
+
+    for (int ii = 0; ii < PI; ++ii) {
+        double2 ua[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) ua[k] = lds_ld2(uab + (ii * VEC_TILE_MAX + qq + 16 * k) * 16);
+        double tr[8], ti[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) tr[k] = ti[k] = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < PATCH_MAX; ++jj) {
+            if (jj < PJ) {
+                const bool row_end = jj + 1 >= PJ;
+                const PatchTile nxt = patch_tile(A, l, ti0, tj0, PI, row_end ? ii + 1 : ii, row_end ? 0 : jj + 1);
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) {
+                    // keep PATCH_LOOK loads ahead: this tile's loads 8..15, then the next tile's 0..7
+                    if (kk < 4) {
+                        patch_issue(cur, 2 * kk + 8, ring, lane_off, cb);
+                        patch_issue(cur, 2 * kk + 9, ring, lane_off, cb);
+                    } else {
+                        patch_issue(nxt, 2 * kk - 8, ring, lane_off, cb);
+                        patch_issue(nxt, 2 * kk - 7, ring, lane_off, cb);
+                    }
+                    // the pair after this one has landed: read it ahead
+                    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(PATCH_LOOK - 2) : "memory");
+                    const int rn = (2 * kk + 2) & (PATCH_RING - 1);
+                    const double2 n0 = lds_ld2(ring + rn * 1024 + lane * 16);
+                    const double2 n1 = lds_ld2(ring + (rn + 1) * 1024 + lane * 16);
+                    // d0 = D[row qq+16kk][cb, cb+1], d1 = D[row qq+16kk][cb+2, cb+3]
+                    tr[kk] = fma(d1.y, ub[jj][3].x, fma(d1.x, ub[jj][2].x, fma(d0.y, ub[jj][1].x, fma(d0.x, ub[jj][0].x, tr[kk]))));
+                    ti[kk] = fma(d1.y, ub[jj][3].y, fma(d1.x, ub[jj][2].y, fma(d0.y, ub[jj][1].y, fma(d0.x, ub[jj][0].y, ti[kk]))));
+                    const double2 a = ua[kk];
+                    col[jj][0].x = fma(d0.x, a.x, col[jj][0].x);
+                    col[jj][0].y = fma(d0.x, a.y, col[jj][0].y);
+                    col[jj][1].x = fma(d0.y, a.x, col[jj][1].x);
+                    col[jj][1].y = fma(d0.y, a.y, col[jj][1].y);
+                    col[jj][2].x = fma(d1.x, a.x, col[jj][2].x);
+                    col[jj][2].y = fma(d1.x, a.y, col[jj][2].y);
+                    col[jj][3].x = fma(d1.y, a.x, col[jj][3].x);
+                    col[jj][3].y = fma(d1.y, a.y, col[jj][3].y);
+                    d0 = n0;
+                    d1 = n1;
+                }
+                cur = nxt;
+            }
+        }
+        // ---- row partials of tile row ii: over the wave's column groups
+        // (lane bits 5, 4), then over the 8 waves in a fixed order
+        double sr[4], si[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sr[k] = swap_reduce<5>(tr[k], tr[k + 4]);
+            si[k] = swap_reduce<5>(ti[k], ti[k + 4]);
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const double zr = swap_reduce<4>(sr[k], sr[k + 2]), zi = swap_reduce<4>(si[k], si[k + 2]);
+            lds_st2(rbuf + (wv * VEC_TILE_MAX + qq + 16 * (k + rcls)) * 16, make_double2(zr, zi));
+        }
+        patch_barrier();
+        if (t < VEC_TILE_MAX) {
+            int r0, ra;
+            segment_of(n, T, ti0 + ii, &r0, &ra);
+            if (t < ra) {
+                double2 z = lds_ld2(rbuf + t * 16);
+#pragma unroll
+                for (int w = 1; w < VEC_THREADS / 64; ++w) z = cadd(z, lds_ld2(rbuf + (w * VEC_TILE_MAX + t) * 16));
+                st_global(rowp_out + ((size_t)(l * T + ti0 + ii) * np + pc) * VEC_TILE_MAX + t, z);
+            }
+        }
+        patch_barrier();
+    }
+    // the stream's last loads (past the patch: no fetch) before the workgroup ends
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+
+    // ---- column partials: sum over the 16 row classes (lane bits 3..0),
+    // halving the values each step; lane (h, q) ends with tile column
+    // jj = q / 4, column cb + q % 4
+    double v[8 * PATCH_MAX];
+#pragma unroll
+    for (int jj = 0; jj < PATCH_MAX; ++jj)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            v[(jj * 4 + c) * 2] = col[jj][c].x;
+            v[(jj * 4 + c) * 2 + 1] = col[jj][c].y;
+        }
+#pragma unroll
+    for (int bit = 3; bit >= 0; --bit) {
+        const int half = 2 << bit;
+        const bool hi = (lane >> bit) & 1;
+#pragma unroll
+        for (int x = 0; x < half; ++x) {
+            const double send = hi ? v[x] : v[x + half];
+            const double keep = hi ? v[x + half] : v[x];
+            v[x] = keep + __shfl_xor(send, 1 << bit);
+        }
+    }
+    {
+        const int jj = qq >> 2, cc = cb + (qq & 3);
+        int c0, rb;
+        segment_of(n, T, tj0 + (jj < PJ ? jj : 0), &c0, &rb);
+        if (jj < PJ && cc < rb)
+            st_global(colp_out + ((size_t)(l * T + tj0 + jj) * np + pr) * VEC_TILE_MAX + cc, make_double2(v[0], v[1]));
+    }
+}
+
+// Products launch of the split path (after a vec_combine launch): one
+// workgroup per patch, patch_np(T)^2 patches per block.
+__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void vec_patch_kernel(VecBuffers b, VecLaunch L) {
+    const int np = patch_np(b.T);
+    const int w = blockIdx.x, per = np * np;
+    const int l = w / per, rem = w - l * per;
+    patch_body(patch_args(b, L.parity), np, l, rem / np, rem - (rem / np) * np);
 }
 
 // Products launch of the next Krylov vector with the recurrence's update
@@ -643,7 +882,7 @@ __device__ __forceinline__ void lz_tile_body(const VecBuffers &b, const LzFused 
     const size_t gi = (size_t)m * n + s0 + ec;
     const int k = z.k;
     // prologue (the partials exist for k = 0 too; their values are unused then)
-    const PartialLoads<TP> pl = load_partials<TP>(b, T, 0, half == 0, m, q, ec);
+    const PartialLoads<TP> pl = load_partials<TP>(b, T, T, 0, half == 0, m, q, ec);
     double2 xp = make_double2(0.0, 0.0), xp2 = xp;
     double E0 = 0.0;
     if (half == 0) {
@@ -778,8 +1017,9 @@ __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
 
 // Uneven group: every RK4 stage-round of the active instances is one
 // combine launch over their segments (work list of (instance, m, q)) and one
-// products launch over their tiles (work list of (instance, l, i, j)); each
-// instance brings its own buffers, tile count and field samples.
+// patch products launch over their blocks' patches (work list of (instance,
+// l, patch row, patch column)); each instance brings its own buffers, tile
+// count and field samples.
 // RK4 launch schedule: round 4k+s completes stage s of step k (stage 4 of
 // step k-1 for s == 0) and forms the input of the next stage.
 __device__ __forceinline__ VecLaunch group_round_launch(int64_t round) {
@@ -806,28 +1046,30 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_group_combine_kernel(const G
     const VecBuffers &b = gi.b;  // read in place: a local copy would be indexed through scratch
     const VecLaunch L = group_round_launch(round);
     const int e = threadIdx.x;
-    const int len = (int)split_len(b.n, b.T, gs.q);
+    const int len = (int)seg_len(b.n, b.T, gs.q);
     if (e >= len) return;
     const int64_t step = (round >> 2) + L.comp.step_delta;
     const double F = (step >= 0 && step < gi.nsteps) ? gi.field[step * 3 + L.comp.slot] : 0.0;
-    const size_t g = (size_t)gs.m * b.n + split_start(b.n, b.T, gs.q) + e;
+    const size_t g = (size_t)gs.m * b.n + seg_start(b.n, b.T, gs.q) + e;
     const int par = L.parity;
-    const double2 z = couple(b.gauge, sum_partials<8>(b, b.T, par, true, gs.m, gs.q, e),
-                             sum_partials<8>(b, b.T, par, false, gs.m, gs.q, e));
+    // partials of the patch products launch (group plans have T <= 8: at most two per segment)
+    const int np = patch_np(b.T);
+    const double2 z = couple(b.gauge, sum_partials<2>(b, b.T, np, par, true, gs.m, gs.q, e),
+                             sum_partials<2>(b, b.T, np, par, false, gs.m, gs.q, e));
     double2 c = ld2(st_ptr(b, par, 0) + g), acc = ld2(st_ptr(b, par, 1) + g), u = ld2(st_ptr(b, par, 2) + g);
     apply_completion(L.comp, desc->dt, F, b.en[g], z, c, acc, u);
     store_state(b, L, CkptTarget{nullptr}, g, c, acc, u);
 }
 
-__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_group_products_kernel(const GroupTile *tiles, const GroupInst *insts, const GroupDesc *desc, int32_t off) {
+// Products round of a group: one workgroup per patch (GroupTile i, j: the
+// patch's row and column within its block).
+__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void vec_group_patch_kernel(const GroupTile *tiles, const GroupInst *insts, const GroupDesc *desc, int32_t off) {
     const GroupTile gt = tiles[blockIdx.x];
     const GroupInst &gi = insts[gt.inst];
     const int64_t round = desc->base_round + off;
     if (round >= 4 * gi.nsteps) return;
-    const VecBuffers &b = gi.b;
-    const int r0 = (int)split_start(b.n, b.T, gt.i), RA = (int)split_len(b.n, b.T, gt.i);
-    const int c0 = (int)split_start(b.n, b.T, gt.j), RB = (int)split_len(b.n, b.T, gt.j);
-    products_body(b, (int)(round & 1), b.T, gt.l, gt.i, gt.j, r0, RA, c0, RB);
+    const PatchArgs A = patch_args(gi.b, (int)(round & 1));
+    patch_body(A, patch_np(A.T), gt.l, gt.i, gt.j);
 }
 
 __global__ void group_desc_kernel(GroupDesc *desc, int64_t base_round, double dt) {
@@ -835,15 +1077,16 @@ __global__ void group_desc_kernel(GroupDesc *desc, int64_t base_round, double dt
     desc->dt = dt;
 }
 
-// Completion only (no products): the final completion of a propagation,
-// every launch when lmax == 0 (no dipole blocks, z == 0), and the single
-// product of tdse_hmul (kind CK_HMUL: y = E o u + F z).
+// Completion only (no products): the completion launch of the split path,
+// the final completion of a propagation, every launch when lmax == 0 (no
+// dipole blocks, z == 0), and the single product of tdse_hmul (kind CK_HMUL:
+// y = E o u + F z). TP bounds the partials per segment, np = L.np (or T).
 template <int TP>
 __global__ __launch_bounds__(VEC_TILE_MAX) void vec_combine_kernel(VecBuffers b, VecLaunch L) {
-    const int T = TP <= 8 ? TP : b.T;
+    const int T = b.T, np = L.np > 0 ? L.np : T;
     const int seg = blockIdx.x;
     const int m = seg / T, q = seg - m * T;
-    const int s0 = (int)split_start(b.n, T, q), len = (int)split_len(b.n, T, q);
+    const int s0 = (int)seg_start(b.n, T, q), len = (int)seg_len(b.n, T, q);
     const int e = threadIdx.x;
     if (e >= len) return;
     const CallDesc *d = b.desc;
@@ -852,7 +1095,8 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_combine_kernel(VecBuffers b,
     const size_t gi = (size_t)m * b.n + s0 + e;
     double2 z = make_double2(0.0, 0.0);
     if (b.lmax > 0)
-        z = couple(b.gauge, sum_partials<TP>(b, T, par, true, m, q, e), sum_partials<TP>(b, T, par, false, m, q, e));
+        z = couple(b.gauge, sum_partials<TP>(b, T, np, par, true, m, q, e),
+                   sum_partials<TP>(b, T, np, par, false, m, q, e));
     double2 c = ld2(st_ptr(b, par, 0) + gi), acc = ld2(st_ptr(b, par, 1) + gi), u = ld2(st_ptr(b, par, 2) + gi);
     const double E0 = b.en[gi];
     if (L.comp.kind == CK_HMUL) {
@@ -878,10 +1122,10 @@ template <int TP, bool HASD>
 __device__ __forceinline__ void hmul_dot_body(const VecBuffers &b, const VecLaunch &L, double *dotp,
                                               const LzNorm &nz) {
     __shared__ double red[VEC_TILE_MAX / 64];
-    const int T = TP <= 8 ? TP : b.T;
+    const int T = b.T, np = L.np > 0 ? L.np : T;
     const int seg = blockIdx.x;
     const int m = seg / T, q = seg - m * T;
-    const int s0 = (int)split_start(b.n, T, q), len = (int)split_len(b.n, T, q);
+    const int s0 = (int)seg_start(b.n, T, q), len = (int)seg_len(b.n, T, q);
     const int e = threadIdx.x;
     const int par = L.parity;
     const double F = field_of(b.desc, L);
@@ -898,16 +1142,16 @@ __device__ __forceinline__ void hmul_dot_body(const VecBuffers &b, const VecLaun
     // norm part, then the partials
     const double2 x = ld2(up);
     const double E0 = b.en[gi];
-    const int np = nz.nparts;
-    const double n0 = nz.normp[e < np ? e : np - 1];
+    const int nparts = nz.nparts;
+    const double n0 = nz.normp[e < nparts ? e : nparts - 1];
     PartialLoads<TP> pr, pc;
     if constexpr (HASD) {
-        pr = load_partials<TP>(b, T, par, true, m, q, ee);
-        pc = load_partials<TP>(b, T, par, false, m, q, ee);
+        pr = load_partials<TP>(b, T, np, par, true, m, q, ee);
+        pc = load_partials<TP>(b, T, np, par, false, m, q, ee);
     }
-    double nsum = e < np ? n0 : 0.0;
-    if (np > VEC_TILE_MAX)  // (a loop here would wait for every load above)
-        for (int k = e + VEC_TILE_MAX; k < np; k += VEC_TILE_MAX) nsum += nz.normp[k];
+    double nsum = e < nparts ? n0 : 0.0;
+    if (nparts > VEC_TILE_MAX)  // (a loop here would wait for every load above)
+        for (int k = e + VEC_TILE_MAX; k < nparts; k += VEC_TILE_MAX) nsum += nz.normp[k];
     double bj = sqrt(block_sum<VEC_TILE_MAX>(nsum, red));
     const double bprev = nz.j > 1 ? bprev_ld : 0.0;
     if (nz.j > 0 && bj <= 1e-13 * (fabs(aprev_ld) + bprev)) bj = 0.0;
@@ -917,7 +1161,7 @@ __device__ __forceinline__ void hmul_dot_body(const VecBuffers &b, const VecLaun
         else nz.beta[nz.j - 1] = bj;
     }
     double2 z = make_double2(0.0, 0.0);
-    if constexpr (HASD) z = couple(b.gauge, add_partials<TP>(pr, T), add_partials<TP>(pc, T));
+    if constexpr (HASD) z = couple(b.gauge, add_partials<TP>(pr, np), add_partials<TP>(pc, np));
     double dot = 0.0;
     if (live) {
         const double2 v = make_double2(x.x * inv, x.y * inv);
@@ -971,10 +1215,10 @@ __global__ void vec_layout_kernel(const double *src, double *dst, int lmax, int 
         int a, bcol;
         tile_elem((int64_t)w, &a, &bcol);
         const int l = (int)(tile / (T * T)), rem = (int)(tile % (T * T)), i = rem / T, j = rem % T;
-        const int RA = (int)split_len(n, T, i), RB = (int)split_len(n, T, j);
+        const int RA = (int)seg_len(n, T, i), RB = (int)seg_len(n, T, j);
         double v = 0.0;
         if (a < RA && bcol < RB) {
-            const int r = (int)split_start(n, T, i) + a, c = (int)split_start(n, T, j) + bcol;
+            const int r = (int)seg_start(n, T, i) + a, c = (int)seg_start(n, T, j) + bcol;
             v = src[((size_t)l * n + r) * n + c];
         }
         dst[g] = v;
@@ -990,9 +1234,9 @@ __global__ void vec_untile_kernel(const double *tiles, double *dst, int lmax, in
         const size_t rg = g / n;
         const int r = (int)(rg % n), l = (int)(rg / n);
         int i = 0, j = 0;
-        while (i + 1 < T && split_start(n, T, i + 1) <= r) ++i;
-        while (j + 1 < T && split_start(n, T, j + 1) <= c) ++j;
-        const int a = r - (int)split_start(n, T, i), bcol = c - (int)split_start(n, T, j);
+        while (i + 1 < T && seg_start(n, T, i + 1) <= r) ++i;
+        while (j + 1 < T && seg_start(n, T, j + 1) <= c) ++j;
+        const int a = r - (int)seg_start(n, T, i), bcol = c - (int)seg_start(n, T, j);
         dst[g] = tiles[(((size_t)l * T + i) * T + j) * VEC_TILE_MAX * VEC_TILE_MAX + tile_pos(a, bcol)];
     }
 }
@@ -1099,7 +1343,9 @@ hipError_t vec_launch_tiles(const VecBuffers &b, const VecLaunch &l, hipStream_t
     return hipGetLastError();
 }
 hipError_t vec_launch_combine(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {
-    TDSE_TP_DISPATCH(b.T, vec_combine_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s, b, l);
+    if (l.np > b.T) return hipErrorInvalidValue;
+    TDSE_TP_DISPATCH(l.np > 0 ? l.np : b.T, vec_combine_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s, b,
+                     l);
     return hipGetLastError();
 }
 hipError_t vec_launch_lz_products(const VecBuffers &b, const LzUpdate &z, hipStream_t s) {
@@ -1133,12 +1379,15 @@ hipError_t vec_launch_lz_fused(const VecBuffers &b, const LzFused &z, hipStream_
 }
 hipError_t vec_launch_hmul_dot(const VecBuffers &b, const VecLaunch &l, double *dotp, const LzNorm &nz,
                                hipStream_t s) {
-    TDSE_TP_DISPATCH(b.T, vec_hmul_dot_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s, b, l, dotp, nz);
+    if (l.np > b.T) return hipErrorInvalidValue;
+    TDSE_TP_DISPATCH(l.np > 0 ? l.np : b.T, vec_hmul_dot_kernel, dim3((b.lmax + 1) * b.T), dim3(VEC_TILE_MAX), 0, s,
+                     b, l, dotp, nz);
     return hipGetLastError();
 }
 hipError_t vec_launch_products(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {
-    const int ntiles = b.lmax * b.T * b.T;
-    TDSE_TP_DISPATCH(b.T, vec_products_kernel, dim3(ntiles), dim3(VEC_THREADS), 0, s, b, l);
+    const int np = patch_np(b.T);
+    if (b.lmax == 0 || b.T > 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(vec_patch_kernel, dim3(b.lmax * np * np), dim3(VEC_THREADS), 0, s, b, l);
     return hipGetLastError();
 }
 hipError_t group_launch_round(const GroupSeg *segs, int nsegs, const GroupTile *tiles, int ntiles,
@@ -1146,7 +1395,7 @@ hipError_t group_launch_round(const GroupSeg *segs, int nsegs, const GroupTile *
     hipLaunchKernelGGL(vec_group_combine_kernel, dim3(nsegs), dim3(VEC_TILE_MAX), 0, s, segs, insts, desc, off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(vec_group_products_kernel, dim3(ntiles), dim3(VEC_THREADS), 0, s, tiles, insts, desc, off);
+    hipLaunchKernelGGL(vec_group_patch_kernel, dim3(ntiles), dim3(VEC_THREADS), 0, s, tiles, insts, desc, off);
     return hipGetLastError();
 }
 hipError_t group_set_desc(GroupDesc *desc, int64_t base_round, double dt, hipStream_t s) {

@@ -31,6 +31,28 @@ int main() {
             CHECK(pos == w);
             CHECK(mx - mn <= 1);
         }
+    // Dipole segments: the split over 16-row units tiles [0, n) in order;
+    // every segment but the last is whole units, none is empty, and none
+    // exceeds 128 rows when T >= ceil(n / 128).
+    for (int n = 1; n < 1200; n += (n < 300 ? 1 : 7))
+        for (int T = 1; T <= (n + 15) / 16 && T <= 24; ++T) {
+            int64_t pos = 0;
+            for (int q = 0; q < T; ++q) {
+                const int64_t st = seg_start(n, T, q), ln = seg_len(n, T, q);
+                CHECK(st == pos);
+                CHECK(ln >= 1);
+                if (q + 1 < T) CHECK(ln % 16 == 0);
+                if (T >= (n + 127) / 128) CHECK(ln <= 128);
+                CHECK(st == 16 * split_start((n + 15) / 16, T, q));
+                pos += ln;
+            }
+            CHECK(pos == n);
+        }
+    // Patches: patch_np(T) per block dimension, each at most 4 tiles wide.
+    for (int T = 1; T <= 16; ++T) {
+        const int np = (T + 3) / 4;
+        for (int p = 0; p < np; ++p) CHECK(split_len(T, np, p) >= 1 && split_len(T, np, p) <= 4);
+    }
     // Tile order: a bijection of [0,128)^2 onto [0,16384); lane (h, q) of
     // wave w reads double2 number 64 (16 w + jj) + 16 h + q in load jj and
     // finds rows q + 16k, columns 16w + 4h + c there.

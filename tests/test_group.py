@@ -40,9 +40,12 @@ def test_group_small_uneven():
         assert rel_l2(o.cpu().numpy(), ref) <= TOL
 
 
-def test_group_equals_single_instance_runs():
-    """Same kernels, same summation order: bitwise equal to propagating alone."""
+def test_group_equals_single_instance_runs(monkeypatch):
+    """Same kernels, same summation order: bitwise equal to propagating alone
+    on the split path (a completion launch, then the patch products launch),
+    which is what every group round runs."""
     from paper_1201_6062_amd.api import Group
+    monkeypatch.setenv("TDSE_SPLIT", "1")
     specs = wl.uneven_specs(64)[:6]
     hs = [wl.hamiltonian(s.lmax, s.n, s.seed) for s in specs]
     fs = [wl.rk4_samples(s.pulse, 0.005, 60 + 13 * q) for q, s in enumerate(specs)]
