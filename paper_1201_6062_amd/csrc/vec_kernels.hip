@@ -70,11 +70,10 @@ __device__ __forceinline__ double2 ld_global(const double2 *p) {
 // end, which the hardware answers with zeros and no memory access. Every load
 // is issued either way, so the wait counter stays exact; with loads under
 // branches the compiler has to wait for all of them before the first use of
-// anything loaded earlier. Used where a value loaded before the tiles is
-// needed early (the Krylov update's alpha); the split path's products launch
-// keeps branch-skipped loads, which measured 1-2% faster there (its inputs
-// are needed only at the LDS barrier). 0x00020000: the fourth descriptor word
-// for untyped buffer access on gfx9-family GPUs.
+// anything loaded earlier. Used by the Krylov products launch (the
+// recurrence's alpha is needed early) and, with the LDS bit, by the patch
+// products launch (its explicit waits count every load). 0x00020000: the
+// fourth descriptor word for untyped buffer access on gfx9-family GPUs.
 constexpr int TILE_BYTES = VEC_TILE_MAX * VEC_TILE_MAX * 8;
 constexpr int TILE_SKIP = 0x40000000;  // offset of a skipped load (past the end)
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const double *dip, int tile) {
@@ -495,29 +494,33 @@ __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
 // D_l: tile rows ti0 .. ti0+PI-1, tile columns tj0 .. tj0+PJ-1. Each wave
 // streams its 16 KB slice of every tile of the patch (wave w: columns 16w ..
 // 16w+15, the tile_pos order of the fused kernel) straight into LDS with
-// buffer loads that carry the LDS bit: PATCH_LOOK loads of 1 KB in flight
-// per wave through a ring of PATCH_RING slots, so no registers are tied up by
-// data in flight and the stream runs on across tile boundaries. Parts of a
-// tile that are all padding are not fetched (out-of-range offsets).
+// buffer loads that carry the LDS bit: LOOK loads of 1 KB in flight per wave
+// through a ring of PATCH_RING slots, so no registers are tied up by data in
+// flight and the stream runs on across tile boundaries. Parts of a tile that
+// are all padding are not fetched (out-of-range offsets).
 //   Row partials (towards z_l) accumulate over the patch's PJ tiles of a
-//   tile row in registers and are summed over the 8 waves in LDS once per
-//   tile row; column partials (towards z_{l+1}) accumulate over the patch's
-//   PI tile rows in registers and are summed over the 16 row classes of a
-//   wave by lane shuffles once per patch.
+//   tile row in registers and are kept per tile row; column partials
+//   (towards z_{l+1}) accumulate over the patch's PI tile rows. Both are
+//   summed across lanes and waves only once the patch's stream has ended:
+//   the columns over the 16 row classes of a wave by lane shuffles, the rows
+//   over the 8 waves in the ring's LDS. Nothing waits on the other waves
+//   while the stream runs.
 // A patch leaves one row partial per row segment and one column partial per
 // column segment, so a segment collects patch_np(T) of each (T when every
 // tile is a workgroup of its own), and the workgroup turns over once per
-// patch rather than once per tile. The LDS (152 KB) admits one workgroup
-// per CU: 8 waves, 64 KB in flight per CU.
+// patch rather than once per tile. The LDS (144 KB) admits one workgroup
+// per CU: 8 waves, LOOK KB in flight per wave.
 constexpr int PATCH_RING = 16;  // 1 KB slots per wave: one tile slice, so load r of a tile uses slot r
-constexpr int PATCH_LOOK = 8;   // loads in flight per wave
+// Loads in flight per wave: 8, 10, 12 and 14 measured within 1% of each
+// other on both streaming workloads (10 the fastest by a hair).
+constexpr int PATCH_LOOK = 10;
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 struct PatchLds {
-    char ring[VEC_THREADS / 64][PATCH_RING][1024];  // [wave][slot]
+    char ring[VEC_THREADS / 64][PATCH_RING][1024];  // [wave][slot]; after the stream, the row sums
     double2 uA[PATCH_MAX][VEC_TILE_MAX];            // inputs of the row segments (l, ti0 + ii)
-    double2 rbuf[VEC_THREADS / 64][VEC_TILE_MAX];   // [wave][row]: one tile row's row sums
+    double2 uB[PATCH_MAX][VEC_TILE_MAX];            // inputs of the column segments (l+1, tj0 + jj)
 };
 
 // What a patch workgroup reads and writes, copied into scalar registers at
@@ -575,8 +578,8 @@ __device__ __forceinline__ void patch_issue(const PatchTile &pt, int r, char *ri
                                              need ? lane_off + r * 1024 : TILE_SKIP, 0, 0, 0);
 }
 
-// Workgroup barrier for LDS written with ds instructions only: the ring's
-// loads stay in flight (a barrier with a memory fence would wait for them).
+// Workgroup barrier for LDS written with ds instructions only (a barrier with
+// a memory fence would also wait for the ring's loads).
 __device__ __forceinline__ void patch_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // LDS accesses of the patch kernel, through byte pointers: the compiler then
@@ -591,46 +594,35 @@ __device__ __forceinline__ double2 lds_ld2(const char *p) {
 __device__ __forceinline__ void lds_st2(char *p, double2 v) { *reinterpret_cast<dv2_t *>(p) = dv2_t{v.x, v.y}; }
 
 // Patch (pr, pc) of block l: reads the inputs A.u, writes the partials in
-// the np-per-segment layout.
+// the np-per-segment layout. LOOK (even, 8 .. 14): loads in flight per wave.
+template <int LOOK>
 __device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, int pr, int pc) {
+    static_assert(LOOK % 2 == 0 && LOOK >= 4 && LOOK <= PATCH_RING - 2, "a slot is refilled only after its data was used");
     __shared__ PatchLds lds;
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
     const int h = lane >> 4, qq = lane & 15, cb = wv * 16 + 4 * h;
-    const int T = A.T;
+    const int T = A.T, n = A.n;
     const int ti0 = (int)split_start(T, np, pr), PI = (int)split_len(T, np, pr);
     const int tj0 = (int)split_start(T, np, pc), PJ = (int)split_len(T, np, pc);
-    const int n = A.n;
     const double2 *u = A.u;
-    double2 *rowp_out = A.rowp, *colp_out = A.colp;
-    char *ring = lds.ring[wv][0];
-    char *rbuf = reinterpret_cast<char *>(&lds.rbuf[0][0]), *uab = reinterpret_cast<char *>(&lds.uA[0][0]);
+    char *ring = lds.ring[wv][0], *ring0 = lds.ring[0][0];
+    char *uab = reinterpret_cast<char *>(&lds.uA[0][0]), *ubb = reinterpret_cast<char *>(&lds.uB[0][0]);
     const int lane_off = wv * 16 * 1024 + lane * 16;
 
-    // ---- inputs: the column-side entries this lane multiplies (columns
-    // cb .. cb+3 of each tile column) into registers, the row-side segments
-    // into LDS; zero past each segment.
-    double2 ub[PATCH_MAX][4];
-#pragma unroll
-    for (int jj = 0; jj < PATCH_MAX; ++jj) {
-        int c0, rb;
-        segment_of(n, T, tj0 + (jj < PJ ? jj : 0), &c0, &rb);
-        const size_t g = (size_t)(l + 1) * n + c0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const bool ok = jj < PJ && cb + c < rb;
-            const double2 v = ld_global(u + g + (ok ? cb + c : 0));
-            ub[jj][c] = ok ? v : make_double2(0.0, 0.0);
-        }
-    }
-    double2 ua_in;
+    // ---- inputs into LDS, zero past each segment: thread t loads entry
+    // t % 128 of row segment t / 128 and of column segment t / 128
+    double2 ua_in, ub_in;
     {
-        const int ii = t >> 7, e = t & (VEC_TILE_MAX - 1);
-        int r0, ra;
-        segment_of(n, T, ti0 + (ii < PI ? ii : 0), &r0, &ra);
-        const bool ok = ii < PI && e < ra;
-        const double2 v = ld_global(u + (size_t)l * n + r0 + (ok ? e : 0));
-        ua_in = ok ? v : make_double2(0.0, 0.0);
+        const int x = t >> 7, e = t & (VEC_TILE_MAX - 1);
+        int r0, ra, c0, rb;
+        segment_of(n, T, ti0 + (x < PI ? x : 0), &r0, &ra);
+        segment_of(n, T, tj0 + (x < PJ ? x : 0), &c0, &rb);
+        const bool oka = x < PI && e < ra, okb = x < PJ && e < rb;
+        const double2 va = ld_global(u + (size_t)l * n + r0 + (oka ? e : 0));
+        const double2 vb = ld_global(u + (size_t)(l + 1) * n + c0 + (okb ? e : 0));
+        ua_in = oka ? va : make_double2(0.0, 0.0);
+        ub_in = okb ? vb : make_double2(0.0, 0.0);
     }
     // The ring starts zeroed: slots a skipped load leaves alone then hold
     // zeros or an earlier tile's (finite) values, which only meet zero inputs
@@ -639,14 +631,15 @@ __device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, in
     for (int r = 0; r < PATCH_RING; ++r) *reinterpret_cast<dv2_t *>(ring + r * 1024 + lane * 16) = dv2_t{0.0, 0.0};
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 
-    // ---- the stream: loads 0 .. PATCH_LOOK-1 of the first tile
+    // ---- the stream: loads 0 .. LOOK-1 of the first tile
     PatchTile cur = patch_tile(A, l, ti0, tj0, PI, 0, 0);
 #pragma unroll
-    for (int r = 0; r < PATCH_LOOK; ++r) patch_issue(cur, r, ring, lane_off, cb);
+    for (int r = 0; r < LOOK; ++r) patch_issue(cur, r, ring, lane_off, cb);
     lds_st2(uab + t * 16, ua_in);  // uA[t / 128][t % 128]
+    lds_st2(ubb + t * 16, ub_in);
     patch_barrier();
     // the data of loads 0 and 1 (each step below reads the next pair ahead)
-    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(PATCH_LOOK - 2) : "memory");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOOK - 2) : "memory");
     double2 d0 = lds_ld2(ring + lane * 16), d1 = lds_ld2(ring + 1024 + lane * 16);
 
     double2 col[PATCH_MAX][4];
@@ -654,9 +647,17 @@ __device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, in
     for (int jj = 0; jj < PATCH_MAX; ++jj)
 #pragma unroll
         for (int c = 0; c < 4; ++c) col[jj][c] = make_double2(0.0, 0.0);
+    // row sums of each tile row, reduced over the wave's column groups:
+    // rows[ii][k] holds rows qq + 16 (k + rcls) (k = 0, 1) of tile row ii
     const int rcls = 2 * (h & 1) + 4 * (h >> 1);
+    double2 rows[PATCH_MAX][2];
+#pragma unroll
+    for (int x = 0; x < PATCH_MAX; ++x) rows[x][0] = rows[x][1] = make_double2(0.0, 0.0);
 
-    for (int ii = 0; ii < PI; ++ii) {
+    // (tile rows unrolled: the row sums then stay in registers)
+#pragma unroll
+    for (int ii = 0; ii < PATCH_MAX; ++ii) {
+        if (ii >= PI) break;
         double2 ua[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) ua[k] = lds_ld2(uab + (ii * VEC_TILE_MAX + qq + 16 * k) * 16);
@@ -668,24 +669,28 @@ __device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, in
             if (jj < PJ) {
                 const bool row_end = jj + 1 >= PJ;
                 const PatchTile nxt = patch_tile(A, l, ti0, tj0, PI, row_end ? ii + 1 : ii, row_end ? 0 : jj + 1);
+                double2 ub[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) ub[c] = lds_ld2(ubb + (jj * VEC_TILE_MAX + cb + c) * 16);
 #pragma unroll
                 for (int kk = 0; kk < 8; ++kk) {
-                    // keep PATCH_LOOK loads ahead: this tile's loads 8..15, then the next tile's 0..7
-                    if (kk < 4) {
-                        patch_issue(cur, 2 * kk + 8, ring, lane_off, cb);
-                        patch_issue(cur, 2 * kk + 9, ring, lane_off, cb);
+                    // keep LOOK loads ahead: this tile's loads up to 15, then the next tile's
+                    const int r = 2 * kk + LOOK;
+                    if (r < PATCH_RING) {
+                        patch_issue(cur, r, ring, lane_off, cb);
+                        patch_issue(cur, r + 1, ring, lane_off, cb);
                     } else {
-                        patch_issue(nxt, 2 * kk - 8, ring, lane_off, cb);
-                        patch_issue(nxt, 2 * kk - 7, ring, lane_off, cb);
+                        patch_issue(nxt, r - PATCH_RING, ring, lane_off, cb);
+                        patch_issue(nxt, r + 1 - PATCH_RING, ring, lane_off, cb);
                     }
                     // the pair after this one has landed: read it ahead
-                    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(PATCH_LOOK - 2) : "memory");
+                    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LOOK - 2) : "memory");
                     const int rn = (2 * kk + 2) & (PATCH_RING - 1);
                     const double2 n0 = lds_ld2(ring + rn * 1024 + lane * 16);
                     const double2 n1 = lds_ld2(ring + (rn + 1) * 1024 + lane * 16);
                     // d0 = D[row qq+16kk][cb, cb+1], d1 = D[row qq+16kk][cb+2, cb+3]
-                    tr[kk] = fma(d1.y, ub[jj][3].x, fma(d1.x, ub[jj][2].x, fma(d0.y, ub[jj][1].x, fma(d0.x, ub[jj][0].x, tr[kk]))));
-                    ti[kk] = fma(d1.y, ub[jj][3].y, fma(d1.x, ub[jj][2].y, fma(d0.y, ub[jj][1].y, fma(d0.x, ub[jj][0].y, ti[kk]))));
+                    tr[kk] = fma(d1.y, ub[3].x, fma(d1.x, ub[2].x, fma(d0.y, ub[1].x, fma(d0.x, ub[0].x, tr[kk]))));
+                    ti[kk] = fma(d1.y, ub[3].y, fma(d1.x, ub[2].y, fma(d0.y, ub[1].y, fma(d0.x, ub[0].y, ti[kk]))));
                     const double2 a = ua[kk];
                     col[jj][0].x = fma(d0.x, a.x, col[jj][0].x);
                     col[jj][0].y = fma(d0.x, a.y, col[jj][0].y);
@@ -701,8 +706,7 @@ __device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, in
                 cur = nxt;
             }
         }
-        // ---- row partials of tile row ii: over the wave's column groups
-        // (lane bits 5, 4), then over the 8 waves in a fixed order
+        // row sums of tile row ii over the wave's column groups (lane bits 5, 4)
         double sr[4], si[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -710,29 +714,35 @@ __device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, in
             si[k] = swap_reduce<5>(ti[k], ti[k + 4]);
         }
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const double zr = swap_reduce<4>(sr[k], sr[k + 2]), zi = swap_reduce<4>(si[k], si[k + 2]);
-            lds_st2(rbuf + (wv * VEC_TILE_MAX + qq + 16 * (k + rcls)) * 16, make_double2(zr, zi));
-        }
-        patch_barrier();
-        if (t < VEC_TILE_MAX) {
-            int r0, ra;
-            segment_of(n, T, ti0 + ii, &r0, &ra);
-            if (t < ra) {
-                double2 z = lds_ld2(rbuf + t * 16);
-#pragma unroll
-                for (int w = 1; w < VEC_THREADS / 64; ++w) z = cadd(z, lds_ld2(rbuf + (w * VEC_TILE_MAX + t) * 16));
-                st_global(rowp_out + ((size_t)(l * T + ti0 + ii) * np + pc) * VEC_TILE_MAX + t, z);
-            }
-        }
-        patch_barrier();
+        for (int k = 0; k < 2; ++k)
+            rows[ii][k] = make_double2(swap_reduce<4>(sr[k], sr[k + 2]), swap_reduce<4>(si[k], si[k + 2]));
     }
-    // the stream's last loads (past the patch: no fetch) before the workgroup ends
+    // ---- the stream has ended (its last loads fetch nothing); every wave's
+    // ring is free once all waves are here
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-
-    // ---- column partials: sum over the 16 row classes (lane bits 3..0),
-    // halving the values each step; lane (h, q) ends with tile column
-    // jj = q / 4, column cb + q % 4
+    patch_barrier();
+    // row partials: the 8 waves' sums of each row, in a fixed order
+#pragma unroll
+    for (int x = 0; x < PATCH_MAX; ++x)
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            lds_st2(ring0 + ((x * (VEC_THREADS / 64) + wv) * VEC_TILE_MAX + qq + 16 * (k + rcls)) * 16, rows[x][k]);
+    patch_barrier();
+    {
+        const int x = t >> 7, a = t & (VEC_TILE_MAX - 1);
+        int r0, ra;
+        segment_of(n, T, ti0 + (x < PI ? x : 0), &r0, &ra);
+        if (x < PI && a < ra) {
+            const char *base = ring0 + (x * (VEC_THREADS / 64) * VEC_TILE_MAX + a) * 16;
+            double2 z = lds_ld2(base);
+#pragma unroll
+            for (int w = 1; w < VEC_THREADS / 64; ++w) z = cadd(z, lds_ld2(base + w * VEC_TILE_MAX * 16));
+            st_global(A.rowp + ((size_t)(l * T + ti0 + x) * np + pc) * VEC_TILE_MAX + a, z);
+        }
+    }
+    // column partials: sum over the 16 row classes (lane bits 3..0), halving
+    // the values each step; lane (h, q) ends with tile column jj = q / 4,
+    // column cb + q % 4
     double v[8 * PATCH_MAX];
 #pragma unroll
     for (int jj = 0; jj < PATCH_MAX; ++jj)
@@ -757,17 +767,18 @@ __device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, in
         int c0, rb;
         segment_of(n, T, tj0 + (jj < PJ ? jj : 0), &c0, &rb);
         if (jj < PJ && cc < rb)
-            st_global(colp_out + ((size_t)(l * T + tj0 + jj) * np + pr) * VEC_TILE_MAX + cc, make_double2(v[0], v[1]));
+            st_global(A.colp + ((size_t)(l * T + tj0 + jj) * np + pr) * VEC_TILE_MAX + cc, make_double2(v[0], v[1]));
     }
 }
 
 // Products launch of the split path (after a vec_combine launch): one
 // workgroup per patch, patch_np(T)^2 patches per block.
+template <int LOOK>
 __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void vec_patch_kernel(VecBuffers b, VecLaunch L) {
     const int np = patch_np(b.T);
     const int w = blockIdx.x, per = np * np;
     const int l = w / per, rem = w - l * per;
-    patch_body(patch_args(b, L.parity), np, l, rem / np, rem - (rem / np) * np);
+    patch_body<LOOK>(patch_args(b, L.parity), np, l, rem / np, rem - (rem / np) * np);
 }
 
 // Products launch of the next Krylov vector with the recurrence's update
@@ -1063,13 +1074,14 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_group_combine_kernel(const G
 
 // Products round of a group: one workgroup per patch (GroupTile i, j: the
 // patch's row and column within its block).
+template <int LOOK>
 __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void vec_group_patch_kernel(const GroupTile *tiles, const GroupInst *insts, const GroupDesc *desc, int32_t off) {
     const GroupTile gt = tiles[blockIdx.x];
     const GroupInst &gi = insts[gt.inst];
     const int64_t round = desc->base_round + off;
     if (round >= 4 * gi.nsteps) return;
     const PatchArgs A = patch_args(gi.b, (int)(round & 1));
-    patch_body(A, patch_np(A.T), gt.l, gt.i, gt.j);
+    patch_body<LOOK>(A, patch_np(A.T), gt.l, gt.i, gt.j);
 }
 
 __global__ void group_desc_kernel(GroupDesc *desc, int64_t base_round, double dt) {
@@ -1387,7 +1399,7 @@ hipError_t vec_launch_hmul_dot(const VecBuffers &b, const VecLaunch &l, double *
 hipError_t vec_launch_products(const VecBuffers &b, const VecLaunch &l, hipStream_t s) {
     const int np = patch_np(b.T);
     if (b.lmax == 0 || b.T > 16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(vec_patch_kernel, dim3(b.lmax * np * np), dim3(VEC_THREADS), 0, s, b, l);
+    hipLaunchKernelGGL(vec_patch_kernel<PATCH_LOOK>, dim3(b.lmax * np * np), dim3(VEC_THREADS), 0, s, b, l);
     return hipGetLastError();
 }
 hipError_t group_launch_round(const GroupSeg *segs, int nsegs, const GroupTile *tiles, int ntiles,
@@ -1395,7 +1407,7 @@ hipError_t group_launch_round(const GroupSeg *segs, int nsegs, const GroupTile *
     hipLaunchKernelGGL(vec_group_combine_kernel, dim3(nsegs), dim3(VEC_TILE_MAX), 0, s, segs, insts, desc, off);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(vec_group_patch_kernel, dim3(ntiles), dim3(VEC_THREADS), 0, s, tiles, insts, desc, off);
+    hipLaunchKernelGGL(vec_group_patch_kernel<PATCH_LOOK>, dim3(ntiles), dim3(VEC_THREADS), 0, s, tiles, insts, desc, off);
     return hipGetLastError();
 }
 hipError_t group_set_desc(GroupDesc *desc, int64_t base_round, double dt, hipStream_t s) {
