@@ -74,17 +74,39 @@ def test_group_full_length_sampled_instances():
 
 @pytest.fixture(scope="module")
 def uneven64():
-    """The 64-instance uneven workload: specs, Hamiltonians' plans, full-length samples, c0."""
+    """The 64-instance uneven workload: specs, Hamiltonians' plans, full-length
+    samples, c0. The plans are created on the split path, so that each one
+    propagated alone runs the kernels a group round runs."""
     specs = wl.uneven_specs(64)
     plans, fs, cs = [], [], []
-    for s in specs:
-        h = wl.hamiltonian(s.lmax, s.n, s.seed)
-        plans.append(plan_of(h))
-        fs.append(torch.as_tensor(wl.rk4_samples(s.pulse, 0.005, s.nsteps), device="cuda"))
-        cs.append(torch.as_tensor(wl.ground_state(s.lmax, s.n)[0], device="cuda"))
+    old = os.environ.get("TDSE_SPLIT")
+    os.environ["TDSE_SPLIT"] = "1"
+    try:
+        for s in specs:
+            h = wl.hamiltonian(s.lmax, s.n, s.seed)
+            plans.append(plan_of(h))
+            fs.append(torch.as_tensor(wl.rk4_samples(s.pulse, 0.005, s.nsteps), device="cuda"))
+            cs.append(torch.as_tensor(wl.ground_state(s.lmax, s.n)[0], device="cuda"))
+    finally:
+        if old is None:
+            del os.environ["TDSE_SPLIT"]
+        else:
+            os.environ["TDSE_SPLIT"] = old
     yield specs, plans, fs, cs
     for p in plans:
         p.close()
+
+
+def test_group_all64_bitwise_alone(uneven64):
+    """All 64 instances in one group for 40 steps: every instance bitwise
+    equal to propagating it alone (same kernels, same summation order)."""
+    from paper_1201_6062_amd.api import Group
+    specs, plans, fs, cs = uneven64
+    steps = 40
+    out = Group(plans).propagate([f[:steps] for f in fs], cs, 0.005)
+    for i, (p, f, c, o) in enumerate(zip(plans, fs, cs, out)):
+        alone = p.propagate(f[:steps][None], c[None], 0.005, "rk4")
+        assert torch.equal(alone.reshape(-1), o), i
 
 
 def test_group_all64_first_200_steps(uneven64):
