@@ -52,30 +52,37 @@ __constant__ double RKF_B4[6] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 41
 __constant__ double RKF_E[6] = {16.0 / 135.0 - 25.0 / 216.0, 0.0, 6656.0 / 12825.0 - 1408.0 / 2565.0,
                                 28561.0 / 56430.0 - 2197.0 / 4104.0, -9.0 / 50.0 + 1.0 / 5.0, 2.0 / 55.0};
 
-template <int TM, int TN, int KC>
+// Stride of one 1 KB group of a staged panel with rows of W doubles: 128 B
+// of padding after each group (the four 16-lane row groups of a fragment
+// read then fall into two LDS bank sets); with a three-deep ring, 64 B after
+// each group of a 128-wide panel (one row per group: its rows then fall
+// into four bank sets, just as evenly spread), so that two workgroups' rings
+// fit one CU's LDS.
+template <int W, int DEPTH>
+__host__ __device__ constexpr int panel_group() { return 1024 + (DEPTH == 3 && W == 128 ? 64 : 128); }
+
+template <int TM, int TN, int KC, int DEPTH = 2>
 struct BatTile {
     static constexpr int THREADS = 256;
     static constexpr int WM = TM / 2, WN = TN / 2;       // 2 x 2 waves
     static constexpr int SM = WM / 16, SN = WN / 16;     // 16 x 16 subtiles per wave
     // The K panels go from global memory straight into LDS (global_load_lds):
     // one instruction moves 64 lanes x 16 B = 1 KB, i.e. 128 / TM rows of the
-    // A panel (128 / TN rows of B). Each such group of rows is followed by
-    // 128 B of padding, so the four 16-lane row groups of a fragment read
-    // fall into two LDS bank sets.
+    // A panel (128 / TN rows of B), each such group followed by padding.
     static constexpr int A_RPI = 128 / TM, B_RPI = 128 / TN;
-    static constexpr int GROUP = 1024 + 128;
+    static constexpr int GROUP_A = panel_group<TM, DEPTH>(), GROUP_B = panel_group<TN, DEPTH>();
     static constexpr int A_GROUPS = KC / A_RPI, B_GROUPS = KC / B_RPI;
     static constexpr int A_PER_W = A_GROUPS / 4, B_PER_W = B_GROUPS / 4;  // instructions per wave
-    static constexpr int A_BYTES = A_GROUPS * GROUP, B_BYTES = B_GROUPS * GROUP;
+    static constexpr int A_BYTES = A_GROUPS * GROUP_A, B_BYTES = B_GROUPS * GROUP_B;
 };
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 // byte offset of element (k, x) of a staged panel with rows of W doubles
-template <int W>
+template <int W, int DEPTH = 2>
 __device__ __forceinline__ int panel_off(int k, int x) {
     constexpr int RPI = 128 / W;
-    return (k / RPI) * (1024 + 128) + ((k % RPI) * W + x) * 8;
+    return (k / RPI) * panel_group<W, DEPTH>() + ((k % RPI) * W + x) * 8;
 }
 
 // One K chunk of a workgroup: start the direct-to-LDS loads of the next
@@ -84,25 +91,42 @@ __device__ __forceinline__ int panel_off(int k, int x) {
 // when la is non-null. The restrict qualifiers tell the compiler that the
 // panels being read and the ones being filled do not overlap, so it does
 // not wait for the new loads before reading the current panels.
-template <int TM, int TN, int KC, bool PIN = false>
+template <int TM, int TN, int KC, bool PIN = false, int DEPTH = 2>
 __device__ __forceinline__ void bat_chunk(const char *__restrict__ la, const char *__restrict__ lb,
                                           char *__restrict__ wa, char *__restrict__ wb,
                                           const double *__restrict__ pa, const double *__restrict__ pb,
                                           int Np, int ldu, int lane, int wv,
                                           d4_t (&acc)[BatTile<TM, TN, KC>::SM][BatTile<TM, TN, KC>::SN]) {
-    using C = BatTile<TM, TN, KC>;
-    if (wa) {
+    using C = BatTile<TM, TN, KC, DEPTH>;
+    if (DEPTH == 3 && wa) {
+        // Buffer loads with the LDS bit: the compiler does not track these
+        // against LDS reads (it would wait for every panel in flight before
+        // reading the current one, the previous chunk's loads included);
+        // the kernel's explicit waits order them.
+        const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(pa), 0, 0x7fffffff, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(pb), 0, 0x7fffffff, 0x00020000);
+#pragma unroll
+        for (int q = 0; q < C::A_PER_W; ++q) {
+            const int g = wv + 4 * q, k = g * C::A_RPI + lane / (TM / 2), x = 2 * (lane % (TM / 2));
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_void_t *)(wa + g * C::GROUP_A), 16, (k * Np + x) * 8, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < C::B_PER_W; ++q) {
+            const int g = wv + 4 * q, k = g * C::B_RPI + lane / (TN / 2), x = 2 * (lane % (TN / 2));
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void_t *)(wb + g * C::GROUP_B), 16, (k * ldu + x) * 8, 0, 0, 0);
+        }
+    } else if (wa) {
 #pragma unroll
         for (int q = 0; q < C::A_PER_W; ++q) {
             const int g = wv + 4 * q, k = g * C::A_RPI + lane / (TM / 2), x = 2 * (lane % (TM / 2));
             __builtin_amdgcn_global_load_lds((const void *)(pa + (size_t)k * Np + x),
-                                             (lds_void_t *)(wa + g * C::GROUP), 16, 0, 0);
+                                             (lds_void_t *)(wa + g * C::GROUP_A), 16, 0, 0);
         }
 #pragma unroll
         for (int q = 0; q < C::B_PER_W; ++q) {
             const int g = wv + 4 * q, k = g * C::B_RPI + lane / (TN / 2), x = 2 * (lane % (TN / 2));
             __builtin_amdgcn_global_load_lds((const void *)(pb + (size_t)k * ldu + x),
-                                             (lds_void_t *)(wb + g * C::GROUP), 16, 0, 0);
+                                             (lds_void_t *)(wb + g * C::GROUP_B), 16, 0, 0);
         }
     }
     if (!la) return;
@@ -115,11 +139,11 @@ __device__ __forceinline__ void bat_chunk(const char *__restrict__ la, const cha
 #pragma unroll
             for (int i = 0; i < C::SM; ++i)
                 af[slot][i] =
-                    *reinterpret_cast<const double *>(la + panel_off<TM>(kr, wy * C::WM + i * 16 + (lane & 15)));
+                    *reinterpret_cast<const double *>(la + panel_off<TM, DEPTH>(kr, wy * C::WM + i * 16 + (lane & 15)));
 #pragma unroll
             for (int j = 0; j < C::SN; ++j)
                 bf[slot][j] =
-                    *reinterpret_cast<const double *>(lb + panel_off<TN>(kr, wx * C::WN + j * 16 + (lane & 15)));
+                    *reinterpret_cast<const double *>(lb + panel_off<TN, DEPTH>(kr, wx * C::WN + j * 16 + (lane & 15)));
         };
         frag(0, 0);
 #pragma unroll
@@ -147,11 +171,11 @@ __device__ __forceinline__ void bat_chunk(const char *__restrict__ la, const cha
 #pragma unroll
             for (int i = 0; i < C::SM; ++i)
                 af[slot][i] =
-                    *reinterpret_cast<const double *>(la + panel_off<TM>(kr, wy * C::WM + i * 16 + (lane & 15)));
+                    *reinterpret_cast<const double *>(la + panel_off<TM, DEPTH>(kr, wy * C::WM + i * 16 + (lane & 15)));
 #pragma unroll
             for (int j = 0; j < C::SN; ++j)
                 bf[slot][j] =
-                    *reinterpret_cast<const double *>(lb + panel_off<TN>(kr, wx * C::WN + j * 16 + (lane & 15)));
+                    *reinterpret_cast<const double *>(lb + panel_off<TN, DEPTH>(kr, wx * C::WN + j * 16 + (lane & 15)));
         };
 #pragma unroll
         for (int d = 0; d < D; ++d)
@@ -181,9 +205,15 @@ __device__ __forceinline__ void bat_chunk(const char *__restrict__ la, const cha
 // own panels; the second group's accumulators are added to the first's in
 // LDS before the epilogue. For grids of few tiles (few pulses): twice the
 // waves per CU.
-template <int TM, int TN, int KC, bool ADJ, int KS>
+// DEPTH: panels in flight. 2: the next chunk's panels load while this
+// chunk's products run, and every chunk ends waiting for all of them. 3: the
+// panels of the chunk after next are issued at the start of each chunk, and
+// a chunk waits only for its own (one chunk's loads stay in flight across
+// the barrier).
+template <int TM, int TN, int KC, bool ADJ, int KS, int DEPTH = 2>
 __global__ __launch_bounds__(256 * KS) __attribute__((amdgpu_waves_per_eu(1, 2))) void bat_stage_kernel(BatBuffers b, BatLaunch L) {
-    using C = BatTile<TM, TN, KC>;
+    using C = BatTile<TM, TN, KC, DEPTH>;
+    static_assert(DEPTH == 2 || (DEPTH == 3 && KS == 1), "three-deep rings for one K group");
     static_assert(C::A_PER_W >= 1 && C::B_PER_W >= 1 && C::A_GROUPS % 4 == 0 && C::B_GROUPS % 4 == 0,
                   "panel groups must split evenly over the 4 waves");
     const int Np = b.np, ldu = b.ldu, lmax = b.lmax;
@@ -195,8 +225,8 @@ __global__ __launch_bounds__(256 * KS) __attribute__((amdgpu_waves_per_eu(1, 2))
     const int m = tile / (RT * CT), rem = tile - m * RT * CT, rt = rem / CT, ct = rem - rt * CT;
     const int r0 = rt * TM, c0 = ct * TN;
 
-    __shared__ __attribute__((aligned(16))) char lds_a[KS][2][C::A_BYTES];
-    __shared__ __attribute__((aligned(16))) char lds_b[KS][2][C::B_BYTES];
+    __shared__ __attribute__((aligned(16))) char lds_a[KS][DEPTH][C::A_BYTES];
+    __shared__ __attribute__((aligned(16))) char lds_b[KS][DEPTH][C::B_BYTES];
 
     const int t = threadIdx.x % 256, lane = t & 63, wv = t >> 6;
     const int kg = KS == 2 ? (int)(threadIdx.x >> 8) : 0;  // K group of this wave
@@ -239,7 +269,27 @@ __global__ __launch_bounds__(256 * KS) __attribute__((amdgpu_waves_per_eu(1, 2))
     const int niter = KS == 1 ? nchunks : (nchunks > 0 ? kchunks : 0);
     char(*la)[C::A_BYTES] = lds_a[kg];
     char(*lb)[C::B_BYTES] = lds_b[kg];
-    if (niter > 0) {
+    if constexpr (DEPTH == 3) {
+        // chunks 0 and 1 in flight; chunk q waits for its own panels only
+        constexpr int LPW = C::A_PER_W + C::B_PER_W;  // loads per wave and chunk
+#pragma unroll
+        for (int d = 0; d < 2; ++d)
+            if (d < kcnt)
+                bat_chunk<TM, TN, KC, false, 3>(nullptr, nullptr, la[d], lb[d], a_src(kbeg + d), b_src(kbeg + d), Np,
+                                                ldu, lane, wv, acc);
+        for (int q = 0; q < kcnt; ++q) {
+            if (q + 1 < kcnt) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LPW) : "memory");
+            else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            // every wave's part of chunk q has landed, and every wave is done
+            // with chunk q - 1, whose buffer the loads below refill
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            const int nb = (q + 2) % 3;
+            const bool next = q + 2 < kcnt;
+            bat_chunk<TM, TN, KC, false, 3>(la[q % 3], lb[q % 3], next ? la[nb] : nullptr, next ? lb[nb] : nullptr,
+                                            next ? a_src(kbeg + q + 2) : nullptr, next ? b_src(kbeg + q + 2) : nullptr,
+                                            Np, ldu, lane, wv, acc);
+        }
+    } else if (niter > 0) {
         if (kcnt > 0)
             bat_chunk<TM, TN, KC, KS == 2>(nullptr, nullptr, la[0], lb[0], a_src(kbeg), b_src(kbeg), Np, ldu, lane, wv, acc);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -867,6 +917,14 @@ static hipError_t bat_launch(const BatBuffers &b, const BatLaunch &l, hipStream_
 #undef TDSE_SKINNY
         return hipErrorInvalidValue;
     }
+    // The default shape of large batches keeps two chunks' panels in flight
+    // (161 against 162 us per stage at 256 pulses, 181 against 186 us for a
+    // Runge-Kutta-Fehlberg stage); with 128 x 128 tiles the three-deep ring
+    // measured slower (186 us: one workgroup per CU).
+    if (b.ks == 1 && b.tm == 128 && b.tn == 64 && b.kc == 16) {
+        hipLaunchKernelGGL((bat_stage_kernel<128, 64, 16, ADJ, 1, 3>), g, blk, 0, s, b, l);
+        return hipGetLastError();
+    }
 #define TDSE_BAT(TM_, TN_, KC_)                                                                \
     if (b.tm == TM_ && b.tn == TN_ && b.kc == KC_ && b.ks == 1) {                              \
         hipLaunchKernelGGL((bat_stage_kernel<TM_, TN_, KC_, ADJ, 1>), g, blk, 0, s, b, l);   \
@@ -880,7 +938,6 @@ static hipError_t bat_launch(const BatBuffers &b, const BatLaunch &l, hipStream_
     TDSE_BAT2(32, 64, 32)
     TDSE_BAT2(32, 32, 16)
     TDSE_BAT(128, 128, 16)
-    TDSE_BAT(128, 64, 16)
     TDSE_BAT(64, 128, 16)
     TDSE_BAT(64, 64, 16)
     TDSE_BAT(64, 32, 16)
