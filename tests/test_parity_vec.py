@@ -86,10 +86,12 @@ def test_rk4_parity(torch_dev, lmax, n, nsteps, path, monkeypatch):
     assert rel_l2(got, ref) <= TOL
 
 
-@pytest.mark.parametrize("lmax,n,nsteps", [(2, 1100, 10), (1, 2048, 8)])
+@pytest.mark.parametrize("lmax,n,nsteps", [(2, 1100, 10), (2, 1600, 6), (1, 2048, 8)])
 def test_rk4_parity_largest_blocks(torch_dev, lmax, n, nsteps, path, monkeypatch):
     """N beyond 1024 (9 tiles per block dimension) up to the largest supported
-    N = 2048 (16): the tile kernels with a run-time tile count."""
+    N = 2048 (16): the tile kernels with a run-time tile count; on the split
+    path 3 or 4 patches per block dimension, of uneven sizes at N = 1600 (13
+    tile rows: patches of 4, 3, 3 and 3)."""
     apply_path(path, monkeypatch, n)
     h, f, c0 = _rk4_case(lmax, n, nsteps, 0.01)
     plan = make_plan(h)
