@@ -88,3 +88,33 @@ def test_noalloc_rejects_what_it_does_not_cover():
     assert lib.tdse_propagate_noalloc(None, 0, 0, 0.01, 1, None, None, None, None, 0, None) == _capi.TDSE_E_INVAL
     assert "plan is NULL" in lib.tdse_last_error().decode()
     _ = ctypes  # (ctypes used through the binding)
+
+
+def test_noalloc_under_graph_capture():
+    """The entry point recorded into a HIP graph (torch.cuda.graph on a side
+    stream): it only enqueues kernels, so the captured graph replays the whole
+    propagation. Three replays with eager work between them, each bitwise
+    equal to the eager call; the tile path over two 64-step chunks and the
+    one-workgroup path."""
+    for lmax, n, seed, nsteps in [(15, 500, 0, 70), (3, 40, 2, 70)]:
+        plan, f, c0 = _case(lmax, n, seed, nsteps, "rk4", 4, 0.005)
+        ref = plan.propagate_noalloc(f, c0, 0.005, "rk4", out=torch.empty_like(c0))
+        out = torch.full_like(c0, float("nan"))
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):  # one eager call on the capturing stream first
+            plan.propagate_noalloc(f, c0, 0.005, "rk4", out=out)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            plan.propagate_noalloc(f, c0, 0.005, "rk4", out=out)
+        for rep in range(3):
+            out.fill_(float("nan"))
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), (lmax, n, rep)
+            plan.propagate(f, c0, 0.005, "rk4")  # eager work of the program between replays
+            torch.cuda.synchronize()
+        del graph
+        plan.close()
