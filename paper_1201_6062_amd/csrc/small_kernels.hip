@@ -2,18 +2,20 @@
 // states, n <= 64): the latency-bound regime where a launch per product would
 // cost more than the product itself.
 //
-// Each state entry (m, a) is owned by a group of 4 lanes. Row a of H's
-// off-diagonal blocks (Sec. 4, the block product after Eq. ode) is the
-// concatenation of row a of D_m (towards u_{m+1}) and column a of D_{m-1}
-// (towards u_{m-1}): lanes 0 and 1 of the group hold the two halves of the
-// first, lanes 2 and 3 the two halves of the second, in registers for the
-// whole run. A lane's elements multiply consecutive entries of u, so its LDS
-// reads are one base address plus compile-time offsets. Per product every
-// lane forms its partial dot product against u (double-buffered in LDS), the
-// group sums the 4 partials with DPP in fixed order, and the group's first
-// lane completes the RK4 stage or Taylor term (appendix B) with c and the
-// stage accumulator kept in its registers. One LDS barrier per product; field
-// samples are staged into LDS 64 steps at a time, one chunk ahead.
+// Rows come in groups of R = 4 consecutive states of one block (3 or 2 for
+// the larger blocks), each group owned by 4 lanes. Row a of H's off-diagonal blocks (Sec. 4, the block
+// product after Eq. ode) is the concatenation of row a of D_m (towards
+// u_{m+1}) and column a of D_{m-1} (towards u_{m-1}): lanes 0 and 1 of a group
+// hold the two halves of the first for the group's four rows, lanes 2 and 3
+// the two halves of the second, in registers for the whole run. Every u entry
+// a lane reads from LDS (double-buffered) then feeds four rows: the product
+// is bound by those LDS reads, and one lane per row read each entry once per
+// row. A lane's elements multiply consecutive entries of u, so its reads are
+// one base address plus compile-time offsets. The group sums its partials
+// with DPP in a fixed order, and lane r < R of the group completes the RK4 stage
+// or Taylor term (appendix B) of row r, with c and the stage accumulator kept
+// in its registers. One LDS barrier per product; field samples are staged
+// into LDS 64 steps at a time, one chunk ahead.
 #include "tdse_internal.h"
 
 namespace tdse {
@@ -48,54 +50,64 @@ struct SmallArgs {
 // lanes whose elements run past their block (those elements are zero).
 constexpr int SMALL_UBUF = 256 + 64;
 
-// EPL: compiled bound on the dipole elements per lane, ceil(n / 2) <= EPL.
-template <int EPL>
-__global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
+// EPL: compiled bound on the dipole elements per lane and row, ceil(n / 2) <=
+// EPL; R: rows per lane group (4; 3 or 2 for the larger blocks, whose
+// elements would not fit the registers four rows at a time with more than
+// one wave per SIMD); MAXT: threads per workgroup it is compiled for.
+template <int EPL, int R, int MAXT>
+__global__ __launch_bounds__(MAXT) void small_propagate_kernel(SmallArgs A) {
+    constexpr int SMALL_R = R;
     const int n = A.n, lmax = A.lmax, ns = (lmax + 1) * n;
     const int S = A.method == TDSE_RK4 ? 3 : 1;
     const int t = threadIdx.x;
-    const int entry = t >> 2, g = t & 3;
-    const bool live = entry < ns;
-    const int es = live ? entry : 0;
-    const int m = es / n, a = es - m * n;
-    const int half = (n + 1) / 2;  // elements per lane
+    const int grp = t >> 2, g = t & 3;
+    const int rg_per_block = (n + SMALL_R - 1) / SMALL_R;
+    const int m = grp / rg_per_block, a0 = (grp - m * rg_per_block) * SMALL_R;
+    const bool live_grp = m <= lmax;
+    const int a = a0 + g;                       // the row this lane completes (lanes g < R)
+    const bool live = live_grp && g < SMALL_R && a < n;
+    const int es = live ? m * n + a : 0;
+    const int half = (n + 1) / 2;  // elements per lane and row
 
     __shared__ double2 ubuf[2][SMALL_UBUF];
     __shared__ double fbuf[2][64 * 3];
     __shared__ double tay_scale[64];  // dt / (p + 1) of Taylor term p + 1
 
-    // dipole elements of this lane (zero where the element does not exist):
-    // lanes 0, 1: row a of D_m, columns b = (g & 1) half + k, times u_{m+1}[b];
-    // lanes 2, 3: column a of D_{m-1}, rows b = (g & 1) half + k, times u_{m-1}[b]
+    // dipole elements of this lane for the group's rows a0 + r (zero where the
+    // element does not exist): lanes 0, 1: row a0 + r of D_m, columns
+    // b = (g & 1) half + k, times u_{m+1}[b]; lanes 2, 3: column a0 + r of
+    // D_{m-1}, rows b = (g & 1) half + k, times u_{m-1}[b]
     const bool up = g < 2;
     const int b0 = (g & 1) * half;
-    double d[EPL];
+    double d[SMALL_R][EPL];
     const size_t tile = (size_t)VEC_TILE_MAX * VEC_TILE_MAX;
 #pragma unroll
-    for (int k = 0; k < EPL; ++k) {
-        const int bb = b0 + k;
-        double v = 0.0;
-        if (live && k < half && bb < n) {
-            if (up) {
-                if (m < lmax) v = A.dip[(size_t)m * tile + tile_pos(a, bb)];
-            } else {
-                // velocity gauge: the column use enters with a minus sign, -i (r - s)
-                if (m > 0) v = (A.gauge ? -1.0 : 1.0) * A.dip[(size_t)(m - 1) * tile + tile_pos(bb, a)];
+    for (int r = 0; r < SMALL_R; ++r)
+#pragma unroll
+        for (int k = 0; k < EPL; ++k) {
+            const int ar = a0 + r, bb = b0 + k;
+            double v = 0.0;
+            if (live_grp && ar < n && k < half && bb < n) {
+                if (up) {
+                    if (m < lmax) v = A.dip[(size_t)m * tile + tile_pos(ar, bb)];
+                } else {
+                    // velocity gauge: the column use enters with a minus sign, -i (r - s)
+                    if (m > 0) v = (A.gauge ? -1.0 : 1.0) * A.dip[(size_t)(m - 1) * tile + tile_pos(bb, ar)];
+                }
             }
+            d[r][k] = v;
         }
-        d[k] = v;
-    }
     // first u entry this lane reads; a missing neighbour block reads entries
     // 0.. instead (its elements are zero)
     int ubase = up ? (m + 1) * n + b0 : (m - 1) * n + b0;
-    if ((up && m >= lmax) || (!up && m <= 0) || !live) ubase = 0;
+    if ((up && m >= lmax) || (!up && m <= 0) || !live_grp) ubase = 0;
     const double E0 = live ? A.en[es] : 0.0;
     double2 c = make_double2(0.0, 0.0), acc = c;
     if (live) c = reinterpret_cast<const double2 *>(A.c0)[es];
     for (int x = t; x < 2 * SMALL_UBUF; x += blockDim.x) ubuf[x / SMALL_UBUF][x % SMALL_UBUF] = make_double2(0.0, 0.0);
     if (t < 64) tay_scale[t] = A.dt / (double)(t + 1);
     __syncthreads();
-    if (live && g == 0) {
+    if (live) {
         ubuf[0][es] = c;
         if (A.ckpt) reinterpret_cast<double2 *>(A.ckpt)[es] = c;
     }
@@ -119,40 +131,49 @@ __global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
             }
         }
         for (int p = 0; p < nprod; ++p) {
-            // partial dot product of this lane (two interleaved chains)
+            // this lane's partial dot products of the group's four rows
             const double2 *ub = &ubuf[par][ubase];
-            double zr = 0.0, zi = 0.0, zr1 = 0.0, zi1 = 0.0;
+            double zr[SMALL_R], zi[SMALL_R];
+#pragma unroll
+            for (int r = 0; r < SMALL_R; ++r) zr[r] = zi[r] = 0.0;
 #pragma unroll
             for (int k = 0; k < EPL; ++k) {
                 const double2 u = ub[k];
-                if (k & 1) {
-                    zr1 = fma(d[k], u.x, zr1);
-                    zi1 = fma(d[k], u.y, zi1);
-                } else {
-                    zr = fma(d[k], u.x, zr);
-                    zi = fma(d[k], u.y, zi);
+#pragma unroll
+                for (int r = 0; r < SMALL_R; ++r) {
+                    zr[r] = fma(d[r][k], u.x, zr[r]);
+                    zi[r] = fma(d[r][k], u.y, zi[r]);
                 }
-                // keep at most 8 LDS reads in flight (register budget at 1024 threads)
+                // keep at most 8 LDS reads in flight
                 if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
             }
-            zr += zr1;
-            zi += zi1;
-            zr += small_dpp(zr, 1);
-            zi += small_dpp(zi, 1);
-            zr += small_dpp(zr, 2);
-            zi += small_dpp(zi, 2);
-            if (A.gauge) {  // z = -i (r - s): (x + iy) -> (y - ix)
-                const double t = zr;
-                zr = zi;
-                zi = -t;
+            // group sums in a fixed order (lanes 0+1, 2+3, then the pairs)
+#pragma unroll
+            for (int r = 0; r < SMALL_R; ++r) {
+                zr[r] += small_dpp(zr[r], 1);
+                zi[r] += small_dpp(zi[r], 1);
+                zr[r] += small_dpp(zr[r], 2);
+                zi[r] += small_dpp(zi[r], 2);
             }
-            if (live && g == 0) {
+            // lane g takes row a0 + g
+            double zrs = zr[0], zis = zi[0];
+#pragma unroll
+            for (int r = 1; r < SMALL_R; ++r) {
+                zrs = g == r ? zr[r] : zrs;
+                zis = g == r ? zi[r] : zis;
+            }
+            if (A.gauge) {  // z = -i (r - s): (x + iy) -> (y - ix)
+                const double tt = zrs;
+                zrs = zis;
+                zis = -tt;
+            }
+            if (live) {
                 const double2 u = ubuf[par][es];
                 int slot = 0;
                 if (A.method == TDSE_RK4) slot = p == 0 ? 0 : (p == 3 ? 2 : 1);
                 const double F = fbuf[fb][fo * S + slot];
                 // k = -i (E0 u + F z)
-                const double yr = fma(F, zr, E0 * u.x), yi = fma(F, zi, E0 * u.y);
+                const double yr = fma(F, zrs, E0 * u.x), yi = fma(F, zis, E0 * u.y);
                 const double kr = yi, ki = -yr;
                 double2 un;
                 if (A.method == TDSE_RK4) {
@@ -184,10 +205,10 @@ __global__ __launch_bounds__(1024) void small_propagate_kernel(SmallArgs A) {
             par ^= 1;
             __syncthreads();
         }
-        if (A.ckpt && live && g == 0 && (step + 1) % A.ckpt_every == 0)
+        if (A.ckpt && live && (step + 1) % A.ckpt_every == 0)
             reinterpret_cast<double2 *>(A.ckpt)[(size_t)((step + 1) / A.ckpt_every) * ns + es] = c;
     }
-    if (live && g == 0) reinterpret_cast<double2 *>(A.cT)[es] = c;
+    if (live) reinterpret_cast<double2 *>(A.cT)[es] = c;
 }
 
 bool small_eligible(int lmax, int n) { return n <= 64 && (lmax + 1) * n <= 256; }
@@ -222,11 +243,27 @@ hipError_t small_propagate(const double *en, const double *dip, int gauge, int l
                            int64_t nsteps, const double *field, const double *c0, double *cT, double *ckpt,
                            int64_t ckpt_every, hipStream_t s) {
     SmallArgs A{en, dip, field, c0, cT, ckpt, nsteps, ckpt_every > 0 ? ckpt_every : 1, dt, lmax, n, method, order, gauge};
-    const int threads = (((lmax + 1) * n * 4 + 63) / 64) * 64;
-    const int epl = (n + 1) / 2;  // dipole elements per lane
-    if (epl <= 16) hipLaunchKernelGGL(small_propagate_kernel<16>, dim3(1), dim3(threads), 0, s, A);
-    else if (epl <= 26) hipLaunchKernelGGL(small_propagate_kernel<26>, dim3(1), dim3(threads), 0, s, A);
-    else hipLaunchKernelGGL(small_propagate_kernel<32>, dim3(1), dim3(threads), 0, s, A);
+    // four lanes per group of R rows; with (lmax + 1) n <= 256 that is at most
+    // 1024 threads for n <= 16 and 512 for n <= 32 (four rows per group); for
+    // n <= 52 four rows where 256 threads suffice (one wave per SIMD: the
+    // 4 x 26 elements take most of its registers), else three; beyond, two
+    // rows (at most 512 threads)
+    const int epl = (n + 1) / 2;  // dipole elements per lane and row
+    auto threads_for = [&](int R) { return ((((lmax + 1) * ((n + R - 1) / R)) * 4 + 63) / 64) * 64; };
+    const dim3 one(1);
+    if (epl <= 8) {
+        hipLaunchKernelGGL((small_propagate_kernel<8, 4, 1024>), one, dim3(threads_for(4)), 0, s, A);
+    } else if (epl <= 16) {
+        hipLaunchKernelGGL((small_propagate_kernel<16, 4, 512>), one, dim3(threads_for(4)), 0, s, A);
+    } else if (epl <= 26 && threads_for(4) <= 256) {
+        hipLaunchKernelGGL((small_propagate_kernel<26, 4, 256>), one, dim3(threads_for(4)), 0, s, A);
+    } else if (epl <= 26) {
+        if (threads_for(3) > 512) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((small_propagate_kernel<26, 3, 512>), one, dim3(threads_for(3)), 0, s, A);
+    } else {
+        if (threads_for(2) > 512) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((small_propagate_kernel<32, 2, 512>), one, dim3(threads_for(2)), 0, s, A);
+    }
     return hipGetLastError();
 }
 
