@@ -64,7 +64,7 @@ typedef enum {
     TDSE_E_INVAL = 1,        /* invalid argument; nothing enqueued */
     TDSE_E_NOMEM = 2,        /* device allocation failed */
     TDSE_E_HIP = 3,          /* a HIP runtime call failed */
-    TDSE_E_UNSUPPORTED = 4,  /* valid request this build does not support */
+    TDSE_E_UNSUPPORTED = 4,  /* valid request the library does not support */
     TDSE_E_UNSTABLE = 5      /* step size outside the method's stability bound */
 } tdse_status;
 
