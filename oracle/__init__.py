@@ -210,7 +210,8 @@ def taylor_adjoint(energies, dipole, order, dt, field, c0, lam_t, n=None, gauge=
 
 def rkf45(energies, dipole, dt, field, c0, n=None, gauge="length"):
     """Runge-Kutta-Fehlberg 4(5) over field[B, nsteps, 6]; returns (c(T) [B, 2n],
-    err [B, nsteps]) with c advanced by the fourth-order weights."""
+    err [B, nsteps]) with c advanced by the fifth-order weights (the solution
+    the paper propagates, Sec. 5.1) and err the embedded estimate."""
     with _gauge(gauge):
         en, dip, lmax, n = _dims_n(energies, dipole, n)
         field = _f64(field)

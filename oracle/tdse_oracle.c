@@ -370,10 +370,11 @@ int oracle_taylor_adjoint(int lmax, int n, const double *en, const double *dip, 
 /*
  * Runge-Kutta-Fehlberg 4(5) (the embedded pair of appendix B's RK family):
  * six stages at t_k + c_i dt with c = (0, 1/4, 3/8, 12/13, 1, 1/2) and
- * Fehlberg's coefficients a_ij; c advances with the fourth-order weights b4
- * and err[k] = |dt sum_i (b5_i - b4_i) k_i|_2 estimates the local error of
- * step k (b5: the fifth-order weights). field[k*6 + i] is the field at stage
- * i of step k.
+ * Fehlberg's coefficients a_ij; c advances with the fifth-order weights b5
+ * (Sec. 5.1: the paper propagates the pair's fifth-order solution) and
+ * err[k] = |dt sum_i (b5_i - b4_i) k_i|_2 is the embedded estimate of step k
+ * (b4: the fourth-order weights). field[k*6 + i] is the field at stage i of
+ * step k.
  */
 int oracle_rkf45(int lmax, int n, const double *en, const double *dip, double dt, int64_t nsteps,
                  const double *field, double *c, double *err)
@@ -403,12 +404,12 @@ int oracle_rkf45(int lmax, int n, const double *en, const double *dip, double dt
         }
         double e2 = 0.0;
         for (size_t j = 0; j < 2 * ns; ++j) {
-            double acc4 = 0.0, de = 0.0;
+            double acc5 = 0.0, de = 0.0;
             for (int i = 0; i < 6; ++i) {
-                acc4 += B4[i] * k[i][j];
+                acc5 += B5[i] * k[i][j];
                 de += (B5[i] - B4[i]) * k[i][j];
             }
-            c[j] = c[j] + dt * acc4;
+            c[j] = c[j] + dt * acc5;
             e2 += (dt * de) * (dt * de);
         }
         if (err) err[s] = sqrt(e2);
