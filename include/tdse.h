@@ -180,10 +180,11 @@ tdse_status tdse_propagate_noalloc(tdse_plan plan, tdse_method method, int32_t t
  * Runge-Kutta-Fehlberg 4(5) propagation (the embedded pair of appendix B's
  * explicit Runge-Kutta family): six stages per step at t_k + c_i dt,
  * c = (0, 1/4, 3/8, 12/13, 1, 1/2), field [batch][nsteps][6] device samples
- * at those times; c advances with the fourth-order weights, and if err !=
+ * at those times; c advances with the fifth-order weights (the pair's
+ * fifth-order solution, which the paper propagates, Sec. 5.1), and if err !=
  * NULL, err[b][k] (device [batch][nsteps]) receives |dt sum_i (b5_i - b4_i)
- * k_i|_2, the estimate of step k's local error (for step-size control by the
- * caller). tdse_propagate with TDSE_RKF45 is this call with err = NULL.
+ * k_i|_2, the pair's embedded estimate of step k's local error (that of its
+ * fourth-order member; for step-size control by the caller). tdse_propagate with TDSE_RKF45 is this call with err = NULL.
  * Batch-1 plans run it on a batched twin of themselves. Errors: as
  * tdse_propagate; TDSE_E_NOMEM if the stage workspace (5 state vectors per
  * pulse, kept by the plan) cannot be allocated.
@@ -221,7 +222,7 @@ tdse_status tdse_propagate_adaptive(tdse_plan plan, double t_final, double dt0, 
  * axis): one step multiplies each eigencomponent of H(F) by R(-i dt lambda),
  * R the method's stability polynomial (the Taylor polynomial of degree 4 for
  * RK4 and of degree p for Taylor-p; 1 + sum_k b^T A^(k-1) 1 z^k for the
- * Fehlberg pair's fourth-order solution). With theta = dt (max|E| + |fmax|
+ * Fehlberg pair's fifth-order solution). With theta = dt (max|E| + |fmax|
  * ||D||), ||D|| bounded by the largest absolute row sum of the coupling
  * (computed at plan creation), returns TDSE_OK when |R(i s)|^2 <= 1 + 1e-14
  * for every |s| <= theta, else TDSE_E_UNSTABLE (tdse_last_error gives the

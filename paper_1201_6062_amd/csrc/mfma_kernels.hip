@@ -38,9 +38,10 @@ __device__ __forceinline__ double bat_xor1(double v) {
 }
 
 // Runge-Kutta-Fehlberg 4(5) tableau (stage times 0, 1/4, 3/8, 12/13, 1, 1/2):
-// stage inputs u_{i+1} = c + dt sum_{q<=i} A[i+1][q] k_q, fourth-order
-// weights B4 (the solution carried forward) and E = B5 - B4 (the error
-// estimate, B5 the fifth-order weights).
+// stage inputs u_{i+1} = c + dt sum_{q<=i} A[i+1][q] k_q, fifth-order
+// weights B5 (the solution carried forward: the paper propagates the pair's
+// fifth-order solution, Sec. 5.1) and E = B5 - B4 (the embedded error
+// estimate, B4 the fourth-order weights).
 __constant__ double RKF_A[6][5] = {
     {0, 0, 0, 0, 0},
     {1.0 / 4.0, 0, 0, 0, 0},
@@ -48,7 +49,7 @@ __constant__ double RKF_A[6][5] = {
     {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0, 0},
     {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0},
     {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0}};
-__constant__ double RKF_B4[6] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0, -1.0 / 5.0, 0.0};
+__constant__ double RKF_B5[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0, 2.0 / 55.0};
 __constant__ double RKF_E[6] = {16.0 / 135.0 - 25.0 / 216.0, 0.0, 6656.0 / 12825.0 - 1408.0 / 2565.0,
                                 28561.0 / 56430.0 - 2197.0 / 4104.0, -9.0 / 50.0 + 1.0 / 5.0, 2.0 / 55.0};
 
@@ -443,19 +444,19 @@ __global__ __launch_bounds__(256 * KS) __attribute__((amdgpu_waves_per_eu(1, 2))
                     }
                     case CK_RKF: {
                         // stage st: keep k_st, then the next stage input, or after
-                        // the sixth stage the fourth-order step and its error
+                        // the sixth stage the fifth-order step and its error estimate
                         double sacc = 0.0, serr = 0.0;
 #pragma unroll
                         for (int q = 0; q < 5; ++q)
                             if (q < st) {
-                                sacc = fma(st < 5 ? RKF_A[st + 1][q] : RKF_B4[q], kq[r][q], sacc);
+                                sacc = fma(st < 5 ? RKF_A[st + 1][q] : RKF_B5[q], kq[r][q], sacc);
                                 serr = fma(RKF_E[q], kq[r][q], serr);
                             }
                         if (st < 5) {
                             b.kst[(size_t)st * kstride + g] = k;
                             unext = fma(dt, fma(RKF_A[st + 1][st], k, sacc), c);
                         } else {
-                            c = fma(dt, fma(RKF_B4[5], k, sacc), c);
+                            c = fma(dt, fma(RKF_B5[5], k, sacc), c);
                             const double e = dt * fma(RKF_E[5], k, serr);
                             gsum[j] = fma(e, e, gsum[j]);
                             unext = c;
@@ -734,7 +735,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
                 for (int qq = 0; qq < 5; ++qq)
                     if (qq < st) {
-                        const double wgt = st < 5 ? RKF_A[st + 1][qq] : RKF_B4[qq];
+                        const double wgt = st < 5 ? RKF_A[st + 1][qq] : RKF_B5[qq];
                         sr = fma(wgt, kq[qq][0], sr);
                         si = fma(wgt, kq[qq][1], si);
                         er = fma(RKF_E[qq], kq[qq][0], er);
@@ -745,8 +746,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                     n_r = fma(dt, fma(RKF_A[st + 1][st], kr, sr), c_r);
                     n_i = fma(dt, fma(RKF_A[st + 1][st], ki, si), c_i);
                 } else {
-                    c_r = fma(dt, fma(RKF_B4[5], kr, sr), c_r);
-                    c_i = fma(dt, fma(RKF_B4[5], ki, si), c_i);
+                    c_r = fma(dt, fma(RKF_B5[5], kr, sr), c_r);
+                    c_i = fma(dt, fma(RKF_B5[5], ki, si), c_i);
                     const double xr = dt * fma(RKF_E[5], kr, er), xi = dt * fma(RKF_E[5], ki, ei);
                     gsum = fma(xr, xr, gsum);
                     gsum = fma(xi, xi, gsum);

@@ -7,8 +7,8 @@
 // method's stability polynomial: the degree-p Taylor polynomial of exp for
 // Taylor-p and for RK4 (p = 4: classic RK4 on a linear autonomous system is
 // Taylor-4), and 1 + sum_k gamma_k z^k with gamma_k = b^T A^{k-1} 1 for the
-// Runge-Kutta-Fehlberg pair (A its stage matrix, b the fourth-order weights
-// that advance the solution). The step is stable when |R(i theta)| <= 1 for
+// Runge-Kutta-Fehlberg pair (A its stage matrix, b the fifth-order weights
+// that advance the solution, as the paper's propagator does, Sec. 5.1). The step is stable when |R(i theta)| <= 1 for
 // every |theta| <= dt ||H||; ||H|| <= max|E| + |F| ||D|| and ||D||_2 <= the
 // largest absolute row sum of the symmetric coupling matrix.
 #pragma once
@@ -20,14 +20,14 @@
 namespace tdse {
 
 // Rounding allowance of the stability test: |R(i theta)|^2 <= 1 + STAB_TOL.
-// Taylor orders p = 1, 2 (mod 4) and the Fehlberg pair's fourth-order
+// Taylor orders p = 1, 2 (mod 4) and the Fehlberg pair's fifth-order
 // solution amplify for every theta > 0 (|R|^2 - 1 ~ theta^(p+1), theta^(p+2),
-// or theta^6 (1/52 - 1/72) for Fehlberg), so their interval is only as wide as
-// this allowance lets it be.
+// or theta^6 (1/360 - 1/1040) for Fehlberg, whose z^6 coefficient is 1/2080),
+// so their interval is only as wide as this allowance lets it be.
 constexpr double STAB_TOL = 1e-14;
 
 // Fehlberg's 4(5) pair: stage matrix (stage times 0, 1/4, 3/8, 12/13, 1, 1/2)
-// and the fourth-order weights.
+// and the fifth-order weights.
 constexpr double FEHLBERG_A[6][6] = {
     {0, 0, 0, 0, 0, 0},
     {1.0 / 4.0, 0, 0, 0, 0, 0},
@@ -35,7 +35,7 @@ constexpr double FEHLBERG_A[6][6] = {
     {1932.0 / 2197.0, -7200.0 / 2197.0, 7296.0 / 2197.0, 0, 0, 0},
     {439.0 / 216.0, -8.0, 3680.0 / 513.0, -845.0 / 4104.0, 0, 0},
     {-8.0 / 27.0, 2.0, -3544.0 / 2565.0, 1859.0 / 4104.0, -11.0 / 40.0, 0}};
-constexpr double FEHLBERG_B4[6] = {25.0 / 216.0, 0.0, 1408.0 / 2565.0, 2197.0 / 4104.0, -1.0 / 5.0, 0.0};
+constexpr double FEHLBERG_B5[6] = {16.0 / 135.0, 0.0, 6656.0 / 12825.0, 28561.0 / 56430.0, -9.0 / 50.0, 2.0 / 55.0};
 
 // Coefficients r[0..deg] of the method's stability polynomial; returns deg
 // (0 for methods without one: the Lanczos propagator is unitary).
@@ -51,7 +51,7 @@ inline int stability_poly(int method, int order, double *r /* [33] */) {
         r[0] = 1.0;
         for (int k = 1; k <= 6; ++k) {
             double g = 0.0;
-            for (int i = 0; i < 6; ++i) g += FEHLBERG_B4[i] * v[i];
+            for (int i = 0; i < 6; ++i) g += FEHLBERG_B5[i] * v[i];
             r[k] = g;
             double w[6];
             for (int i = 0; i < 6; ++i) {

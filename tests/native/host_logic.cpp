@@ -98,7 +98,7 @@ int main() {
     CHECK(validate_propagate(true, 0, 0, 0.1, 5, true, 1, &why) == TDSE_OK);
     // Stability polynomials against the step maps themselves: one step of
     // dy/dt = -i lam y run stage by stage (RK4 tableau; Fehlberg's tableau with
-    // its fourth-order weights; the Taylor recursion) equals R(-i dt lam).
+    // its fifth-order weights; the Taylor recursion) equals R(-i dt lam).
     {
         typedef std::complex<double> cd;
         for (double th : {0.1, 0.7, 1.9, 2.5, 3.1}) {
@@ -119,7 +119,7 @@ int main() {
                 deg = stability_poly(TDSE_TAYLOR, p, r);
                 CHECK(fabs(std::norm(acc) - amplification2(r, deg, th)) < 1e-12);
             }
-            // Fehlberg, fourth-order solution
+            // Fehlberg, fifth-order solution
             cd k[6];
             for (int i = 0; i < 6; ++i) {
                 cd u = 1.0;
@@ -127,24 +127,26 @@ int main() {
                 k[i] = z * u;
             }
             cd yf = 1.0;
-            for (int i = 0; i < 6; ++i) yf += FEHLBERG_B4[i] * k[i];
+            for (int i = 0; i < 6; ++i) yf += FEHLBERG_B5[i] * k[i];
             deg = stability_poly(TDSE_RKF45, 0, r);
             CHECK(fabs(std::norm(yf) - amplification2(r, deg, th)) < 1e-13);
         }
         double r[33];
         stability_poly(TDSE_RKF45, 0, r);
-        // fourth order: the exponential's coefficients up to z^4
+        // fifth order: the exponential's coefficients up to z^5
         CHECK(fabs(r[1] - 1.0) < 1e-15 && fabs(r[2] - 0.5) < 1e-15 && fabs(r[3] - 1.0 / 6.0) < 1e-15 &&
-              fabs(r[4] - 1.0 / 24.0) < 1e-15);
+              fabs(r[4] - 1.0 / 24.0) < 1e-15 && fabs(r[5] - 1.0 / 120.0) < 1e-15);
         // bounds: classic values on the imaginary axis
         CHECK(fabs(stability_bound(TDSE_RK4, 0) - 2.0 * sqrt(2.0)) < 1e-6);
         CHECK(fabs(stability_bound(TDSE_TAYLOR, 4) - 2.0 * sqrt(2.0)) < 1e-6);
         CHECK(fabs(stability_bound(TDSE_TAYLOR, 3) - sqrt(3.0)) < 1e-6);
         CHECK(stability_bound(TDSE_TAYLOR, 1) < 2e-7);  // explicit Euler amplifies at once
         CHECK(stability_bound(TDSE_TAYLOR, 8) > stability_bound(TDSE_RK4, 0));
-        // Fehlberg's fourth-order solution: |R|^2 - 1 = theta^6 (1/52 - 1/72) + ...
-        CHECK(fabs(r[5] - 1.0 / 104.0) < 1e-15 && fabs(r[6]) < 1e-15);
-        CHECK(fabs(stability_bound(TDSE_RKF45, 0) - pow(1e-14 / (1.0 / 52 - 1.0 / 72), 1.0 / 6)) < 1e-4);
+        // Fehlberg's fifth-order solution: z^6 coefficient 1/2080, so
+        // |R|^2 - 1 = theta^6 (1/360 - 1/1040) + ... (1/360 from the degree-5
+        // Taylor part)
+        CHECK(fabs(r[6] - 1.0 / 2080.0) < 1e-15);
+        CHECK(fabs(stability_bound(TDSE_RKF45, 0) - pow(1e-14 / (1.0 / 360 - 1.0 / 1040), 1.0 / 6)) < 1e-4);
         for (int p = 1; p <= 16; ++p)
             CHECK(has_stability_interval(TDSE_TAYLOR, p) == (p % 4 == 0 || p % 4 == 3));
         CHECK(has_stability_interval(TDSE_RK4, 0) && !has_stability_interval(TDSE_RKF45, 0));
