@@ -276,8 +276,13 @@ tdse_status tdse_adjoint(tdse_plan plan, tdse_method method, int32_t taylor_orde
  * graph. Instances are ordered by step count, so the ones still running form
  * a prefix of both lists.
  * tdse_group_create: plans[count] (host array), the group keeps references
- * (the plans must outlive the group). Errors: TDSE_E_INVAL (a plan with
- * batch != 1, plans on different devices), TDSE_E_UNSUPPORTED (n > 1024).
+ * (the plans must outlive the group). Every member streams its blocks at the
+ * default tile count ceil(n / 128): for a plan built with another count (a
+ * tuned or forced one) the group makes and owns a copy of its blocks at the
+ * default count (lmax * ceil(n/128)^2 * 128 KB of device memory; created on
+ * `stream`, synchronised). Errors: TDSE_E_INVAL (a plan with batch != 1,
+ * plans on different devices), TDSE_E_UNSUPPORTED (n > 1024), TDSE_E_NOMEM
+ * (such a copy could not be allocated).
  * tdse_group_propagate: RK4 only (TDSE_E_UNSUPPORTED otherwise); nsteps[count]
  * (host), fields, c0, cT: host arrays of `count` device pointers laid out as
  * in tdse_propagate. Instance i runs its own nsteps[i] steps; instances that

@@ -1249,6 +1249,9 @@ tdse_status tdse_propagate_adaptive(tdse_plan p, double t_final, double dt0, dou
     return TDSE_OK;
 }
 
+// Tile count a group member streams with: the default ceil(n / 128).
+static int group_tiles(int n) { return (n + VEC_TILE_MAX - 1) / VEC_TILE_MAX; }
+
 // Captured group chunks hold the work-list addresses: drop them before the
 // lists move.
 static void drop_group_graphs(tdse_group g) {
@@ -1270,15 +1273,50 @@ tdse_status tdse_group_create(tdse_group *out, int32_t count, const tdse_plan *p
         const tdse_plan p = plans[k];
         if (!p) return fail(TDSE_E_INVAL, "plans[" + std::to_string(k) + "] is NULL");
         if (p->batch != 1) return fail(TDSE_E_INVAL, "group members must be batch-1 plans");
-        if (p->T > 8)
-            return fail(TDSE_E_UNSUPPORTED, "group members need at most 8 tiles per block dimension (n <= 1024 at "
-                                            "the default tile count; plans[" + std::to_string(k) + "] has " +
-                                                std::to_string(p->T) + ")");
+        if (group_tiles(p->n) > 8)
+            return fail(TDSE_E_UNSUPPORTED, "group members need n <= 1024 (plans[" + std::to_string(k) +
+                                                "] has n = " + std::to_string(p->n) + ")");
         if (p->device != plans[0]->device) return fail(TDSE_E_INVAL, "group members must share one device");
     }
     tdse_group g = new (std::nothrow) tdse_group_s();
     if (!g) return fail(TDSE_E_NOMEM, "host allocation failed");
     g->plans.assign(plans, plans + count);
+    g->retiled.assign(count, nullptr);
+    // A member built with more tiles than the default (a tuned or forced
+    // count) streams a copy of its blocks at the default count: inside a group
+    // every CU already has work, so the extra workgroups smaller tiles buy a
+    // lone plan do not help, while each of its patches streams fewer bytes
+    // per workgroup (measured: a group on the lone-tuned counts ran at 0.98x).
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    double *rowmajor = nullptr;
+    size_t row_cap = 0;
+    hipError_t e = hipSuccess;
+    for (int32_t k = 0; k < count && e == hipSuccess; ++k) {
+        const tdse_plan p = plans[k];
+        const int t0 = group_tiles(p->n);
+        if (p->lmax == 0 || p->T == t0) continue;
+        const size_t dense = (size_t)p->lmax * p->n * p->n;
+        if (dense > row_cap) {
+            if (rowmajor) (void)hipFree(rowmajor);
+            rowmajor = nullptr;
+            row_cap = 0;
+            if ((e = hipMalloc(&rowmajor, dense * sizeof(double))) != hipSuccess) break;
+            row_cap = dense;
+        }
+        const size_t tiled = (size_t)p->lmax * t0 * t0 * VEC_TILE_MAX * VEC_TILE_MAX;
+        if ((e = hipMalloc(&g->retiled[k], tiled * sizeof(double))) != hipSuccess) break;
+        e = vec_untile(p->dip, rowmajor, p->lmax, p->n, p->T, s);
+        if (e == hipSuccess) e = vec_layout(rowmajor, g->retiled[k], p->lmax, p->n, t0, s);
+        // the next member reuses the row-major buffer
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    if (rowmajor) (void)hipFree(rowmajor);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        tdse_group_destroy(g);
+        return e == hipErrorOutOfMemory ? fail(TDSE_E_NOMEM, "hipMalloc of a re-tiled group member failed")
+                                        : hip_fail(e, "re-tiling of a group member");
+    }
     *out = g;
     return TDSE_OK;
 }
@@ -1321,15 +1359,22 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
         const tdse_plan p = g->plans[order_idx[q]];
         GroupInst gi{};
         gi.b = p->vb;
+        if (g->retiled[order_idx[q]]) {
+            // the default tile count over the plan's own state and partial
+            // buffers (sized for its larger count)
+            gi.b.dip = g->retiled[order_idx[q]];
+            gi.b.T = group_tiles(p->n);
+        }
         gi.field = fields[order_idx[q]];
         gi.nsteps = nsteps[order_idx[q]];
         g->insts.push_back(gi);
-        const int npd = patch_np(p->T);  // patches per block dimension
+        const int T = gi.b.T;
+        const int npd = patch_np(T);  // patches per block dimension
         for (int l = 0; l < p->lmax; ++l)
             for (int i = 0; i < npd; ++i)
                 for (int j = 0; j < npd; ++j) g->tiles.push_back({(int32_t)q, (int16_t)l, (int8_t)i, (int8_t)j});
         for (int mm = 0; mm <= p->lmax; ++mm)
-            for (int qq = 0; qq < p->T; ++qq) g->segs.push_back({(int32_t)q, (int16_t)mm, (int16_t)qq});
+            for (int qq = 0; qq < T; ++qq) g->segs.push_back({(int32_t)q, (int16_t)mm, (int16_t)qq});
         prefix.push_back((int64_t)g->tiles.size());
         seg_prefix.push_back((int64_t)g->segs.size());
     }
@@ -1377,7 +1422,8 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
         (void)hipGetLastError();
         return fail(TDSE_E_NOMEM, "hipMalloc of the group descriptor failed");
     }
-    for (int k : order_idx) TDSE_HIP(vec_launch_start(g->plans[k]->vb, 0, c0[k], TDSE_RK4, s));
+    for (size_t q = 0; q < order_idx.size(); ++q)
+        TDSE_HIP(vec_launch_start(g->insts[q].b, 0, c0[order_idx[q]], TDSE_RK4, s));
     // Rounds go in chunks of GROUP_CHUNK_ROUNDS; a chunk's launches cover the
     // instances active at its first round (the kernels skip instances that
     // finish inside the chunk). Whole chunks replay a captured graph.
@@ -1418,27 +1464,29 @@ tdse_status tdse_group_propagate(tdse_group g, tdse_method method, int32_t order
                 TDSE_HIP(group_launch_round(g->d_segs, ns, g->d_tiles, nt, g->d_insts, g->d_desc, off, s));
         }
     }
-    // final completion of every instance (c(T) -> cT)
-    for (int k : order_idx) {
-        tdse_plan p = g->plans[k];
+    // final completion of every instance (c(T) -> cT), over the partials of
+    // the group's rounds (the instance table's tile count)
+    for (size_t q = 0; q < order_idx.size(); ++q) {
+        const int k = order_idx[q];
+        const VecBuffers &vb = g->insts[q].b;
         CallDesc d{};
         d.nsteps = nsteps[k];
         d.field = fields[k];
         d.ckpt_every = 1;
         d.dt = dt;
         d.slots = 3;
-        TDSE_HIP(set_desc(p->vb.desc, d, s));
+        TDSE_HIP(set_desc(vb.desc, d, s));
         const int64_t base = nsteps[k] > 0 ? ((nsteps[k] - 1) / CHUNK_STEPS) * CHUNK_STEPS : 0;
-        TDSE_HIP(chunk_begin(p->vb.desc, base, s));
+        TDSE_HIP(chunk_begin(vb.desc, base, s));
         VecLaunch L{};
         L.comp = final_completion(TDSE_RK4, 4);
         L.off = (int32_t)(nsteps[k] - base);
         L.parity = 0;
         L.finish = 1;
         L.slots = 3;
-        L.np = patch_np(p->T);  // the group's products rounds are patch launches
+        L.np = patch_np(vb.T);  // the group's products rounds are patch launches
         L.out = cT[k];
-        TDSE_HIP(vec_launch_combine(p->vb, L, s));
+        TDSE_HIP(vec_launch_combine(vb, L, s));
     }
     return TDSE_OK;
 }
@@ -1452,6 +1500,8 @@ tdse_status tdse_group_destroy(tdse_group g) {
     if (g->d_segs) (void)hipFree(g->d_segs);
     if (g->d_insts) (void)hipFree(g->d_insts);
     if (g->d_desc) (void)hipFree(g->d_desc);
+    for (double *r : g->retiled)
+        if (r) (void)hipFree(r);
     delete g;
     return TDSE_OK;
 }

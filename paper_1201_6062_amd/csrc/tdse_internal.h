@@ -265,6 +265,9 @@ tdse_status create_plan(tdse_plan *out, const double *energies, const double *di
 // ---------------------------------------------------------------------------
 struct tdse_group_s {
     std::vector<tdse_plan> plans;
+    // per member: its blocks tiled at the default tile count, owned by the
+    // group, where the plan itself was built with another count (else null)
+    std::vector<double *> retiled;
     // work list and instance table of the last call (host copies stay alive
     // until the next call, so the asynchronous uploads can read them)
     std::vector<tdse::GroupTile> tiles;

@@ -17,6 +17,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <string>
 #include <vector>
@@ -141,25 +142,51 @@ static void synth(int lmax, int n, std::vector<double> &en, std::vector<double> 
     for (auto &d : dip) d = 0.02 * (u01() - 0.5);
 }
 
+// The kernels a plan built with a choice runs: candidates that resolve to the
+// same kernels (a tuned shape equal to the library's own pick) are timed once.
+static std::string resolved(const tdse_plan_s *p) {
+    char buf[96];
+    if (p->batch == 1)
+        snprintf(buf, sizeof buf, "T%d_s%d_x%d", p->T, (int)p->small, (int)p->split);
+    else
+        snprintf(buf, sizeof buf, "%dx%dx%dx%d", p->bb.tm, p->bb.tn, p->bb.kc, p->bb.ks);
+    return buf;
+}
+
+// Builds a plan with choice tc and, unless its kernels are already in `seen`,
+// times the fastest of TUNE_REPS propagations of nsteps steps after an
+// untimed one (graph capture, first touches). *us_per_step < 0: skipped.
+constexpr int TUNE_REPS = 2;
 static tdse_status time_choice(int lmax, int n, int batch, const TileChoice &tc, const double *den,
                                const double *ddip, const double *dfield, double *dc0, double *dcT,
-                               int64_t nsteps, hipStream_t s, double *us_per_step) {
+                               int64_t nsteps, hipStream_t s, std::vector<std::string> *seen,
+                               double *us_per_step) {
+    *us_per_step = -1.0;
     tdse_plan p = nullptr;
     tdse_status st = create_plan(&p, den, ddip, TDSE_LENGTH, lmax, n, batch, s, &tc);
     if (st != TDSE_OK) return st;
+    const std::string key = resolved(p);
+    for (const std::string &k : *seen)
+        if (k == key) {
+            tdse_destroy(p);
+            return TDSE_OK;
+        }
+    seen->push_back(key);
     hipEvent_t e0, e1;
     TDSE_HIP(hipEventCreate(&e0));
     TDSE_HIP(hipEventCreate(&e1));
     st = tdse_propagate(p, TDSE_RK4, 0, 1e-3, nsteps, dfield, dc0, dcT, nullptr, 0, s);
-    if (st == TDSE_OK) {
+    double best = 1e300;
+    for (int r = 0; r < TUNE_REPS && st == TDSE_OK; ++r) {
         (void)hipEventRecord(e0, s);
         st = tdse_propagate(p, TDSE_RK4, 0, 1e-3, nsteps, dfield, dc0, dcT, nullptr, 0, s);
         (void)hipEventRecord(e1, s);
         (void)hipEventSynchronize(e1);
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        *us_per_step = ms * 1e3 / (double)nsteps;
+        best = std::min(best, ms * 1e3 / (double)nsteps);
     }
+    if (st == TDSE_OK) *us_per_step = best;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     tdse_destroy(p);
@@ -201,10 +228,10 @@ extern "C" tdse_status tdse_tune(int32_t lmax, int32_t n, int32_t batch, const c
     constexpr double TUNE_MARGIN = 0.03;
     std::vector<TileChoice> cands{{0, 0, 0, 0, 0}};
     if (batch == 1) {
-        // tile counts T0 .. T0 + 3, at most 8 where T0 allows it (plans of
-        // more than 8 tiles per block dimension cannot join an uneven group)
-        const int t0 = (n + VEC_TILE_MAX - 1) / VEC_TILE_MAX, tmax = t0 <= 8 ? 8 : 16;
-        for (int T = t0; T <= t0 + 3 && T <= tmax && T <= (n + 15) / 16; ++T) cands.push_back({T, 0, 0, 0, 0});
+        // tile counts T0 .. T0 + 3 (at most 16, segments of whole 16-row
+        // units); uneven groups stream every member at T0 whatever its plan's
+        const int t0 = (n + VEC_TILE_MAX - 1) / VEC_TILE_MAX;
+        for (int T = t0; T <= t0 + 3 && T <= 16 && T <= (n + 15) / 16; ++T) cands.push_back({T, 0, 0, 0, 0});
     } else {
         // the LDS kernels' 11 tile shapes with one K group, the two shapes
         // compiled with two K groups, and for 2B <= 64 the small-batch kernel
@@ -219,11 +246,13 @@ extern "C" tdse_status tdse_tune(int32_t lmax, int32_t n, int32_t batch, const c
     }
     CacheEntry best{{0, 0, 0, 0, 0}, 1e300};
     double default_us = 1e300;
+    std::vector<std::string> seen;
     for (size_t c = 0; c < cands.size(); ++c) {
         const TileChoice &tc = cands[c];
         if (st != TDSE_OK) break;
         double us = 0.0;
-        tdse_status r = time_choice(lmax, n, batch, tc, den, ddip, dfield, dc0, dcT, nsteps, s, &us);
+        tdse_status r = time_choice(lmax, n, batch, tc, den, ddip, dfield, dc0, dcT, nsteps, s, &seen, &us);
+        if (r == TDSE_OK && us < 0.0) continue;  // the same kernels as a candidate already timed
         if (r == TDSE_OK && c == 0) default_us = us;
         if (r == TDSE_OK && us < best.us) best = {tc, us};
         if (r == TDSE_E_HIP) st = r;

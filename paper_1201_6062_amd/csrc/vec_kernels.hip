@@ -1063,7 +1063,7 @@ __global__ __launch_bounds__(VEC_TILE_MAX) void vec_group_combine_kernel(const G
     const double F = (step >= 0 && step < gi.nsteps) ? gi.field[step * 3 + L.comp.slot] : 0.0;
     const size_t g = (size_t)gs.m * b.n + seg_start(b.n, b.T, gs.q) + e;
     const int par = L.parity;
-    // partials of the patch products launch (group plans have T <= 8: at most two per segment)
+    // partials of the patch products launch (groups stream at T <= 8: at most two per segment)
     const int np = patch_np(b.T);
     const double2 z = couple(b.gauge, sum_partials<2>(b, b.T, np, par, true, gs.m, gs.q, e),
                              sum_partials<2>(b, b.T, np, par, false, gs.m, gs.q, e));

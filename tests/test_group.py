@@ -57,6 +57,33 @@ def test_group_equals_single_instance_runs(monkeypatch):
         assert torch.equal(alone.reshape(-1), o)
 
 
+def test_group_members_on_other_tile_counts(monkeypatch):
+    """Members built with forced tile counts above the default (up to 11, past
+    the 8 a group streams with) join a group, which streams each at its
+    default count: bitwise equal to the same group of default plans, and
+    within the tolerance of the oracle."""
+    from paper_1201_6062_amd.api import Group
+    shapes = [(3, 300, 5), (2, 500, 7), (4, 257, 9), (1, 1000, 11), (2, 130, 0)]
+    hs = [wl.hamiltonian(l, n, 300 + q) for q, (l, n, _) in enumerate(shapes)]
+    fs = [wl.rk4_samples(wl.Pulse(0.08, 0.5, 2.0), 0.01, 40 + 7 * q) for q in range(len(shapes))]
+    cs = [wl.random_state(np.random.default_rng(50 + q), h.nstates)[0] for q, h in enumerate(hs)]
+    forced = []
+    for h, (_, _, t) in zip(hs, shapes):
+        if t:
+            monkeypatch.setenv("TDSE_TILE", f"T={t}")
+        else:
+            monkeypatch.delenv("TDSE_TILE", raising=False)
+        forced.append(plan_of(h))
+    monkeypatch.delenv("TDSE_TILE", raising=False)
+    default = [plan_of(h) for h in hs]
+    out_f = Group(forced).propagate(fs, cs, 0.01)
+    out_d = Group(default).propagate(fs, cs, 0.01)
+    for q, (h, f, c) in enumerate(zip(hs, fs, cs)):
+        assert torch.equal(out_f[q], out_d[q]), shapes[q]
+        ref = oracle.rk4(h.energies, h.dipole, 0.01, f[None], c[None], n=h.n)[0]
+        assert rel_l2(out_f[q].cpu().numpy(), ref) <= TOL, shapes[q]
+
+
 def test_group_full_length_sampled_instances():
     """Instances 16, 21, 39 of the 64-instance workload, whole pulses, vs stored oracle results."""
     from paper_1201_6062_amd.api import Group
