@@ -553,10 +553,16 @@ struct PatchTile {
     int ra, rb;
 };
 
-__device__ __forceinline__ PatchTile patch_tile(const PatchArgs &A, int l, int ti0, int tj0, int PI, int ii, int jj) {
+// Tile row / column of the patch that the stream visits at position x of n:
+// in order, or (rev) from the last one back.
+__device__ __forceinline__ int patch_pos(int x, int n, int rev) { return rev ? n - 1 - x : x; }
+
+// The tile visited at stream position (ii, jj) (ii == PI: past the last one).
+__device__ __forceinline__ PatchTile patch_tile(const PatchArgs &A, int l, int ti0, int tj0, int PI, int PJ, int rev,
+                                                int ii, int jj) {
     const int T = A.T;
     const bool live = ii < PI;
-    const int i = ti0 + (live ? ii : 0), j = tj0 + jj;
+    const int i = ti0 + (live ? patch_pos(ii, PI, rev) : 0), j = tj0 + patch_pos(jj, PJ, rev);
     int r0, ra, c0, rb;
     segment_of(A.n, T, i, &r0, &ra);
     segment_of(A.n, T, j, &c0, &rb);
@@ -595,8 +601,13 @@ __device__ __forceinline__ void lds_st2(char *p, double2 v) { *reinterpret_cast<
 
 // Patch (pr, pc) of block l: reads the inputs A.u, writes the partials in
 // the np-per-segment layout. LOOK (even, 8 .. 14): loads in flight per wave.
+// rev: visit the patch's tiles from the last back to the first. Launches
+// alternate the direction, so each starts on the tiles the one before it
+// streamed last, part of which the GPU's memory-side cache (MALL) still holds:
+// a products launch over 504 MB of tiles takes about 8% less time than with
+// one direction throughout.
 template <int LOOK>
-__device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, int pr, int pc) {
+__device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, int pr, int pc, int rev) {
     static_assert(LOOK % 2 == 0 && LOOK >= 4 && LOOK <= PATCH_RING - 2, "a slot is refilled only after its data was used");
     __shared__ PatchLds lds;
     const int t = threadIdx.x, lane = t & 63;
@@ -632,7 +643,7 @@ __device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, in
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 
     // ---- the stream: loads 0 .. LOOK-1 of the first tile
-    PatchTile cur = patch_tile(A, l, ti0, tj0, PI, 0, 0);
+    PatchTile cur = patch_tile(A, l, ti0, tj0, PI, PJ, rev, 0, 0);
 #pragma unroll
     for (int r = 0; r < LOOK; ++r) patch_issue(cur, r, ring, lane_off, cb);
     lds_st2(uab + t * 16, ua_in);  // uA[t / 128][t % 128]
@@ -658,9 +669,10 @@ __device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, in
 #pragma unroll
     for (int ii = 0; ii < PATCH_MAX; ++ii) {
         if (ii >= PI) break;
+        const int ai = patch_pos(ii, PI, rev);  // tile row of the patch
         double2 ua[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) ua[k] = lds_ld2(uab + (ii * VEC_TILE_MAX + qq + 16 * k) * 16);
+        for (int k = 0; k < 8; ++k) ua[k] = lds_ld2(uab + (ai * VEC_TILE_MAX + qq + 16 * k) * 16);
         double tr[8], ti[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) tr[k] = ti[k] = 0.0;
@@ -668,10 +680,12 @@ __device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, in
         for (int jj = 0; jj < PATCH_MAX; ++jj) {
             if (jj < PJ) {
                 const bool row_end = jj + 1 >= PJ;
-                const PatchTile nxt = patch_tile(A, l, ti0, tj0, PI, row_end ? ii + 1 : ii, row_end ? 0 : jj + 1);
+                const PatchTile nxt =
+                    patch_tile(A, l, ti0, tj0, PI, PJ, rev, row_end ? ii + 1 : ii, row_end ? 0 : jj + 1);
+                const int aj = patch_pos(jj, PJ, rev);  // tile column of the patch
                 double2 ub[4];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) ub[c] = lds_ld2(ubb + (jj * VEC_TILE_MAX + cb + c) * 16);
+                for (int c = 0; c < 4; ++c) ub[c] = lds_ld2(ubb + (aj * VEC_TILE_MAX + cb + c) * 16);
 #pragma unroll
                 for (int kk = 0; kk < 8; ++kk) {
                     // keep LOOK loads ahead: this tile's loads up to 15, then the next tile's
@@ -721,12 +735,15 @@ __device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, in
     // ring is free once all waves are here
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     patch_barrier();
-    // row partials: the 8 waves' sums of each row, in a fixed order
+    // row partials: the 8 waves' sums of each row, in a fixed order (rows[x]
+    // holds the tile row visited x-th; past PI, zeros into unused space)
 #pragma unroll
-    for (int x = 0; x < PATCH_MAX; ++x)
+    for (int x = 0; x < PATCH_MAX; ++x) {
+        const int ax = x < PI ? patch_pos(x, PI, rev) : x;
 #pragma unroll
         for (int k = 0; k < 2; ++k)
-            lds_st2(ring0 + ((x * (VEC_THREADS / 64) + wv) * VEC_TILE_MAX + qq + 16 * (k + rcls)) * 16, rows[x][k]);
+            lds_st2(ring0 + ((ax * (VEC_THREADS / 64) + wv) * VEC_TILE_MAX + qq + 16 * (k + rcls)) * 16, rows[x][k]);
+    }
     patch_barrier();
     {
         const int x = t >> 7, a = t & (VEC_TILE_MAX - 1);
@@ -763,11 +780,12 @@ __device__ __forceinline__ void patch_body(const PatchArgs &A, int np, int l, in
         }
     }
     {
-        const int jj = qq >> 2, cc = cb + (qq & 3);
+        const int jj = qq >> 2, cc = cb + (qq & 3);  // jj: the tile column visited jj-th
+        const int aj = jj < PJ ? patch_pos(jj, PJ, rev) : 0;
         int c0, rb;
-        segment_of(n, T, tj0 + (jj < PJ ? jj : 0), &c0, &rb);
+        segment_of(n, T, tj0 + aj, &c0, &rb);
         if (jj < PJ && cc < rb)
-            st_global(A.colp + ((size_t)(l * T + tj0 + jj) * np + pr) * VEC_TILE_MAX + cc, make_double2(v[0], v[1]));
+            st_global(A.colp + ((size_t)(l * T + tj0 + aj) * np + pr) * VEC_TILE_MAX + cc, make_double2(v[0], v[1]));
     }
 }
 
@@ -778,7 +796,7 @@ __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 
     const int np = patch_np(b.T);
     const int w = blockIdx.x, per = np * np;
     const int l = w / per, rem = w - l * per;
-    patch_body<LOOK>(patch_args(b, L.parity), np, l, rem / np, rem - (rem / np) * np);
+    patch_body<LOOK>(patch_args(b, L.parity), np, l, rem / np, rem - (rem / np) * np, L.parity);
 }
 
 // Products launch of the next Krylov vector with the recurrence's update
@@ -1081,7 +1099,7 @@ __global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(2, 
     const int64_t round = desc->base_round + off;
     if (round >= 4 * gi.nsteps) return;
     const PatchArgs A = patch_args(gi.b, (int)(round & 1));
-    patch_body<LOOK>(A, patch_np(A.T), gt.l, gt.i, gt.j);
+    patch_body<LOOK>(A, patch_np(A.T), gt.l, gt.i, gt.j, (int)(round & 1));
 }
 
 __global__ void group_desc_kernel(GroupDesc *desc, int64_t base_round, double dt) {
