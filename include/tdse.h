@@ -281,8 +281,8 @@ tdse_status tdse_adjoint(tdse_plan plan, tdse_method method, int32_t taylor_orde
  * tuned or forced one) the group makes and owns a copy of its blocks at the
  * default count (lmax * ceil(n/128)^2 * 128 KB of device memory; created on
  * `stream`, synchronised). Errors: TDSE_E_INVAL (a plan with batch != 1,
- * plans on different devices), TDSE_E_UNSUPPORTED (n > 1024), TDSE_E_NOMEM
- * (such a copy could not be allocated).
+ * plans on different devices, one plan given twice), TDSE_E_UNSUPPORTED
+ * (n > 1024), TDSE_E_NOMEM (such a copy could not be allocated).
  * tdse_group_propagate: RK4 only (TDSE_E_UNSUPPORTED otherwise); nsteps[count]
  * (host), fields, c0, cT: host arrays of `count` device pointers laid out as
  * in tdse_propagate. Instance i runs its own nsteps[i] steps; instances that

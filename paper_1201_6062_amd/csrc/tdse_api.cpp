@@ -1277,6 +1277,10 @@ tdse_status tdse_group_create(tdse_group *out, int32_t count, const tdse_plan *p
             return fail(TDSE_E_UNSUPPORTED, "group members need n <= 1024 (plans[" + std::to_string(k) +
                                                 "] has n = " + std::to_string(p->n) + ")");
         if (p->device != plans[0]->device) return fail(TDSE_E_INVAL, "group members must share one device");
+        for (int32_t m = 0; m < k; ++m)
+            if (plans[m] == p)  // one plan's state buffers cannot hold two instances
+                return fail(TDSE_E_INVAL, "plans[" + std::to_string(m) + "] and plans[" + std::to_string(k) +
+                                              "] are the same plan");
     }
     tdse_group g = new (std::nothrow) tdse_group_s();
     if (!g) return fail(TDSE_E_NOMEM, "host allocation failed");

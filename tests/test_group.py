@@ -84,6 +84,14 @@ def test_group_members_on_other_tile_counts(monkeypatch):
         assert rel_l2(out_f[q].cpu().numpy(), ref) <= TOL, shapes[q]
 
 
+def test_group_rejects_a_plan_given_twice():
+    from paper_1201_6062_amd.api import Group
+    h = wl.hamiltonian(2, 70, 1)
+    p = plan_of(h)
+    with pytest.raises(Exception, match="same plan"):
+        Group([p, plan_of(h), p])
+
+
 def test_group_full_length_sampled_instances():
     """Instances 16, 21, 39 of the 64-instance workload, whole pulses, vs stored oracle results."""
     from paper_1201_6062_amd.api import Group
