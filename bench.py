@@ -563,6 +563,41 @@ def tuned_measure(torch, group_steps: int = 400):
     return out
 
 
+def library_references(torch, reps: int = 20):
+    """What vendor library code reaches on this GPU, beside the kernels' own
+    fractions: an FP64 batched GEMM of the batched stage's shape (16 blocks,
+    512 x 1024 by 1024 x 512: the products of one RK4 stage at 256 pulses,
+    without the epilogue) through torch.bmm (rocBLAS / hipBLASLt), and a 1 GiB
+    device-to-device copy (bytes read + written)."""
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+    g = torch.Generator(device="cuda").manual_seed(0)
+    a = torch.randn(16, 512, 1024, dtype=torch.float64, device="cuda", generator=g)
+    b = torch.randn(16, 1024, 512, dtype=torch.float64, device="cuda", generator=g).contiguous()
+    c = torch.empty(16, 512, 512, dtype=torch.float64, device="cuda")
+    s = timed(lambda: torch.bmm(a, b, out=c))
+    tf = 2.0 * 16 * 512 * 512 * 1024 / s / 1e12
+    del a, b, c
+    x = torch.ones((1 << 30) // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    s = timed(lambda: y.copy_(x))
+    tbs = 2.0 * x.numel() * 8 / s / 1e12
+    del x, y
+    return {"fp64_bmm": {"what": "torch.bmm FP64, 16 x (512x1024 @ 1024x512)", "tflops": tf,
+                         "frac_of_fp64_peak": tf / FP64_PEAK_TFLOPS},
+            "device_copy": {"what": "1 GiB FP64 tensor copy_ (read + write)", "TBps": tbs,
+                            "frac_of_hbm_peak": tbs * 1e3 / HBM_PEAK_GBS}}
+
+
 def calibrate_copy(torch, mb: int = 1024, reps: int = 5):
     """Plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
     x = torch.ones(mb * (1 << 20) // 8, dtype=torch.float64, device="cuda")
@@ -584,7 +619,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the small-problem and group measurements")
     ap.add_argument("--only", choices=["single", "diag", "batched", "small", "small_tiles", "group", "taylor8",
                                        "lanczos", "lanczos_b8", "lsweep", "adjoint", "adjoint_taylor8", "rkf45",
-                                       "velocity", "tuned"],
+                                       "velocity", "tuned", "refs"],
                     default=None,
                     help="profiling runs: measure one workload and print its record alone")
     ap.add_argument("--tile", default=None, help="batched tile TMxTN (tuning experiments)")
@@ -635,7 +670,8 @@ def main():
             "adjoint_taylor8": lambda: adjoint_measure(torch, steps=a.truncate or 512, method="taylor", order=8),
             "rkf45": lambda: rkf45_measure(torch, steps=a.truncate or 50),
             "velocity": lambda: velocity_measure(torch),
-            "tuned": lambda: tuned_measure(torch)}
+            "tuned": lambda: tuned_measure(torch),
+            "refs": lambda: library_references(torch)}
     if a.only in only:
         print(json.dumps(only[a.only]()))
         return
@@ -710,6 +746,7 @@ def main():
                                          "frac": out["hbm_diagnostic"]["frac_of_hbm_peak"]}
     if not a.no_batched:
         out["batched"] = batched_measure(torch)
+        out["library_references"] = library_references(torch)
     if not a.no_extra:
         out["single_small"] = small_measure(torch)
         out["single_small_tiles"] = small_measure(torch, force_tiles=True)
