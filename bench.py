@@ -565,10 +565,10 @@ def tuned_measure(torch, group_steps: int = 400):
 
 def library_references(torch, reps: int = 20):
     """What vendor library code reaches on this GPU, beside the kernels' own
-    fractions: an FP64 batched GEMM of the batched stage's shape (16 blocks,
-    512 x 1024 by 1024 x 512: the products of one RK4 stage at 256 pulses,
-    without the epilogue) through torch.bmm (rocBLAS / hipBLASLt), and a 1 GiB
-    device-to-device copy (bytes read + written)."""
+    fractions: FP64 batched GEMMs of the batched stage's shape (16 blocks,
+    512 x 1024 by 1024 x 2B: the products of one RK4 stage without the
+    epilogue, at 256 and at 32 pulses) through torch.bmm (rocBLAS /
+    hipBLASLt), and a 1 GiB device-to-device copy (bytes read + written)."""
     def timed(fn):
         for _ in range(3):
             fn()
@@ -581,19 +581,23 @@ def library_references(torch, reps: int = 20):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3 / reps
     g = torch.Generator(device="cuda").manual_seed(0)
-    a = torch.randn(16, 512, 1024, dtype=torch.float64, device="cuda", generator=g)
-    b = torch.randn(16, 1024, 512, dtype=torch.float64, device="cuda", generator=g).contiguous()
-    c = torch.empty(16, 512, 512, dtype=torch.float64, device="cuda")
-    s = timed(lambda: torch.bmm(a, b, out=c))
-    tf = 2.0 * 16 * 512 * 512 * 1024 / s / 1e12
-    del a, b, c
+    gemm = {}
+    for cols in (512, 64):  # 256 pulses; 32 pulses (the adjoint workload)
+        a = torch.randn(16, 512, 1024, dtype=torch.float64, device="cuda", generator=g)
+        b = torch.randn(16, 1024, cols, dtype=torch.float64, device="cuda", generator=g).contiguous()
+        c = torch.empty(16, 512, cols, dtype=torch.float64, device="cuda")
+        s = timed(lambda: torch.bmm(a, b, out=c))
+        gemm[cols] = 2.0 * 16 * 512 * cols * 1024 / s / 1e12
+        del a, b, c
     x = torch.ones((1 << 30) // 8, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
     s = timed(lambda: y.copy_(x))
     tbs = 2.0 * x.numel() * 8 / s / 1e12
     del x, y
-    return {"fp64_bmm": {"what": "torch.bmm FP64, 16 x (512x1024 @ 1024x512)", "tflops": tf,
-                         "frac_of_fp64_peak": tf / FP64_PEAK_TFLOPS},
+    return {"fp64_bmm": {"what": "torch.bmm FP64, 16 x (512x1024 @ 1024x512)", "tflops": gemm[512],
+                         "frac_of_fp64_peak": gemm[512] / FP64_PEAK_TFLOPS},
+            "fp64_bmm_64_columns": {"what": "torch.bmm FP64, 16 x (512x1024 @ 1024x64)", "tflops": gemm[64],
+                                    "frac_of_fp64_peak": gemm[64] / FP64_PEAK_TFLOPS},
             "device_copy": {"what": "1 GiB FP64 tensor copy_ (read + write)", "TBps": tbs,
                             "frac_of_hbm_peak": tbs * 1e3 / HBM_PEAK_GBS}}
 
