@@ -727,7 +727,7 @@ def main():
                                              "divided by the product launches: start to start, so it includes "
                                              "the gaps between launches and the per-chunk staging kernels",
                      "limited_by": "launch latency, not HBM: the 30 MB dipole stays in the XCDs' L2 across "
-                                   "launches (3.75 MB per XCD of 4 MB); about 2.5 us of each launch is the "
+                                   "launches (3.75 MB per XCD of 4 MB); about 2.3 us of each launch is the "
                                    "kernel boundary. The HBM-streaming rates are in hbm_streaming",
                      "traffic_note": "FETCH_SIZE + WRITE_SIZE per dispatch under rocprofv3 --pmc, where "
                                      "dispatches run serialized and start with a cold L2: an upper bound of "

@@ -35,7 +35,10 @@ def sources():
 # Per-file code generation options. The matrix-core kernels keep their
 # accumulators in ordinary VGPRs (VGPR-form MFMA): with AGPR accumulators the
 # register allocator copied all of them out and back on every K chunk.
-FILE_FLAGS = {"mfma_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+FILE_FLAGS = {"mfma_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+              # the tile kernel's leading scalar arguments (14 dwords) go into
+              # scalar registers before the wave starts
+              "vec_kernels.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=8"]}
 
 
 def _compile(src: str) -> str:
