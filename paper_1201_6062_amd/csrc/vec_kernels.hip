@@ -1050,8 +1050,23 @@ __device__ __forceinline__ void lz_tile_body(const VecBuffers &b, const LzFused 
     }
 }
 
+// As the tile kernel, with the words its first loads need (the tile, the
+// read side's partials, x_{k-1}, x_{k-2}, lmax, n and k) as leading scalar
+// arguments, preloaded into scalar registers.
 template <int TP, int G>
-__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_lz_fused_kernel(VecBuffers b, LzFused z) {
+__global__ __launch_bounds__(VEC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void vec_lz_fused_kernel(
+    const double *dip, double2 *rowp, double2 *colp, const double *xprev, const double *xprev2, int32_t lmax,
+    int32_t n, int32_t k, VecBuffers bk, LzFused zk) {
+    VecBuffers b = bk;
+    b.dip = dip;
+    b.side[0].rowp = rowp;
+    b.side[0].colp = colp;
+    b.lmax = lmax;
+    b.n = n;
+    LzFused z = zk;
+    z.xprev = xprev;
+    z.xprev2 = xprev2;
+    z.k = k;
     const int T = TP <= 8 ? TP : b.T;
     const int ntiles = b.lmax * T * T;
     const int w = blockIdx.x;
@@ -1407,8 +1422,10 @@ hipError_t vec_launch_lz_products(const VecBuffers &b, const LzUpdate &z, hipStr
     TDSE_TP_DISPATCH(b.T, vec_lz_products_kernel, dim3(b.lmax * b.T * b.T), dim3(VEC_THREADS), 0, s, b, z);
     return hipGetLastError();
 }
+typedef void (*LzFusedKernel)(const double *, double2 *, double2 *, const double *, const double *, int32_t, int32_t,
+                              int32_t, VecBuffers, LzFused);
 template <int G>
-static void (*lz_fused_kernel_for(int T))(VecBuffers, LzFused) {
+static LzFusedKernel lz_fused_kernel_for(int T) {
     switch (T) {
     case 1: return vec_lz_fused_kernel<1, G>;
     case 2: return vec_lz_fused_kernel<2, G>;
@@ -1426,9 +1443,11 @@ static void (*lz_fused_kernel_for(int T))(VecBuffers, LzFused) {
 hipError_t vec_launch_lz_fused(const VecBuffers &b, const LzFused &z, hipStream_t s) {
     const int ntiles = b.lmax * b.T * b.T;
     if (b.lmax == 0 || ntiles > VEC_THREADS || (b.lmax + 1) * b.T > 2 * VEC_THREADS) return hipErrorInvalidValue;
-    void (*k)(VecBuffers, LzFused) = b.gauge ? lz_fused_kernel_for<1>(b.T) : lz_fused_kernel_for<0>(b.T);
+    LzFusedKernel k = b.gauge ? lz_fused_kernel_for<1>(b.T) : lz_fused_kernel_for<0>(b.T);
     if (!k) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k, dim3(ntiles), dim3(VEC_THREADS), 0, s, parity_view(b, (z.k + 1) & 1), z);
+    const VecBuffers v = parity_view(b, (z.k + 1) & 1);
+    hipLaunchKernelGGL(k, dim3(ntiles), dim3(VEC_THREADS), 0, s, v.dip, v.side[0].rowp, v.side[0].colp, z.xprev,
+                       z.xprev2, v.lmax, v.n, z.k, v, z);
     return hipGetLastError();
 }
 hipError_t vec_launch_hmul_dot(const VecBuffers &b, const VecLaunch &l, double *dotp, const LzNorm &nz,
