@@ -35,9 +35,10 @@ def sources():
 # Per-file code generation options. The matrix-core kernels keep their
 # accumulators in ordinary VGPRs (VGPR-form MFMA): with AGPR accumulators the
 # register allocator copied all of them out and back on every K chunk.
-FILE_FLAGS = {"mfma_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
-              # the tile kernel's leading scalar arguments (14 dwords) go into
-              # scalar registers before the wave starts
+# Kernel-argument preloading: the leading scalar arguments of the tile,
+# Krylov and small-batch kernels (at most 14 dwords) go into scalar registers
+# before the wave starts.
+FILE_FLAGS = {"mfma_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form", "-mllvm", "-amdgpu-kernarg-preload-count=6"],
               "vec_kernels.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=8"]}
 
 

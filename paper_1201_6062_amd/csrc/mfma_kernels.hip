@@ -528,12 +528,23 @@ struct SkinnyTile {
     static constexpr int SLOTS = NACC * 4;           // doubles of accumulator per lane
 };
 
+// The words the first loads need (both dipole copies, the stage input read,
+// Np, ldu and lmax: 9 dwords) come as leading scalar arguments, which are
+// preloaded into scalar registers before the wave starts (built with
+// -amdgpu-kernarg-preload-count), so the k loop's first loads do not wait for
+// a kernel-argument fetch.
 template <int NG, bool ADJ, int DEPTH, int CHUNK>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void bat_skinny_kernel(BatBuffers b,
-                                                                                                    BatLaunch L) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void bat_skinny_kernel(
+    const double *dp, const double *dTp, const double *U, int32_t Np, int32_t ldu, int32_t lmax, BatBuffers bk,
+    BatLaunch L) {
     static_assert(CHUNK % DEPTH == 0, "a chunk holds whole rounds of the load ring");
     using S = SkinnyTile<NG>;
-    const int Np = b.np, ldu = b.ldu, lmax = b.lmax;
+    BatBuffers b = bk;
+    b.d = const_cast<double *>(dp);
+    b.dT = const_cast<double *>(dTp);
+    b.np = Np;
+    b.ldu = ldu;
+    b.lmax = lmax;
     const int RT = Np / S::TM, CT = ldu / S::TN;
     const int ntiles = (lmax + 1) * RT * CT;
     const int w = blockIdx.x;
@@ -543,8 +554,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int r0 = rt * S::TM, c0 = ct * S::TN;
     const int t = threadIdx.x, lane = t & 63;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform: buffer descriptors stay scalar
-    const int q = lane >> 4, li = lane & 15;
-    const double *U = L.parity ? b.u[1] : b.u[0];
+    const int q = lane >> 4, li = lane & 15;  // U: the stage input read (b.u[L.parity])
 
     // ---- this wave's k range: with both neighbour blocks, waves 0-3 split the
     // row use of D_m and waves 4-7 the transposed use of D_{m-1}; with one,
@@ -910,7 +920,8 @@ static hipError_t bat_launch(const BatBuffers &b, const BatLaunch &l, hipStream_
         const int chunk = maxlen <= 8 ? 8 : maxlen <= 16 ? 16 : maxlen <= 32 ? 32 : 64;
 #define TDSE_SKINNY(NG_, CH_)                                                                      \
     if (b.tn == 32 * NG_ && chunk == CH_) {                                                        \
-        hipLaunchKernelGGL((bat_skinny_kernel<NG_, ADJ, 8, CH_>), g, blk2, 0, s, b, l);          \
+        hipLaunchKernelGGL((bat_skinny_kernel<NG_, ADJ, 8, CH_>), g, blk2, 0, s, b.d, b.dT,      \
+                           l.parity ? b.u[1] : b.u[0], b.np, b.ldu, b.lmax, b, l);            \
         return hipGetLastError();                                                                  \
     }
         TDSE_SKINNY(2, 8) TDSE_SKINNY(2, 16) TDSE_SKINNY(2, 32) TDSE_SKINNY(2, 64)
