@@ -84,6 +84,17 @@ def test_group_members_on_other_tile_counts(monkeypatch):
         assert rel_l2(out_f[q].cpu().numpy(), ref) <= TOL, shapes[q]
 
 
+def test_group_rejects_members_beyond_1024_states_per_block():
+    """A group streams every member at ceil(n / 128) tiles per block
+    dimension, at most 8: n = 1100 is refused, whatever the plan's own count."""
+    from paper_1201_6062_amd.api import Group
+    from paper_1201_6062_amd._capi import TDSE_E_UNSUPPORTED, TdseError
+    h = wl.hamiltonian(1, 1100, 3)
+    with pytest.raises(TdseError, match="n <= 1024") as err:
+        Group([plan_of(wl.hamiltonian(1, 60, 2)), plan_of(h)])
+    assert err.value.status == TDSE_E_UNSUPPORTED
+
+
 def test_group_rejects_a_plan_given_twice():
     from paper_1201_6062_amd.api import Group
     h = wl.hamiltonian(2, 70, 1)
