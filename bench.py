@@ -115,7 +115,7 @@ def host_cpu():
         nproc = len(os.sched_getaffinity(0))
     except (AttributeError, OSError):
         pass
-    # the machine's CPU share: OMP_NUM_THREADS is set to it there
+    # the job's CPU share: OMP_NUM_THREADS is set to it where the job runs
     share = int(os.environ.get("OMP_NUM_THREADS", nproc) or nproc)
     return model, nproc, max(1, min(nproc, share))
 
