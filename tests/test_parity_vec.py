@@ -164,6 +164,26 @@ def test_split_at_scale(torch_dev):
     assert rel_l2(got, oracle.taylor(h.energies, h.dipole, 6, 0.01, ft, c0)) <= TOL
 
 
+@pytest.mark.parametrize("T", [5, 6, 7, 9])
+def test_split_uneven_patches_both_directions(torch_dev, T, monkeypatch):
+    """Forced tile counts on the split path, so a block's patches are uneven
+    (T = 5: 3 and 2 tiles each way, ..., T = 9: 3 patches of 3) and carry a
+    ragged last tile (N = 300); odd launches visit each patch's tiles from the
+    last one back. RK4 (4 launches per step) and Taylor-3 (3: the direction
+    alternates between steps) vs the live oracle."""
+    monkeypatch.setenv("TDSE_TILE", f"T={T}")
+    monkeypatch.setenv("TDSE_SPLIT", "1")
+    h = wl.hamiltonian(3, 300, 40 + T)
+    plan = make_plan(h)
+    c0 = wl.random_state(np.random.default_rng(T), h.nstates)
+    f = wl.rk4_samples(wl.Pulse(0.08, 0.6, 2.0), 0.01, 7)[None]
+    got = plan.propagate(f, c0, 0.01, "rk4").cpu().numpy()
+    assert rel_l2(got, oracle.rk4(h.energies, h.dipole, 0.01, f, c0, n=300)) <= TOL
+    ft = wl.taylor_samples(wl.Pulse(0.08, 0.6, 2.0), 0.01, 5)[None]
+    got = plan.propagate(ft, c0, 0.01, "taylor", order=3).cpu().numpy()
+    assert rel_l2(got, oracle.taylor(h.energies, h.dipole, 3, 0.01, ft, c0, n=300)) <= TOL
+
+
 @pytest.mark.parametrize("name,method,order", [("single_large_rk4", "rk4", 0),
                                                ("single_large_taylor8", "taylor", 8)])
 def test_single_large_full_length(torch_dev, name, method, order):
